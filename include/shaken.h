@@ -1,0 +1,269 @@
+/*
+ * libshaken — C ABI of the MI355X (gfx950) shaken-dynamics library.
+ *
+ * The shaken dynamics (D'Autilia, Andrianaivo and Troiani, "Parallel
+ * simulation of two-dimensional Ising models using Probabilistic Cellular
+ * Automata", arXiv:1908.07341, section 2) is a probabilistic cellular
+ * automaton on a pair of L x L tori (sigma, tau).  One step is two half-steps:
+ *   A: every tau_x is drawn independently from the field
+ *      J (sigma_down + sigma_left) + q sigma_x                (eq. (15))
+ *   B: every sigma'_x is drawn independently from the field
+ *      J (tau_up + tau_right) + q tau_x                        (eq. (16))
+ * with P(new spin = +1) = e^h / (2 cosh h).
+ *
+ * Conventions shared by every entry point:
+ *   - site x = (i, j), i = column (east), j = row (north), linear index
+ *     s = j*L + i; up = (i, j+1), right = (i+1, j), down = (i, j-1),
+ *     left = (i-1, j), all mod L (eq. (4));
+ *   - layouts: SD_I8 = one int8 per site, +1 -> 0x01, -1 -> 0xFF;
+ *     SD_P64 / SD_P32 = one bit per site (1 = +1), bit s of the lattice is
+ *     bit s%64 of 64-bit word s/64 (the same bytes for both; P64 needs
+ *     L % 64 == 0 and 8-byte alignment, P32 needs L % 32 == 0 and 4-byte
+ *     alignment);
+ *   - randomness: the counter-based stream keyed by (seed, stream, half-step
+ *     index t, site s): step n of a chain uses t = 2n (A) and t = 2n+1 (B); the
+ *     result is a pure function of the arguments, so run(k1) followed by
+ *     run(step0 + k1, k2) equals run(k1 + k2);
+ *   - pointers named "device" must be device memory (hipMalloc or torch CUDA
+ *     tensors); the library never frees, keeps or reallocates caller memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream); work is
+ *     enqueued asynchronously on it, except where a function says otherwise;
+ *   - every function validates its arguments before enqueuing anything and
+ *     returns SD_EINVAL (or SD_EUNSUPPORTED) without side effects on bad
+ *     arguments; SD_EHIP reports a HIP runtime error (asynchronous errors of
+ *     earlier work may surface here); sd_last_error() gives a message for the
+ *     last non-OK status of the calling thread.  Limits: 2 <= L <= 65535;
+ *     step indices below 2^29.
+ */
+#ifndef SHAKEN_H
+#define SHAKEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SD_API __attribute__((visibility("default")))
+#else
+#define SD_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SD_OK = 0,
+    SD_EINVAL = -1,
+    SD_EUNSUPPORTED = -2,
+    SD_EHIP = -3,
+    SD_ENOSPACE = -4
+} sd_status;
+
+typedef enum { SD_I8 = 0, SD_P32 = 1, SD_P64 = 2 } sd_layout;
+
+typedef enum { SD_INIT_UP = 0, SD_INIT_DOWN = 1, SD_INIT_RANDOM = 2 } sd_init_kind;
+
+/* Flags of sd_half_step / sd_run. */
+#define SD_FLAG_COMPLEMENT_RNG 1u /* replace every uniform r by 2^32-1-r (global spin-flip check) */
+#define SD_FLAG_GLOBAL_KERNELS 2u /* sd_run: always use one grid-wide launch per half-step, never the
+                                     single-workgroup LDS-resident kernel used for small lattices */
+
+#define SD_ABI_VERSION 1
+
+SD_API int32_t sd_abi_version(void);
+
+/* Message of the last non-OK status returned to the calling thread. */
+SD_API const char* sd_last_error(void);
+
+/* Bytes of one lattice, or 0 if (L, layout) is not supported. */
+SD_API size_t sd_lattice_bytes(int32_t L, int32_t layout);
+
+/*
+ * Heat-bath thresholds of Algorithm 3's draw "+1 if rand() < e^h/(2cosh h)".
+ * out_host[idx], idx = 2k + [c = +1] (k = number of +1 among the two
+ * J-neighbours, c = partner spin), for h = J(2k-2) + q(2c-1):
+ *   U = max(1, round-half-even(2^32 / (1 + exp(2|h|)))),
+ *   T = 2^32 - U (h > 0), U (h < 0), 2^31 (h = 0);
+ * a new spin is +1 iff its 32-bit uniform is < T.  Host memory, synchronous.
+ * EINVAL: non-finite J or q, null out_host.
+ */
+SD_API sd_status sd_threshold_table(double J, double q, uint32_t out_host[6]);
+
+/*
+ * Fill a lattice (device, sd_lattice_bytes(L, layout) bytes): all +1, all -1,
+ * or i.i.d. +1 with probability p_up (RANDOM: site s is +1 iff its uniform at
+ * t = 0 of the initialisation stream is < round-half-even(p_up * 2^32)).
+ * The paper's runs start from all -1 (section 3.1).
+ * EINVAL: bad L/layout/kind, p_up outside [0, 1] for RANDOM, null lattice.
+ */
+SD_API sd_status sd_init(void* lattice, int32_t L, int32_t layout, int32_t kind, double p_up, uint64_t seed,
+                  uint32_t stream, void* hip_stream);
+
+/*
+ * One half-step: which = 0 draws tau (dst) from sigma (src) with the
+ * down/left field (eq. (15)); which = 1 draws sigma' (dst) from tau (src) with
+ * the up/right field (eq. (16)).  t is the half-step index (< 2^30).  src and
+ * dst are device lattices of the same layout and must not overlap.
+ */
+SD_API sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, int32_t which, double J, double q,
+                       uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags, void* hip_stream);
+
+/*
+ * k_steps full steps of one chain, steps step0 .. step0+k_steps-1, in place:
+ * (lattices of at most 65536 sites with L % 64 == 0 run in one workgroup with
+ * both lattices held in LDS, one launch for all steps; larger ones use two
+ * grid-wide launches per step; the result is the same bit for bit)
+ * sigma (device) is updated, tau (device, same size) receives the last
+ * half-step-A lattice (its input content is ignored).  If obs (device) is not
+ * NULL it receives, after every obs_every-th step, the int64 triple
+ * (M, A, B) = (sum sigma, sum sigma_x (tau_up + tau_right), sum sigma_x tau_x)
+ * of the pair (sigma_n, tau_n) — the new sigma and the tau it was drawn from —
+ * so that m = M / L^2 and H(sigma, tau) = -(J A + q B) (section 3.1, eq. (5)):
+ * obs[3 * r + {0, 1, 2}] for record r = 0 .. k_steps/obs_every - 1.
+ * EINVAL: bad sizes, obs without obs_every, step0 + k_steps >= 2^29.
+ */
+SD_API sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
+                 uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
+                 uint32_t flags, void* hip_stream);
+
+/* (M, A, B) of an arbitrary pair of device lattices into out3 (device, 3 int64). */
+SD_API sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,
+                     void* hip_stream);
+
+/*
+ * Row-wise correlation sums D(r) = sum_x sigma_(i,j) sigma_(i+r mod L, j),
+ * r = 0 .. rmax (0 <= rmax < L), into out (device, rmax+1 int64).  The
+ * normalised C(r) = D(r) / L^2 and the connected form are left to the caller
+ * (the paper's Table 1 reports diagonal correlations of this kind).
+ */
+SD_API sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax, int64_t* out,
+                      void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Trajectories and their log-likelihood (differentiation with respect to     */
+/* (J, q)).                                                                   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Record a trajectory: traj (device) receives the 2*k_steps + 1 lattices
+ * X_0 = sigma0, X_1 = tau_1, X_2 = sigma_1, ..., X_{2k} = sigma_k of the chain
+ * started from sigma0 at step step0, back to back, each sd_lattice_bytes(L,
+ * layout) bytes (layout SD_P64 or SD_P32).  sigma0 may be traj itself (then it
+ * is not copied) but must not otherwise overlap it.  The lattices are
+ * bit-identical to those of sd_run.
+ */
+SD_API sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_t layout, double J, double q,
+                               uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, void* hip_stream);
+
+/*
+ * Sufficient statistics of the log-likelihood of n_traj packed (SD_P64)
+ * trajectories of n_lat lattices each (traj[a][m][L][L/64], device, as written
+ * by sd_trajectory): counts12[2*idx + [s = +1]] (device, 12 int64) counts the
+ * sites drawn to s with field class idx = 2k + [c = +1] over every transition
+ * X_m -> X_{m+1} (half-step A for even m, B for odd m) of every trajectory.
+ * By the product form of eqs. (15)-(16) the log-likelihood of the trajectories
+ * is  LL(J, q) = sum over the counts of n * (h s - log 2cosh h),
+ * h = J(2k-2) + q(2c-1).  L must be a multiple of 64.
+ */
+SD_API sd_status sd_loglik_counts(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* counts12,
+                                  void* hip_stream);
+
+/*
+ * ll[0] (device float) = LL(J, q) from the counts, Jq (device) = {J, q} in
+ * FP32.  Evaluated with binary32 operations only (values carried as pairs of
+ * floats), rounded to FP32 at the end.
+ */
+SD_API sd_status sd_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, void* hip_stream);
+
+/*
+ * grad[0..1] (device floats) = g_out[0] * (dLL/dJ, dLL/dq), with
+ * dLL/dJ = sum n (2k-2)(s - tanh h), dLL/dq = sum n (2c-1)(s - tanh h);
+ * g_out (device float) may be NULL for 1.  Same arithmetic as sd_loglik_fwd.
+ */
+SD_API sd_status sd_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
+                               void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Batched scan: many independent chains in one persistent launch.            */
+/* ------------------------------------------------------------------------- */
+
+/* One chain of a batch: its couplings, lattice size (a multiple of 64) and
+ * stream id (the chain's randomness is exactly that of sd_run with the same
+ * seed and stream). */
+typedef struct {
+    double J;
+    double q;
+    int32_t L;
+    uint32_t stream;
+} sd_chain_desc;
+
+typedef struct sd_batch_plan sd_batch_plan;
+
+/*
+ * Plan a batch of n_chains chains (the paper's (q, J) scan of section 3.1 runs
+ * one chain per parameter pair).  Host-side setup, synchronous: computes every
+ * chain's threshold table, lays out one lattice buffer holding sigma and tau of
+ * every chain (sd_batch_lattice_bytes, offsets from sd_batch_chain_offset) and a
+ * trace buffer of sd_batch_trace_len int64 = n_chains x (k_steps / obs_every)
+ * records x (M, A, B), groups the chains by lattice size (largest first) and
+ * picks each group's workgroup size: measured and cached in the JSON file
+ * tune_cache_path if that is not NULL (measuring allocates scratch device
+ * memory for the duration of the call), 256 otherwise.  layout is SD_P64 or
+ * SD_I8.  The plan owns small device tables, side streams and a hipGraph; free
+ * it with sd_batch_plan_destroy.  EUNSUPPORTED: a chain whose two lattices do
+ * not fit in one workgroup's LDS.
+ */
+SD_API sd_status sd_batch_plan_create(sd_batch_plan** plan, const sd_chain_desc* chains_host, int32_t n_chains,
+                                      int32_t layout, uint64_t seed, uint32_t k_steps, uint32_t obs_every,
+                                      uint32_t flags, const char* tune_cache_path);
+
+/* Size in bytes of the lattice buffer of a plan (0 for NULL). */
+SD_API size_t sd_batch_lattice_bytes(const sd_batch_plan* plan);
+
+/* Number of int64 in the trace buffer of a plan (0 for NULL). */
+SD_API size_t sd_batch_trace_len(const sd_batch_plan* plan);
+
+/* Byte offset of chain's sigma (which = 0) or tau (which = 1) in the lattice
+ * buffer, or -1 for a bad argument. */
+SD_API int64_t sd_batch_chain_offset(const sd_batch_plan* plan, int32_t chain, int32_t which);
+
+/* Launch shape chosen for size group `bucket` (0 = largest L); outputs may be NULL. */
+SD_API sd_status sd_batch_launch_shape(const sd_batch_plan* plan, int32_t bucket, int32_t* L, int32_t* n_chains,
+                                       int32_t* threads, int32_t* blocks);
+
+/* Initialise every chain's sigma as sd_init would with the chain's own stream. */
+SD_API sd_status sd_batch_init(sd_batch_plan* plan, void* lattices, int32_t kind, double p_up, void* hip_stream);
+
+/*
+ * Run every chain for the plan's k_steps steps from step index step0, in
+ * place, as one graph launch: a kernel zeroes the work-queue counters, then one
+ * persistent kernel per size group (on forked streams) pops chains from its
+ * queue.  Chain c ends bit-identical to sd_run on the same sigma with the same
+ * seed, stream, step0 and k_steps, and its trace rows equal sd_run's obs rows.
+ * lattices (device, 16-byte aligned) and traces (device, or NULL when the plan
+ * records nothing) follow the plan's layout.  The graph is captured on the
+ * first call and reused while (lattices, traces, step0, stream) stay the same.
+ */
+SD_API sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0,
+                              void* hip_stream);
+
+/* The same work as sd_batch_run, enqueued as plain kernel launches (no graph). */
+SD_API sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0,
+                                     void* hip_stream);
+
+/* Free a plan (NULL is ignored).  Synchronises with nothing; the caller must
+ * not destroy a plan whose graph is still executing. */
+SD_API void sd_batch_plan_destroy(sd_batch_plan* plan);
+
+/*
+ * Diagnostics.  sd_debug_fastdiv returns n / d (d >= 1) computed with the
+ * multiply-shift division the kernels use for row and column indices; 0 for
+ * d == 0.  Host only, synchronous.
+ */
+SD_API uint32_t sd_debug_fastdiv(uint32_t n, uint32_t d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHAKEN_H */

@@ -147,6 +147,15 @@ def row_thresholds(src: np.ndarray, J: float, q: float, which: int) -> np.ndarra
     return out
 
 
+def row_thresholds_of(src: np.ndarray, J: float, q: float, which: int, j: int) -> np.ndarray:
+    """Thresholds of the sites of row j only (src is the whole L x L lattice)."""
+    src = _lat(src)
+    L = src.shape[0]
+    row = np.zeros(L, dtype=np.uint32)
+    lib().or_row_thresholds(_p(src, ctypes.c_int8), L, float(J), float(q), which, j, _p(row, ctypes.c_uint32))
+    return row
+
+
 def half_step(src: np.ndarray, J: float, q: float, which: int, seed: int, stream: int, t: int) -> np.ndarray:
     src = _lat(src)
     L = src.shape[0]

@@ -1,0 +1,247 @@
+"""ctypes binding of libshaken with the names of include/shaken.h.
+
+Argument marshalling only: tensors become device pointers, the current torch
+stream becomes the hipStream_t, and a non-OK status becomes ShakenError.  All
+work runs in the library's HIP kernels; there is no fallback: if libshaken.so
+has not been built, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshaken.so")
+
+SD_OK, SD_EINVAL, SD_EUNSUPPORTED, SD_EHIP, SD_ENOSPACE = 0, -1, -2, -3, -4
+SD_I8, SD_P32, SD_P64 = 0, 1, 2
+SD_INIT_UP, SD_INIT_DOWN, SD_INIT_RANDOM = 0, 1, 2
+SD_FLAG_COMPLEMENT_RNG = 1
+SD_FLAG_GLOBAL_KERNELS = 2
+
+
+class sd_chain_desc(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_double), ("q", ctypes.c_double), ("L", ctypes.c_int32), ("stream", ctypes.c_uint32)]
+
+# Every function the header declares, with its ctypes signature.
+_VP, _I32, _U32, _U64, _F64, _F32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                      ctypes.c_double, ctypes.c_float)
+SIGNATURES = {
+    "sd_abi_version": (_I32, []),
+    "sd_last_error": (ctypes.c_char_p, []),
+    "sd_lattice_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "sd_threshold_table": (_I32, [_F64, _F64, ctypes.POINTER(_U32)]),
+    "sd_init": (_I32, [_VP, _I32, _I32, _I32, _F64, _U64, _U32, _VP]),
+    "sd_half_step": (_I32, [_VP, _VP, _I32, _I32, _I32, _F64, _F64, _U64, _U32, _U32, _U32, _VP]),
+    "sd_run": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
+    "sd_observe": (_I32, [_VP, _VP, _I32, _I32, _VP, _VP]),
+    "sd_corr_row": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_batch_plan_create": (_I32, [ctypes.POINTER(_VP), ctypes.POINTER(sd_chain_desc), _I32, _I32, _U64, _U32,
+                                     _U32, _U32, ctypes.c_char_p]),
+    "sd_batch_lattice_bytes": (ctypes.c_size_t, [_VP]),
+    "sd_batch_trace_len": (ctypes.c_size_t, [_VP]),
+    "sd_batch_chain_offset": (ctypes.c_int64, [_VP, _I32, _I32]),
+    "sd_batch_launch_shape": (_I32, [_VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                      ctypes.POINTER(_I32)]),
+    "sd_batch_init": (_I32, [_VP, _VP, _I32, _F64, _VP]),
+    "sd_batch_run": (_I32, [_VP, _VP, _VP, _U64, _VP]),
+    "sd_batch_run_direct": (_I32, [_VP, _VP, _VP, _U64, _VP]),
+    "sd_batch_plan_destroy": (None, [_VP]),
+    "sd_trajectory": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP]),
+    "sd_loglik_counts": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
+    "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "sd_debug_fastdiv": (_U32, [_U32, _U32]),
+}
+
+
+class ShakenError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libshaken status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(or python paper_1908_07341_amd/build.py)")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != SD_OK:
+        raise ShakenError(status, lib().sd_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    if not t.is_cuda:
+        raise ValueError("libshaken works on device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libshaken needs contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(hip_stream):
+    if hip_stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(hip_stream, torch.cuda.Stream):
+        return ctypes.c_void_p(hip_stream.cuda_stream)
+    return ctypes.c_void_p(hip_stream)
+
+
+def sd_abi_version() -> int:
+    return int(lib().sd_abi_version())
+
+
+def sd_lattice_bytes(L: int, layout: int) -> int:
+    return int(lib().sd_lattice_bytes(L, layout))
+
+
+def sd_threshold_table(J: float, q: float) -> list:
+    out = (ctypes.c_uint32 * 6)()
+    _check(lib().sd_threshold_table(float(J), float(q), out))
+    return [int(x) for x in out]
+
+
+def sd_init(lattice, L, layout, kind, p_up=0.5, seed=1, stream=0, hip_stream=None) -> None:
+    _check(lib().sd_init(_ptr(lattice), L, layout, kind, float(p_up), seed, stream, _stream(hip_stream)))
+
+
+def sd_half_step(src, dst, L, layout, which, J, q, seed, stream, t, flags=0, hip_stream=None) -> None:
+    _check(lib().sd_half_step(_ptr(src), _ptr(dst), L, layout, which, float(J), float(q), seed, stream, t, flags,
+                              _stream(hip_stream)))
+
+
+def sd_run(sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs=None, obs_every=0, flags=0,
+           hip_stream=None) -> None:
+    _check(lib().sd_run(_ptr(sigma), _ptr(tau), L, layout, float(J), float(q), seed, stream, step0, k_steps,
+                        _ptr(obs), obs_every, flags, _stream(hip_stream)))
+
+
+def sd_observe(sigma, tau, L, layout, out3, hip_stream=None) -> None:
+    _check(lib().sd_observe(_ptr(sigma), _ptr(tau), L, layout, _ptr(out3), _stream(hip_stream)))
+
+
+def sd_corr_row(sigma, L, layout, rmax, out, hip_stream=None) -> None:
+    _check(lib().sd_corr_row(_ptr(sigma), L, layout, rmax, _ptr(out), _stream(hip_stream)))
+
+
+def sd_trajectory(sigma0, traj, L, layout, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:
+    _check(lib().sd_trajectory(_ptr(sigma0), _ptr(traj), L, layout, float(J), float(q), seed, stream, step0,
+                               k_steps, _stream(hip_stream)))
+
+
+def sd_loglik_counts(traj, n_traj, n_lat, L, counts12, hip_stream=None) -> None:
+    _check(lib().sd_loglik_counts(_ptr(traj), n_traj, n_lat, L, _ptr(counts12), _stream(hip_stream)))
+
+
+def sd_loglik_fwd(counts12, Jq, ll, hip_stream=None) -> None:
+    _check(lib().sd_loglik_fwd(_ptr(counts12), _ptr(Jq), _ptr(ll), _stream(hip_stream)))
+
+
+def sd_loglik_bwd(counts12, Jq, g_out, grad, hip_stream=None) -> None:
+    _check(lib().sd_loglik_bwd(_ptr(counts12), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
+
+
+class sd_batch_plan:
+    """Owner of a libshaken batch plan handle (sd_batch_plan_destroy on close)."""
+
+    def __init__(self, handle: int):
+        self.handle = ctypes.c_void_p(handle)
+
+    def close(self):
+        if self.handle:
+            lib().sd_batch_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sd_batch_plan_create(J, q, L, stream, layout=SD_P64, seed=1, k_steps=1, obs_every=1, flags=0,
+                         tune_cache_path=None) -> sd_batch_plan:
+    n = len(L)
+    arr = (sd_chain_desc * n)()
+    for i in range(n):
+        arr[i].J, arr[i].q, arr[i].L, arr[i].stream = float(J[i]), float(q[i]), int(L[i]), int(stream[i])
+    h = ctypes.c_void_p(0)
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().sd_batch_plan_create(ctypes.byref(h), arr, n, layout, seed, k_steps, obs_every, flags, path))
+    return sd_batch_plan(h.value)
+
+
+def sd_batch_lattice_bytes(plan: sd_batch_plan) -> int:
+    return int(lib().sd_batch_lattice_bytes(plan.handle))
+
+
+def sd_batch_trace_len(plan: sd_batch_plan) -> int:
+    return int(lib().sd_batch_trace_len(plan.handle))
+
+
+def sd_batch_chain_offset(plan: sd_batch_plan, chain: int, which: int) -> int:
+    return int(lib().sd_batch_chain_offset(plan.handle, chain, which))
+
+
+def sd_batch_launch_shape(plan: sd_batch_plan, bucket: int):
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().sd_batch_launch_shape(plan.handle, bucket, *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
+
+
+def sd_batch_init(plan: sd_batch_plan, lattices, kind, p_up=0.5, hip_stream=None) -> None:
+    _check(lib().sd_batch_init(plan.handle, _ptr(lattices), kind, float(p_up), _stream(hip_stream)))
+
+
+def sd_batch_run(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None) -> None:
+    _check(lib().sd_batch_run(plan.handle, _ptr(lattices), _ptr(traces), step0, _stream(hip_stream)))
+
+
+def sd_batch_run_direct(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None) -> None:
+    _check(lib().sd_batch_run_direct(plan.handle, _ptr(lattices), _ptr(traces), step0, _stream(hip_stream)))
+
+
+def sd_batch_plan_destroy(plan: sd_batch_plan) -> None:
+    plan.close()
+
+
+def sd_debug_fastdiv(n: int, d: int) -> int:
+    return int(lib().sd_debug_fastdiv(n, d))
+
+
+# ---------------------------------------------------------------------------
+# Device memory helpers (plumbing: shapes and dtypes of lattice tensors).
+# ---------------------------------------------------------------------------
+def new_lattice(L: int, layout: int, device="cuda") -> torch.Tensor:
+    """An uninitialised lattice tensor: int8 [L, L] for SD_I8, int64 [L, L/64]
+    for SD_P64, int32 [L, L/32] for SD_P32 (the packed bytes are the same)."""
+    nbytes = sd_lattice_bytes(L, layout)
+    if nbytes == 0:
+        raise ValueError(f"unsupported lattice L={L} layout={layout}")
+    if layout == SD_I8:
+        return torch.empty((L, L), dtype=torch.int8, device=device)
+    if layout == SD_P64:
+        return torch.empty((L, L // 64), dtype=torch.int64, device=device)
+    return torch.empty((L, L // 32), dtype=torch.int32, device=device)

@@ -1,0 +1,302 @@
+// Host side of the C ABI: argument validation, the FP64 threshold table,
+// launch geometry and the step loop.  Declarations and the contract of every
+// entry point are in include/shaken.h.
+#include "shaken.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "sd_batch.hpp"
+#include "sd_host.hpp"
+#include "sd_kernels.hpp"
+
+namespace sd {
+
+thread_local std::string g_last_error;
+
+sd_status fail(sd_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+sd_status hip_fail(hipError_t e, const char* what) {
+    return fail(SD_EHIP, "%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+}
+
+bool layout_supported(int32_t L, int32_t layout) {
+    if (L < 2 || L > 65535)
+        return false;
+    switch (layout) {
+        case SD_I8:
+            return true;
+        case SD_P32:
+            return L % 32 == 0;
+        case SD_P64:
+            return L % 64 == 0;
+        default:
+            return false;
+    }
+}
+
+size_t lattice_bytes(int32_t L, int32_t layout) {
+    if (!layout_supported(L, layout))
+        return 0;
+    const size_t n = (size_t)L * (size_t)L;
+    return layout == SD_I8 ? n : n / 8;
+}
+
+int kernel_layout(int32_t L, int32_t layout, const void* p) {
+    if (layout == SD_P64)
+        return kLayP64;
+    if (layout == SD_P32)
+        return kLayP32;
+    const bool aligned = (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+    return (L % 64 == 0 && aligned) ? kLayI8Row : kLayI8Any;
+}
+
+Geom make_geom(int32_t L, int klay) {
+    Geom G;
+    G.L = (uint32_t)L;
+    G.n_sites = (uint32_t)L * (uint32_t)L;
+    G.n_groups = (uint32_t)(((uint64_t)G.n_sites + 63u) / 64u);
+    switch (klay) {
+        case kLayP64:
+        case kLayI8Row:
+            G.words_row = (uint32_t)L / 64u;
+            break;
+        case kLayP32:
+            G.words_row = (uint32_t)L / 32u;
+            break;
+        default:
+            G.words_row = 1;
+            break;
+    }
+    G.div_row = make_fastdiv(G.words_row);
+    G.div_L = make_fastdiv((uint32_t)L);
+    return G;
+}
+
+uint32_t threshold(double h) {
+    if (h == 0.0)
+        return 0x80000000u;
+    const double a = std::fabs(h);
+    const double u = 4294967296.0 / (1.0 + std::exp(2.0 * a));
+    const double r = std::nearbyint(u);
+    const uint64_t U = (r < 1.0) ? 1u : (uint64_t)r;
+    return h > 0.0 ? (uint32_t)(4294967296ull - U) : (uint32_t)U;
+}
+
+void threshold_table(double J, double q, uint32_t T[6]) {
+    for (int k = 0; k <= 2; ++k)
+        for (int cp = 0; cp <= 1; ++cp)
+            T[2 * k + cp] = threshold(J * (double)(2 * k - 2) + q * (double)(2 * cp - 1));
+}
+
+DrawParams dynamics_params(double J, double q, uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags) {
+    DrawParams dp;
+    threshold_table(J, q, dp.T);
+    dp.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    dp.key1 = (uint32_t)(seed >> 32);
+    dp.stream = stream;
+    dp.t = t;
+    dp.tag2 = 2u * kTagDynamics;
+    dp.rng_xor = (flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
+    return dp;
+}
+
+bool overlap(const void* a, const void* b, size_t n) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + n && y < x + n;
+}
+
+sd_status check_lattice(const void* p, int32_t L, int32_t layout, const char* name) {
+    if (!layout_supported(L, layout))
+        return fail(SD_EINVAL, "%s: unsupported (L=%d, layout=%d)", name, L, layout);
+    if (!p)
+        return fail(SD_EINVAL, "%s: null lattice pointer", name);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    if ((layout == SD_P64 && (a & 7u)) || (layout == SD_P32 && (a & 3u)))
+        return fail(SD_EINVAL, "%s: lattice pointer not aligned to its word size", name);
+    return SD_OK;
+}
+
+}  // namespace sd
+
+using namespace sd;
+
+extern "C" {
+
+int32_t sd_abi_version(void) { return SD_ABI_VERSION; }
+
+const char* sd_last_error(void) { return g_last_error.c_str(); }
+
+size_t sd_lattice_bytes(int32_t L, int32_t layout) { return lattice_bytes(L, layout); }
+
+sd_status sd_threshold_table(double J, double q, uint32_t out_host[6]) {
+    if (!out_host)
+        return fail(SD_EINVAL, "sd_threshold_table: null output");
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "sd_threshold_table: J and q must be finite");
+    threshold_table(J, q, out_host);
+    return SD_OK;
+}
+
+sd_status sd_init(void* lattice, int32_t L, int32_t layout, int32_t kind, double p_up, uint64_t seed,
+                  uint32_t stream, void* hip_stream) {
+    sd_status s = check_lattice(lattice, L, layout, "sd_init");
+    if (s != SD_OK)
+        return s;
+    if (kind != SD_INIT_UP && kind != SD_INIT_DOWN && kind != SD_INIT_RANDOM)
+        return fail(SD_EINVAL, "sd_init: unknown kind %d", kind);
+    if (kind == SD_INIT_RANDOM && !(p_up >= 0.0 && p_up <= 1.0))
+        return fail(SD_EINVAL, "sd_init: p_up must lie in [0, 1]");
+    const int klay = kernel_layout(L, layout, lattice);
+    const Geom G = make_geom(L, klay);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if (kind == SD_INIT_RANDOM) {
+        const double Pd = std::nearbyint(p_up * 4294967296.0);
+        if (Pd >= 4294967296.0) {
+            e = launch_init(klay, lattice, G, 1, false, DrawParams{}, st);
+        } else {
+            DrawParams dp;
+            for (int i = 0; i < 6; ++i)
+                dp.T[i] = (uint32_t)Pd;
+            dp.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+            dp.key1 = (uint32_t)(seed >> 32);
+            dp.stream = stream;
+            dp.t = 0;
+            dp.tag2 = 2u * kTagInit;
+            dp.rng_xor = 0;
+            e = launch_init(klay, lattice, G, 0, true, dp, st);
+        }
+    } else {
+        e = launch_init(klay, lattice, G, kind == SD_INIT_UP ? 1 : 0, false, DrawParams{}, st);
+    }
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_init");
+}
+
+sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, int32_t which, double J, double q,
+                       uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags, void* hip_stream) {
+    sd_status s = check_lattice(src, L, layout, "sd_half_step(src)");
+    if (s == SD_OK)
+        s = check_lattice(dst, L, layout, "sd_half_step(dst)");
+    if (s != SD_OK)
+        return s;
+    if (which != 0 && which != 1)
+        return fail(SD_EINVAL, "sd_half_step: which must be 0 (A) or 1 (B)");
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "sd_half_step: J and q must be finite");
+    if (t >= (1u << 30))
+        return fail(SD_EINVAL, "sd_half_step: half-step index must be < 2^30");
+    if (flags & ~SD_FLAG_COMPLEMENT_RNG)
+        return fail(SD_EINVAL, "sd_half_step: unknown flags");
+    if (overlap(src, dst, lattice_bytes(L, layout)))
+        return fail(SD_EINVAL, "sd_half_step: src and dst overlap");
+    const int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, src) == kLayI8Row &&
+                                           kernel_layout(L, layout, dst) == kLayI8Row)
+                                              ? kLayI8Row
+                                              : kLayI8Any)
+                                       : kernel_layout(L, layout, src);
+    const Geom G = make_geom(L, klay);
+    const DrawParams dp = dynamics_params(J, q, seed, stream, t, flags);
+    hipError_t e = launch_half_step(klay, which, src, dst, G, dp, nullptr, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_half_step");
+}
+
+sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
+                 uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
+                 uint32_t flags, void* hip_stream) {
+    sd_status s = check_lattice(sigma, L, layout, "sd_run(sigma)");
+    if (s == SD_OK)
+        s = check_lattice(tau, L, layout, "sd_run(tau)");
+    if (s != SD_OK)
+        return s;
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "sd_run: J and q must be finite");
+    if (step0 + (uint64_t)k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "sd_run: step indices must stay below 2^29");
+    if (obs && obs_every == 0)
+        return fail(SD_EINVAL, "sd_run: obs given without obs_every");
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GLOBAL_KERNELS))
+        return fail(SD_EINVAL, "sd_run: unknown flags");
+    if (overlap(sigma, tau, lattice_bytes(L, layout)))
+        return fail(SD_EINVAL, "sd_run: sigma and tau overlap");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, sigma) == kLayI8Row &&
+                                           kernel_layout(L, layout, tau) == kLayI8Row)
+                                              ? kLayI8Row
+                                              : kLayI8Any)
+                                       : kernel_layout(L, layout, sigma);
+    const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
+    const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
+    const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0)) &&
+                        n_words <= kSingleLdsMaxWords && !(flags & SD_FLAG_GLOBAL_KERNELS);
+    if (lds_ok) {
+        if (k_steps == 0)
+            return SD_OK;
+        hipError_t e = launch_single_chain_lds(sigma, tau, L, klay == kLayI8Row, J, q, seed, stream, step0, k_steps,
+                                               n_rec ? obs : nullptr, obs_every, flags, 256, st);
+        return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
+    }
+    const Geom G = make_geom(L, klay);
+    hipError_t e = hipSuccess;
+    if (n_rec)
+        e = launch_fill_i64(obs, (size_t)n_rec * 3u, 0, st);
+    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
+        const uint64_t n = step0 + m;
+        DrawParams dp = dynamics_params(J, q, seed, stream, (uint32_t)(2 * n), flags & SD_FLAG_COMPLEMENT_RNG);
+        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st);
+        if (e != hipSuccess)
+            break;
+        dp.t = (uint32_t)(2 * n + 1);
+        int64_t* rec = nullptr;
+        if (n_rec && (m + 1) % obs_every == 0)
+            rec = obs + 3u * (size_t)((m + 1) / obs_every - 1);
+        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st);
+    }
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
+}
+
+sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,
+                     void* hip_stream) {
+    sd_status s = check_lattice(sigma, L, layout, "sd_observe(sigma)");
+    if (s == SD_OK)
+        s = check_lattice(tau, L, layout, "sd_observe(tau)");
+    if (s != SD_OK)
+        return s;
+    if (!out3)
+        return fail(SD_EINVAL, "sd_observe: null output");
+    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    hipError_t e = launch_observe(klay, sigma, tau, make_geom(L, klay), out3, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_observe");
+}
+
+sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax, int64_t* out,
+                      void* hip_stream) {
+    sd_status s = check_lattice(sigma, L, layout, "sd_corr_row");
+    if (s != SD_OK)
+        return s;
+    if (!out)
+        return fail(SD_EINVAL, "sd_corr_row: null output");
+    if (rmax < 0 || rmax >= L)
+        return fail(SD_EINVAL, "sd_corr_row: rmax must satisfy 0 <= rmax < L");
+    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    hipError_t e = launch_corr_row(klay, sigma, make_geom(L, klay), rmax, out, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
+}
+
+uint32_t sd_debug_fastdiv(uint32_t n, uint32_t d) {
+    if (d == 0)
+        return 0;
+    return fdiv_host(n, make_fastdiv(d));
+}
+
+}  // extern "C"

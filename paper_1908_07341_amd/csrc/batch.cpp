@@ -1,0 +1,484 @@
+// Host side of the batched scan: plan creation (threshold tables, lattice and
+// trace layout, buckets by lattice size, launch shapes from the autotuner),
+// hipGraph capture of the persistent launch, and plan teardown.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sd_autotune.hpp"
+#include "sd_batch.hpp"
+#include "sd_host.hpp"
+
+struct sd_batch_plan {
+    int device = 0;
+    int32_t n_chains = 0;
+    int32_t layout = SD_P64;
+    uint64_t seed = 0;
+    uint32_t k_steps = 0, obs_every = 0, n_rec = 0, flags = 0;
+    std::vector<sd::ChainDesc> descs;
+    size_t lattice_total = 0;
+
+    struct Bucket {
+        uint32_t L = 0;
+        uint32_t max_words = 0;
+        uint32_t first = 0, count = 0;   // range in the order array
+        uint32_t threads = 256, blocks = 1;
+    };
+    std::vector<Bucket> buckets;
+    uint32_t tail_cap = 2048;
+
+    sd::ChainDesc* d_descs = nullptr;
+    uint32_t* d_order = nullptr;
+    uint32_t* d_counters = nullptr;
+
+    // cached graph of the last run shape
+    bool have_graph = false;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void* g_lattices = nullptr;
+    int64_t* g_traces = nullptr;
+    uint64_t g_step0 = 0;
+    hipStream_t g_stream = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> events;
+};
+
+namespace sd {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+void release_graph(sd_batch_plan* p) {
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->have_graph = false;
+}
+
+BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t* traces, uint64_t step0) {
+    const sd_batch_plan::Bucket& bk = p->buckets[b];
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.chains = p->d_descs;
+    a.order = p->d_order + bk.first;
+    a.n_chains = bk.count;
+    a.counter = p->d_counters + b;
+    a.lattices = static_cast<uint8_t*>(lattices);
+    a.traces = p->n_rec ? traces : nullptr;
+    a.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.step0 = (uint32_t)step0;
+    a.k_steps = p->k_steps;
+    a.obs_every = p->obs_every ? p->obs_every : 1u;
+    a.rng_xor = (p->flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
+    a.max_words = bk.max_words;
+    a.tail_cap = p->tail_cap;
+    a.int8_io = p->layout == SD_I8 ? 1u : 0u;
+    return a;
+}
+
+hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint64_t step0, hipStream_t st) {
+    hipError_t e = launch_zero_u32(p->d_counters, (uint32_t)p->buckets.size(), st);
+    if (e != hipSuccess)
+        return e;
+    if (p->buckets.size() == 1) {
+        const auto& bk = p->buckets[0];
+        return launch_batch_chains(bucket_args(p, 0, lattices, traces, step0), bk.blocks, bk.threads, st);
+    }
+    // fork: every bucket runs on its own stream after the counters are zeroed
+    e = hipEventRecord(p->events[0], st);
+    for (size_t b = 0; b < p->buckets.size() && e == hipSuccess; ++b) {
+        hipStream_t s = p->side[b];
+        e = hipStreamWaitEvent(s, p->events[0], 0);
+        if (e == hipSuccess) {
+            const auto& bk = p->buckets[b];
+            e = launch_batch_chains(bucket_args(p, b, lattices, traces, step0), bk.blocks, bk.threads, s);
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(p->events[1 + b], s);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(st, p->events[1 + b], 0);
+    }
+    return e;
+}
+
+}  // namespace
+
+// Measured choice of the batched kernel's block size for chains of size L: a
+// sample of this plan's chains of that size runs 16 steps on scratch lattices
+// for every candidate; the fastest is kept in the cache file.
+uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_chains, sd_batch_plan* p) {
+    const uint32_t fallback = 256;
+    if (!cache_path || !*cache_path)
+        return fallback;
+    const std::string key = "batch:" + device_arch() + ":L=" + std::to_string(L) + ":k=" +
+                            std::to_string(p->obs_every ? 1 : 0);
+    const long cached = tune_cache_get(cache_path, key);
+    if (cached > 0)
+        return (uint32_t)cached;
+    int dev = 0, n_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fallback;
+    std::vector<ChainDesc> sample;
+    for (const ChainDesc& d : p->descs)
+        if (d.L == L && sample.size() < std::min<uint32_t>(n_chains, 2u * (uint32_t)n_cu))
+            sample.push_back(d);
+    const uint32_t S = (uint32_t)sample.size();
+    const uint32_t k = 16;
+    const size_t bytes = lattice_bytes((int32_t)L, p->layout);
+    size_t off = 0;
+    for (uint32_t i = 0; i < S; ++i) {
+        sample[i].sig_offset = off;
+        off = align_up(off + bytes);
+        sample[i].tau_offset = off;
+        off = align_up(off + bytes);
+        sample[i].trace_offset = (uint64_t)i * k * 3u;
+    }
+    std::vector<uint32_t> order(S);
+    for (uint32_t i = 0; i < S; ++i)
+        order[i] = i;
+    void* lat = nullptr;
+    int64_t* tr = nullptr;
+    ChainDesc* dd = nullptr;
+    uint32_t* dord = nullptr;
+    uint32_t* cnt = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&lat, off);
+    if (e == hipSuccess) e = hipMalloc(&tr, sizeof(int64_t) * S * k * 3u);
+    if (e == hipSuccess) e = hipMalloc(&dd, sizeof(ChainDesc) * S);
+    if (e == hipSuccess) e = hipMalloc(&dord, sizeof(uint32_t) * S);
+    if (e == hipSuccess) e = hipMalloc(&cnt, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(lat, 0x5A, off);
+    if (e == hipSuccess) e = hipMemcpy(dd, sample.data(), sizeof(ChainDesc) * S, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dord, order.data(), sizeof(uint32_t) * S, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    long best = -1;
+    if (e == hipSuccess) {
+        const size_t lds = batch_lds_bytes(L * (L / 64u), p->tail_cap);
+        auto measure = [&](long threads) -> double {
+            BatchArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.chains = dd;
+            a.order = dord;
+            a.n_chains = S;
+            a.counter = cnt;
+            a.lattices = static_cast<uint8_t*>(lat);
+            a.traces = tr;
+            a.key0 = 1;
+            a.k_steps = k;
+            a.obs_every = 1;
+            a.max_words = L * (L / 64u);
+            a.tail_cap = p->tail_cap;
+            a.int8_io = p->layout == SD_I8 ? 1u : 0u;
+            int per_cu = 0;
+            if (batch_occupancy((uint32_t)threads, lds, &per_cu) != hipSuccess || per_cu < 1)
+                return -1.0;
+            const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(S, (uint32_t)per_cu * (uint32_t)n_cu));
+            float best_ms = -1.0f;
+            for (int rep = 0; rep < 2; ++rep) {
+                if (launch_zero_u32(cnt, 1, nullptr) != hipSuccess) return -1.0;
+                if (hipEventRecord(e0, nullptr) != hipSuccess) return -1.0;
+                if (launch_batch_chains(a, blocks, (uint32_t)threads, nullptr) != hipSuccess) return -1.0;
+                if (hipEventRecord(e1, nullptr) != hipSuccess) return -1.0;
+                if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+                if (rep > 0)
+                    best_ms = ms;
+            }
+            return best_ms / 1e3;
+        };
+        best = tune_pick({128, 256, 512, 1024}, measure);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (lat) (void)hipFree(lat);
+    if (tr) (void)hipFree(tr);
+    if (dd) (void)hipFree(dd);
+    if (dord) (void)hipFree(dord);
+    if (cnt) (void)hipFree(cnt);
+    (void)hipGetLastError();
+    if (best <= 0)
+        return fallback;
+    tune_cache_put(cache_path, key, best);
+    return (uint32_t)best;
+}
+
+// Single-chain LDS-resident run used by sd_run for small lattices.
+hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_io, double J, double q,
+                                   uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,
+                                   uint32_t obs_every, uint32_t flags, uint32_t threads, hipStream_t st) {
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.counter = nullptr;
+    threshold_table(J, q, a.single.T);
+    a.single.L = (uint32_t)L;
+    a.single.stream = stream;
+    a.single.divW = make_fastdiv((uint32_t)L / 64u);
+    a.single_sig = static_cast<uint8_t*>(sigma);
+    a.single_tau = static_cast<uint8_t*>(tau);
+    a.traces = obs;
+    a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(seed >> 32);
+    a.step0 = (uint32_t)step0;
+    a.k_steps = k_steps;
+    a.obs_every = obs_every ? obs_every : 1u;
+    a.rng_xor = (flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
+    a.max_words = (uint32_t)L * ((uint32_t)L / 64u);
+    a.tail_cap = 1024;
+    a.int8_io = int8_io ? 1u : 0u;
+    hipError_t e = batch_kernel_attributes(batch_lds_bytes(a.max_words, a.tail_cap));
+    if (e != hipSuccess)
+        return e;
+    return launch_batch_chains(a, 1, threads, st);
+}
+
+}  // namespace sd
+
+using namespace sd;
+
+extern "C" {
+
+sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* chains, int32_t n_chains, int32_t layout,
+                               uint64_t seed, uint32_t k_steps, uint32_t obs_every, uint32_t flags,
+                               const char* tune_cache_path) {
+    if (!plan_out || !chains || n_chains <= 0)
+        return fail(SD_EINVAL, "sd_batch_plan_create: need an output handle and at least one chain");
+    *plan_out = nullptr;
+    if (layout != SD_P64 && layout != SD_I8)
+        return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: layout must be SD_P64 or SD_I8");
+    if (k_steps >= (1u << 29))
+        return fail(SD_EINVAL, "sd_batch_plan_create: k_steps must be below 2^29");
+    if (flags & ~SD_FLAG_COMPLEMENT_RNG)
+        return fail(SD_EINVAL, "sd_batch_plan_create: unknown flags");
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_batch_plan_create");
+    int max_lds = 0, n_cu = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_batch_plan_create");
+
+    sd_batch_plan* p = new (std::nothrow) sd_batch_plan();
+    if (!p)
+        return fail(SD_ENOSPACE, "sd_batch_plan_create: out of host memory");
+    p->device = device;
+    p->n_chains = n_chains;
+    p->layout = layout;
+    p->seed = seed;
+    p->k_steps = k_steps;
+    p->obs_every = obs_every;
+    p->n_rec = obs_every ? k_steps / obs_every : 0u;
+    p->flags = flags;
+    p->descs.resize((size_t)n_chains);
+
+    std::map<uint32_t, std::vector<uint32_t>, std::greater<uint32_t>> by_L;   // largest L first
+    size_t off = 0;
+    for (int32_t c = 0; c < n_chains; ++c) {
+        const sd_chain_desc& in = chains[c];
+        if (in.L < 64 || in.L > 65535 || in.L % 64 != 0 || !std::isfinite(in.J) || !std::isfinite(in.q)) {
+            delete p;
+            return fail(SD_EINVAL, "sd_batch_plan_create: chain %d needs finite J, q and L a multiple of 64", c);
+        }
+        const size_t words = (size_t)in.L * (in.L / 64);
+        if (batch_lds_bytes((uint32_t)words, p->tail_cap) > (size_t)max_lds) {
+            delete p;
+            return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: chain %d (L=%d) does not fit in %d bytes of LDS", c,
+                        in.L, max_lds);
+        }
+        ChainDesc& d = p->descs[(size_t)c];
+        threshold_table(in.J, in.q, d.T);
+        d.L = (uint32_t)in.L;
+        d.stream = in.stream;
+        d.divW = make_fastdiv((uint32_t)in.L / 64u);
+        const size_t bytes = lattice_bytes(in.L, layout);
+        d.sig_offset = off;
+        off = align_up(off + bytes);
+        d.tau_offset = off;
+        off = align_up(off + bytes);
+        d.trace_offset = (uint64_t)c * p->n_rec * 3u;
+        by_L[(uint32_t)in.L].push_back((uint32_t)c);
+    }
+    p->lattice_total = off;
+
+    std::vector<uint32_t> order;
+    order.reserve((size_t)n_chains);
+    for (auto& kv : by_L) {
+        sd_batch_plan::Bucket bk;
+        bk.L = kv.first;
+        bk.max_words = kv.first * (kv.first / 64u);
+        bk.first = (uint32_t)order.size();
+        bk.count = (uint32_t)kv.second.size();
+        order.insert(order.end(), kv.second.begin(), kv.second.end());
+        p->buckets.push_back(bk);
+    }
+
+    size_t max_words = 0;
+    for (auto& bk : p->buckets)
+        max_words = std::max(max_words, (size_t)bk.max_words);
+    e = batch_kernel_attributes(batch_lds_bytes((uint32_t)max_words, p->tail_cap));
+    if (e == hipSuccess)
+        e = hipMalloc(&p->d_descs, sizeof(ChainDesc) * p->descs.size());
+    if (e == hipSuccess)
+        e = hipMalloc(&p->d_order, sizeof(uint32_t) * order.size());
+    if (e == hipSuccess)
+        e = hipMalloc(&p->d_counters, sizeof(uint32_t) * p->buckets.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_descs, p->descs.data(), sizeof(ChainDesc) * p->descs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_order, order.data(), sizeof(uint32_t) * order.size(), hipMemcpyHostToDevice);
+    for (size_t b = 0; b < p->buckets.size() && e == hipSuccess; ++b) {
+        hipStream_t s = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            p->side.push_back(s);
+    }
+    for (size_t i = 0; i < p->buckets.size() + 1 && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            p->events.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        sd_batch_plan_destroy(p);
+        return hip_fail(e, "sd_batch_plan_create");
+    }
+
+    // launch shape per bucket: cached / tuned block size, grid = resident blocks
+    for (auto& bk : p->buckets) {
+        uint32_t threads = autotune_batch_threads(tune_cache_path, bk.L, bk.count, p);
+        const size_t lds = batch_lds_bytes(bk.max_words, p->tail_cap);
+        int per_cu = 0;
+        e = batch_occupancy(threads, lds, &per_cu);
+        if (e != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        uint64_t blocks = (uint64_t)per_cu * (uint64_t)n_cu;
+        bk.threads = threads;
+        bk.blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, bk.count));
+    }
+    *plan_out = p;
+    return SD_OK;
+}
+
+size_t sd_batch_lattice_bytes(const sd_batch_plan* plan) { return plan ? plan->lattice_total : 0; }
+
+size_t sd_batch_trace_len(const sd_batch_plan* plan) {
+    return plan ? (size_t)plan->n_chains * plan->n_rec * 3u : 0;
+}
+
+int64_t sd_batch_chain_offset(const sd_batch_plan* plan, int32_t chain, int32_t which) {
+    if (!plan || chain < 0 || chain >= plan->n_chains || (which != 0 && which != 1))
+        return -1;
+    const ChainDesc& d = plan->descs[(size_t)chain];
+    return (int64_t)(which == 0 ? d.sig_offset : d.tau_offset);
+}
+
+sd_status sd_batch_launch_shape(const sd_batch_plan* plan, int32_t bucket, int32_t* L, int32_t* n_chains,
+                                int32_t* threads, int32_t* blocks) {
+    if (!plan || bucket < 0 || (size_t)bucket >= plan->buckets.size())
+        return fail(SD_EINVAL, "sd_batch_launch_shape: no such bucket");
+    const auto& bk = plan->buckets[(size_t)bucket];
+    if (L) *L = (int32_t)bk.L;
+    if (n_chains) *n_chains = (int32_t)bk.count;
+    if (threads) *threads = (int32_t)bk.threads;
+    if (blocks) *blocks = (int32_t)bk.blocks;
+    return SD_OK;
+}
+
+sd_status sd_batch_init(sd_batch_plan* plan, void* lattices, int32_t kind, double p_up, void* hip_stream) {
+    if (!plan || !lattices)
+        return fail(SD_EINVAL, "sd_batch_init: null plan or lattices");
+    for (int32_t c = 0; c < plan->n_chains; ++c) {
+        const ChainDesc& d = plan->descs[(size_t)c];
+        sd_status s = sd_init(static_cast<uint8_t*>(lattices) + d.sig_offset, (int32_t)d.L, plan->layout, kind, p_up,
+                              plan->seed, d.stream, hip_stream);
+        if (s != SD_OK)
+            return s;
+    }
+    return SD_OK;
+}
+
+sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0, void* hip_stream) {
+    if (!plan || !lattices)
+        return fail(SD_EINVAL, "sd_batch_run: null plan or lattices");
+    if (plan->n_rec && !traces)
+        return fail(SD_EINVAL, "sd_batch_run: the plan records observables, traces must not be null");
+    if (step0 + plan->k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "sd_batch_run: step indices must stay below 2^29");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(lattices);
+    if (a % 16u)
+        return fail(SD_EINVAL, "sd_batch_run: lattices must be 16-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipSuccess;
+    if (!(plan->have_graph && plan->g_lattices == lattices && plan->g_traces == traces && plan->g_step0 == step0 &&
+          plan->g_stream == st)) {
+        release_graph(plan);
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hip_fail(e, "sd_batch_run: begin capture");
+        hipError_t ee = enqueue_batch(plan, lattices, traces, step0, st);
+        e = hipStreamEndCapture(st, &plan->graph);
+        if (ee != hipSuccess)
+            e = ee;
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            release_graph(plan);
+            return hip_fail(e, "sd_batch_run: graph capture");
+        }
+        plan->have_graph = true;
+        plan->g_lattices = lattices;
+        plan->g_traces = traces;
+        plan->g_step0 = step0;
+        plan->g_stream = st;
+    }
+    e = hipGraphLaunch(plan->exec, st);
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run: graph launch");
+}
+
+sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0,
+                              void* hip_stream) {
+    if (!plan || !lattices)
+        return fail(SD_EINVAL, "sd_batch_run_direct: null plan or lattices");
+    if (plan->n_rec && !traces)
+        return fail(SD_EINVAL, "sd_batch_run_direct: the plan records observables, traces must not be null");
+    if (step0 + plan->k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "sd_batch_run_direct: step indices must stay below 2^29");
+    if (reinterpret_cast<uintptr_t>(lattices) % 16u)
+        return fail(SD_EINVAL, "sd_batch_run_direct: lattices must be 16-byte aligned");
+    hipError_t e = enqueue_batch(plan, lattices, traces, step0, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run_direct");
+}
+
+void sd_batch_plan_destroy(sd_batch_plan* plan) {
+    if (!plan)
+        return;
+    release_graph(plan);
+    for (hipStream_t s : plan->side)
+        (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : plan->events)
+        (void)hipEventDestroy(ev);
+    if (plan->d_descs)
+        (void)hipFree(plan->d_descs);
+    if (plan->d_order)
+        (void)hipFree(plan->d_order);
+    if (plan->d_counters)
+        (void)hipFree(plan->d_counters);
+    delete plan;
+}
+
+}  // extern "C"

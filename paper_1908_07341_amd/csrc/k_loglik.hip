@@ -1,0 +1,261 @@
+// Trajectory log-likelihood of the shaken dynamics and its gradient.
+//
+// By the product form of the half-step transition probabilities (section 2,
+// eqs. (15)-(16)) a trajectory X_0 = sigma_0, X_1 = tau_1, X_2 = sigma_1, ...
+// has log-probability  sum over transitions and sites of h_x s_x - log 2cosh h_x,
+// with s_x the drawn spin and h_x its field (down/left neighbours of X_m for
+// even m, up/right for odd m).  h takes six values, so the 12 counts
+//   n[2*idx + [s = +1]],  idx = 2k + [c = +1]
+// are sufficient statistics: LL = sum n (h s - log 2cosh h),
+// dLL/dJ = sum n (2k-2)(s - tanh h),  dLL/dq = sum n c (s - tanh h).
+//
+// k_loglik_counts streams the packed trajectories once (HBM-bound) and
+// accumulates the counts exactly in 64-bit integers.  The forward and backward
+// kernels combine them with binary32 arithmetic only; every value is carried
+// as an unevaluated sum of two floats (about 48 significant bits) because near
+// the maximum of the likelihood the per-class terms (size ~N) cancel down to a
+// gradient of size ~sqrt(N).
+#include "sd_loglik.hpp"
+
+namespace sd {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Counts
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restrict__ traj, uint32_t n_traj,
+                                                        uint32_t n_lat, uint32_t L, FastDiv divW,
+                                                        unsigned long long* __restrict__ counts) {
+    __shared__ int64_t red[12 * 4];
+    const uint32_t W = L / 64u;
+    const uint32_t n_words = L * W;
+    const uint32_t blocks_per_traj = (n_words + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = blockIdx.x / blocks_per_traj;
+    const uint32_t g = (blockIdx.x % blocks_per_traj) * blockDim.x + threadIdx.x;
+    int64_t acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        acc[i] = 0;
+    if (a < n_traj && g < n_words) {
+        const uint32_t j = fdiv(g, divW);
+        const uint32_t w = g - j * W;
+        const uint32_t down = (j == 0 ? L - 1 : j - 1) * W + w;
+        const uint32_t up = (j == L - 1 ? 0 : j + 1) * W + w;
+        const uint32_t prev = j * W + (w == 0 ? W - 1 : w - 1);
+        const uint32_t next = j * W + (w == W - 1 ? 0 : w + 1);
+        const uint64_t* X = traj + (size_t)a * n_lat * n_words;
+        uint64_t c = X[g];
+        for (uint32_t m = 0; m + 1 < n_lat; ++m) {
+            const uint64_t* Xm = X + (size_t)m * n_words;
+            const uint64_t y = Xm[n_words + g];
+            uint64_t n1, n2;
+            if ((m & 1u) == 0) {
+                n1 = Xm[down];
+                n2 = (c << 1) | (Xm[prev] >> 63);
+            } else {
+                n1 = Xm[up];
+                n2 = (c >> 1) | (Xm[next] << 63);
+            }
+            const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
+            const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const int64_t plus = __popcll(cls[i] & y);
+                acc[2 * i + 1] += plus;
+                acc[2 * i] += __popcll(cls[i]) - plus;
+            }
+            c = y;
+        }
+    }
+    block_sum_i64<12>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (acc[i])
+                atomicAdd(counts + i, (unsigned long long)acc[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Float-float arithmetic (pairs of binary32, error-free transformations).
+// ---------------------------------------------------------------------------
+struct ff {
+    float hi, lo;
+};
+
+__device__ __forceinline__ ff two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ ff quick_two_sum(float a, float b) {
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ ff two_prod(float a, float b) {
+    const float p = a * b;
+    return {p, __builtin_fmaf(a, b, -p)};
+}
+
+__device__ __forceinline__ ff ff_add(ff x, ff y) {
+    ff s = two_sum(x.hi, y.hi);
+    ff t = two_sum(x.lo, y.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ ff ff_neg(ff x) { return {-x.hi, -x.lo}; }
+
+__device__ __forceinline__ ff ff_sub(ff x, ff y) { return ff_add(x, ff_neg(y)); }
+
+__device__ __forceinline__ ff ff_mul(ff x, ff y) {
+    ff p = two_prod(x.hi, y.hi);
+    p.lo += x.hi * y.lo + x.lo * y.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ __forceinline__ ff ff_mul_f(ff x, float y) {
+    ff p = two_prod(x.hi, y);
+    p.lo += x.lo * y;
+    return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ __forceinline__ ff ff_div(ff x, ff y) {
+    const float q1 = x.hi / y.hi;
+    ff r = ff_sub(x, ff_mul_f(y, q1));
+    const float q2 = r.hi / y.hi;
+    r = ff_sub(r, ff_mul_f(y, q2));
+    const float q3 = r.hi / y.hi;
+    ff q = quick_two_sum(q1, q2);
+    return ff_add(q, ff{q3, 0.0f});
+}
+
+__device__ __forceinline__ ff ff_from_i64(int64_t v) {
+    const float hi = (float)v;
+    const float lo = (float)(v - (int64_t)hi);
+    return {hi, lo};
+}
+
+__device__ __forceinline__ ff ff_ldexp(ff x, int k) { return {ldexpf(x.hi, k), ldexpf(x.lo, k)}; }
+
+// ln 2 = 0.6931471805599453094...: binary32 head and the remainder.
+constexpr float kLn2Hi = 0.693147182464599609375f;
+constexpr float kLn2Lo = -1.904654323148236e-09f;
+
+// e^x for x <= 0 (x given as float-float): x = k ln2 + r with |r| <= ln2/2,
+// e^r by its Taylor series to degree 13 (truncation below 2e-16), then 2^k.
+__device__ ff ff_exp_nonpos(ff x) {
+    const float k = rintf(x.hi / kLn2Hi);
+    ff r = ff_sub(x, two_prod(k, kLn2Hi));
+    r = ff_sub(r, ff_mul_f(ff{kLn2Lo, 0.0f}, k));
+    // Horner with coefficients 1/i!
+    ff inv_fact[14];
+    inv_fact[0] = {1.0f, 0.0f};
+    for (int i = 1; i < 14; ++i)
+        inv_fact[i] = ff_div(inv_fact[i - 1], ff{(float)i, 0.0f});
+    ff p = inv_fact[13];
+    for (int i = 12; i >= 0; --i)
+        p = ff_add(ff_mul(p, r), inv_fact[i]);
+    return ff_ldexp(p, (int)k);
+}
+
+// log(1 + y) for 0 <= y <= 1: 2 atanh(z), z = y / (2 + y) <= 1/3, by the odd
+// series of atanh to 20 terms (truncation below 1e-19).
+__device__ ff ff_log1p_unit(ff y) {
+    const ff z = ff_div(y, ff_add(ff{2.0f, 0.0f}, y));
+    const ff z2 = ff_mul(z, z);
+    ff s = ff_div(ff{1.0f, 0.0f}, ff{41.0f, 0.0f});
+    for (int i = 19; i >= 0; --i)
+        s = ff_add(ff_mul(s, z2), ff_div(ff{1.0f, 0.0f}, ff{(float)(2 * i + 1), 0.0f}));
+    return ff_mul_f(ff_mul(z, s), 2.0f);
+}
+
+struct ClassTerms {
+    ff h;        // field of the class
+    ff log2ch;   // log 2cosh h
+    ff tanh_h;
+    float a, c;  // dh/dJ, dh/dq
+};
+
+__device__ ClassTerms class_terms(int idx, float J, float q) {
+    const int k = idx >> 1;
+    ClassTerms t;
+    t.a = (float)(2 * k - 2);
+    t.c = (idx & 1) ? 1.0f : -1.0f;
+    t.h = two_sum(J * t.a, q * t.c);   // both products are exact
+    const ff absh = t.h.hi < 0.0f ? ff_neg(t.h) : t.h;
+    const ff y = ff_exp_nonpos(ff_mul_f(absh, -2.0f));   // e^{-2|h|}
+    t.log2ch = ff_add(absh, ff_log1p_unit(y));
+    ff th = ff_div(ff_sub(ff{1.0f, 0.0f}, y), ff_add(ff{1.0f, 0.0f}, y));
+    t.tanh_h = t.h.hi < 0.0f ? ff_neg(th) : th;
+    return t;
+}
+
+__global__ void k_loglik_fwd(const int64_t* __restrict__ counts, const float* __restrict__ Jq,
+                             float* __restrict__ ll) {
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    const float J = Jq[0], q = Jq[1];
+    ff acc = {0.0f, 0.0f};
+    for (int idx = 0; idx < 6; ++idx) {
+        const ClassTerms t = class_terms(idx, J, q);
+        const int64_t np = counts[2 * idx + 1], nm = counts[2 * idx];
+        const ff d = ff_from_i64(np - nm), N = ff_from_i64(np + nm);
+        acc = ff_add(acc, ff_sub(ff_mul(d, t.h), ff_mul(N, t.log2ch)));
+    }
+    ll[0] = acc.hi + acc.lo;
+}
+
+__global__ void k_loglik_bwd(const int64_t* __restrict__ counts, const float* __restrict__ Jq,
+                             const float* __restrict__ g_out, float* __restrict__ grad) {
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    const float J = Jq[0], q = Jq[1];
+    ff gJ = {0.0f, 0.0f}, gq = {0.0f, 0.0f};
+    for (int idx = 0; idx < 6; ++idx) {
+        const ClassTerms t = class_terms(idx, J, q);
+        const int64_t np = counts[2 * idx + 1], nm = counts[2 * idx];
+        const ff resid = ff_sub(ff_from_i64(np - nm), ff_mul(ff_from_i64(np + nm), t.tanh_h));
+        gJ = ff_add(gJ, ff_mul_f(resid, t.a));
+        gq = ff_add(gq, ff_mul_f(resid, t.c));
+    }
+    const float go = g_out ? g_out[0] : 1.0f;
+    const ff rJ = ff_mul_f(gJ, go), rq = ff_mul_f(gq, go);
+    grad[0] = rJ.hi + rJ.lo;
+    grad[1] = rq.hi + rq.lo;
+}
+
+}  // namespace
+
+hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_lat, uint32_t L, int64_t* counts12,
+                                hipStream_t st) {
+    hipError_t e = launch_fill_i64(counts12, 12, 0, st);
+    if (e != hipSuccess)
+        return e;
+    const uint32_t n_words = L * (L / 64u);
+    const uint32_t bpt = (n_words + 255u) / 256u;
+    const uint64_t blocks = (uint64_t)bpt * n_traj;
+    if (blocks == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st, static_cast<const uint64_t*>(traj),
+                       n_traj, n_lat, L, make_fastdiv(L / 64u), reinterpret_cast<unsigned long long*>(counts12));
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, hipStream_t st) {
+    hipLaunchKernelGGL(k_loglik_fwd, dim3(1), dim3(64), 0, st, counts12, Jq, ll);
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_loglik_bwd, dim3(1), dim3(64), 0, st, counts12, Jq, g_out, grad);
+    return hipGetLastError();
+}
+
+}  // namespace sd

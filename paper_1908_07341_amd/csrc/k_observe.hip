@@ -1,0 +1,173 @@
+// Reductions over lattices: the pair observables M, A, B and the row-wise
+// spin-spin correlation sums D(r).
+//
+// M = sum_x sigma_x (magnetisation times L^2, section 3.1), and from the pair
+// Hamiltonian of eq. (5): A = sum_x sigma_x (tau_up + tau_right),
+// B = sum_x sigma_x tau_x, so that H(sigma, tau) = -(J A + q B).  With bit
+// 1 = +1, a product of two spins is +1 exactly when their bits agree, so every
+// sum is n - 2 * popcount(xor) over the n sites involved: exact integers.
+//
+// D(r) = sum_x sigma_(i,j) sigma_(i+r,j): the row-wise analogue of the
+// correlations of Table 1.  Each row is staged in LDS as a bit string followed
+// by a second copy of itself, so that the row rotated by r is a plain funnel
+// shift of two LDS words for every r.
+#include "sd_kernels.hpp"
+
+namespace sd {
+
+namespace {
+
+__device__ __forceinline__ void add_obs(int64_t* out3, int64_t pc, int64_t dpair, int64_t dself, int64_t n,
+                                        int64_t* red) {
+    int64_t v[4] = {pc, dpair, dself, n};
+    block_sum_i64<4>(v, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 0), (unsigned long long)(2 * v[0] - v[3]));
+        atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), (unsigned long long)(2 * v[3] - 2 * v[1]));
+        atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), (unsigned long long)(v[3] - 2 * v[2]));
+    }
+}
+
+// Packed layouts (L % 32 == 0): one lane per 32-bit word.
+__global__ __launch_bounds__(256) void k_observe_packed(const uint32_t* __restrict__ sigma,
+                                                         const uint32_t* __restrict__ tau, Geom G,
+                                                         int64_t* __restrict__ out3) {
+    __shared__ int64_t red[4 * 4];
+    const uint32_t W = G.L / 32u;
+    const uint32_t n_words = G.n_sites / 32u;
+    int64_t pc = 0, dpair = 0, dself = 0, n = 0;
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_words; u += gridDim.x * blockDim.x) {
+        const uint32_t j = fdiv(u, G.div_row);
+        const uint32_t w = u - j * W;
+        const uint32_t s = sigma[u];
+        const uint32_t t = tau[u];
+        const uint32_t up = tau[(j == G.L - 1 ? 0 : j + 1) * W + w];
+        const uint32_t next = tau[j * W + (w == W - 1 ? 0 : w + 1)];
+        const uint32_t right = (t >> 1) | (next << 31);
+        pc += __popc(s);
+        dpair += __popc(s ^ up) + __popc(s ^ right);
+        dself += __popc(s ^ t);
+        n += 32;
+    }
+    add_obs(out3, pc, dpair, dself, n, red);
+}
+
+// int8 layout, any L: one lane per site.
+__global__ __launch_bounds__(256) void k_observe_i8(const int8_t* __restrict__ sigma, const int8_t* __restrict__ tau,
+                                                     Geom G, int64_t* __restrict__ out3) {
+    __shared__ int64_t red[4 * 4];
+    int64_t pc = 0, dpair = 0, dself = 0, n = 0;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < G.n_sites; s += gridDim.x * blockDim.x) {
+        const uint32_t j = fdiv(s, G.div_L);
+        const uint32_t i = s - j * G.L;
+        const int sx = sigma[s] > 0;
+        const int tx = tau[s] > 0;
+        const int up = tau[(size_t)(j == G.L - 1 ? 0 : j + 1) * G.L + i] > 0;
+        const int right = tau[(size_t)j * G.L + (i == G.L - 1 ? 0 : i + 1)] > 0;
+        pc += sx;
+        dpair += (sx ^ up) + (sx ^ right);
+        dself += sx ^ tx;
+        n += 1;
+    }
+    add_obs(out3, pc, dpair, dself, n, red);
+}
+
+// Bits of one row, followed by a second copy, in LDS words (bit p of the
+// string is bit p % 32 of word p / 32).
+constexpr uint32_t kCorrMaxL = 65535;
+constexpr uint32_t kCorrWords = (2 * kCorrMaxL + 64) / 32 + 2;
+
+template <int PACKED>
+__device__ __forceinline__ void stage_row(const void* sigma, const Geom& G, uint32_t j, uint32_t* row, uint32_t nw2) {
+    if constexpr (PACKED) {
+        const uint32_t* s = static_cast<const uint32_t*>(sigma);
+        const uint32_t W = G.L / 32u;
+        for (uint32_t k = threadIdx.x; k < nw2; k += blockDim.x)
+            row[k] = s[(size_t)j * W + (k % W)];
+    } else {
+        const int8_t* s = static_cast<const int8_t*>(sigma) + (size_t)j * G.L;
+        for (uint32_t k = threadIdx.x; k < nw2; k += blockDim.x) {
+            uint32_t word = 0;
+            uint32_t col = (uint32_t)(((uint64_t)32u * k) % G.L);
+            for (int b = 0; b < 32; ++b) {
+                word |= (uint32_t)(s[col] > 0) << b;
+                if (++col == G.L)
+                    col = 0;
+            }
+            row[k] = word;
+        }
+    }
+}
+
+// out[r] += sum over the block's rows of D_row(r), r = blockIdx.x * blockDim.x + tid.
+template <int PACKED>
+__global__ __launch_bounds__(256) void k_corr_row(const void* __restrict__ sigma, Geom G, int32_t rmax,
+                                                   int64_t* __restrict__ out) {
+    __shared__ uint32_t row[kCorrWords];
+    const uint32_t L = G.L;
+    const uint32_t nwr = (L + 31u) / 32u;                 // words covering one row
+    const uint32_t nw2 = (2u * L + 63u) / 32u + 1u;       // words of the doubled string
+    const uint32_t last_bits = L - 32u * (nwr - 1u);      // valid bits of the last word
+    const uint32_t last_mask = last_bits == 32u ? ~0u : ((1u << last_bits) - 1u);
+    const int32_t r = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    int64_t acc = 0;
+    for (uint32_t j = blockIdx.y; j < L; j += gridDim.y) {
+        __syncthreads();
+        stage_row<PACKED>(sigma, G, j, row, nw2);
+        __syncthreads();
+        if (r <= rmax) {
+            uint32_t diff = 0;
+            for (uint32_t k = 0; k < nwr; ++k) {
+                const uint32_t off = 32u * k + (uint32_t)r;
+                const uint32_t q = off >> 5, sh = off & 31u;
+                const uint32_t rot = sh ? ((row[q] >> sh) | (row[q + 1] << (32u - sh))) : row[q];
+                const uint32_t mask = (k == nwr - 1u) ? last_mask : ~0u;
+                diff += __popc((row[k] ^ rot) & mask);
+            }
+            acc += (int64_t)L - 2 * (int64_t)diff;
+        }
+    }
+    if (r <= rmax)
+        atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)acc);
+}
+
+}  // namespace
+
+hipError_t launch_observe(int layout, const void* sigma, const void* tau, const Geom& G, int64_t* out3,
+                          hipStream_t st) {
+    hipError_t e = launch_fill_i64(out3, 3, 0, st);
+    if (e != hipSuccess)
+        return e;
+    if (layout == kLayP64 || layout == kLayP32) {
+        uint32_t n_words = G.n_sites / 32u;
+        uint32_t blocks = (n_words + 255u) / 256u;
+        blocks = blocks < kMaxBlocks ? blocks : kMaxBlocks;
+        hipLaunchKernelGGL(k_observe_packed, dim3(blocks ? blocks : 1), dim3(256), 0, st,
+                           static_cast<const uint32_t*>(sigma), static_cast<const uint32_t*>(tau), G, out3);
+    } else {
+        uint32_t blocks = (G.n_sites + 255u) / 256u;
+        blocks = blocks < kMaxBlocks ? blocks : kMaxBlocks;
+        hipLaunchKernelGGL(k_observe_i8, dim3(blocks ? blocks : 1), dim3(256), 0, st,
+                           static_cast<const int8_t*>(sigma), static_cast<const int8_t*>(tau), G, out3);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
+                           hipStream_t st) {
+    hipError_t e = launch_fill_i64(out, (size_t)rmax + 1, 0, st);
+    if (e != hipSuccess)
+        return e;
+    const uint32_t r_chunks = ((uint32_t)rmax + 256u) / 256u;
+    uint32_t row_blocks = kMaxBlocks / r_chunks;
+    row_blocks = row_blocks < G.L ? row_blocks : G.L;
+    row_blocks = row_blocks ? row_blocks : 1u;
+    const dim3 grid(r_chunks, row_blocks);
+    if (layout == kLayP64 || layout == kLayP32)
+        hipLaunchKernelGGL((k_corr_row<1>), grid, dim3(256), 0, st, sigma, G, rmax, out);
+    else
+        hipLaunchKernelGGL((k_corr_row<0>), grid, dim3(256), 0, st, sigma, G, rmax, out);
+    return hipGetLastError();
+}
+
+}  // namespace sd

@@ -1,0 +1,318 @@
+// Half-step kernels of the shaken dynamics and the random initial lattice.
+//
+// Half-step A (section 2, eq. (15) and the per-site sampling after it): every
+// tau_x is drawn at once from the field J(sigma_down + sigma_left) + q sigma_x.
+// Half-step B (eq. (16)): every sigma'_x from J(tau_up + tau_right) + q tau_x.
+// One lane owns one 64-site group (64 consecutive sites in row-major order):
+// it gathers the partner bits c and the two J-neighbour bits n1, n2 of its 64
+// sites, draws the eight random planes of the group, compares them bit-sliced
+// against the threshold table and resolves the rare undecided sites together
+// with the rest of the workgroup.  Half-step B can also fold the observables
+// M, A, B of the new pair (sigma', tau) into the same pass, since it already
+// holds tau_x, tau_up and tau_right of every site it writes.
+#include "sd_kernels.hpp"
+
+namespace sd {
+
+namespace {
+
+constexpr int kTailCap = 1024;
+
+__device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t x) {
+    // byte k of x is 0x01 (+1) or 0xFF (-1); bit k of the result is 1 for +1
+    uint32_t y = (~x >> 7) & 0x01010101u;
+    return (y * 0x10204080u) >> 28;
+}
+
+__device__ __forceinline__ uint32_t bits4_to_bytes(uint32_t n) {
+    uint32_t z = (n * 0x00204081u) & 0x01010101u;   // byte k = bit k of n
+    uint32_t w = z ^ 0x01010101u;                    // 1 where the spin is -1
+    return z | ((w << 8) - w);
+}
+
+__device__ __forceinline__ uint64_t load_bits64_i8(const int8_t* p) {
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+    uint64_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint4 x = v[q];
+        uint32_t b16 = bytes_to_bits4(x.x) | (bytes_to_bits4(x.y) << 4) | (bytes_to_bits4(x.z) << 8) |
+                       (bytes_to_bits4(x.w) << 12);
+        bits |= (uint64_t)b16 << (16 * q);
+    }
+    return bits;
+}
+
+__device__ __forceinline__ void store_bits64_i8(int8_t* p, uint64_t bits) {
+    uint4* v = reinterpret_cast<uint4*>(p);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t b16 = (uint32_t)(bits >> (16 * q)) & 0xFFFFu;
+        uint4 x;
+        x.x = bits4_to_bytes(b16 & 0xF);
+        x.y = bits4_to_bytes((b16 >> 4) & 0xF);
+        x.z = bits4_to_bytes((b16 >> 8) & 0xF);
+        x.w = bits4_to_bytes((b16 >> 12) & 0xF);
+        v[q] = x;
+    }
+}
+
+// Partner bits c and neighbour bits n1, n2 of group g (all 64 bits valid for
+// every layout except the generic int8 one, which reports its valid mask).
+template <int LAYOUT, int WHICH>
+__device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t g, uint64_t& c, uint64_t& n1,
+                                       uint64_t& n2, uint64_t& valid) {
+    valid = ~0ull;
+    if constexpr (LAYOUT == kLayP64) {
+        const uint64_t* s = static_cast<const uint64_t*>(src);
+        const uint32_t W = G.words_row;
+        const uint32_t j = fdiv(g, G.div_row);
+        const uint32_t w = g - j * W;
+        const uint32_t row = j * W;
+        c = s[g];
+        if constexpr (WHICH == 0) {
+            n1 = s[(j == 0 ? G.L - 1 : j - 1) * W + w];                       // down
+            uint64_t prev = s[row + (w == 0 ? W - 1 : w - 1)];
+            n2 = (c << 1) | (prev >> 63);                                     // left
+        } else {
+            n1 = s[(j == G.L - 1 ? 0 : j + 1) * W + w];                       // up
+            uint64_t next = s[row + (w == W - 1 ? 0 : w + 1)];
+            n2 = (c >> 1) | (next << 63);                                     // right
+        }
+    } else if constexpr (LAYOUT == kLayP32) {
+        const uint32_t* s = static_cast<const uint32_t*>(src);
+        const uint32_t W = G.words_row;   // 32-bit words per row
+        uint32_t cc[2], a[2], b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t u = 2 * g + h;
+            const uint32_t j = fdiv(u, G.div_row);
+            const uint32_t w = u - j * W;
+            const uint32_t row = j * W;
+            const uint32_t x = s[u];
+            cc[h] = x;
+            if constexpr (WHICH == 0) {
+                a[h] = s[(j == 0 ? G.L - 1 : j - 1) * W + w];
+                uint32_t prev = s[row + (w == 0 ? W - 1 : w - 1)];
+                b[h] = (x << 1) | (prev >> 31);
+            } else {
+                a[h] = s[(j == G.L - 1 ? 0 : j + 1) * W + w];
+                uint32_t next = s[row + (w == W - 1 ? 0 : w + 1)];
+                b[h] = (x >> 1) | (next << 31);
+            }
+        }
+        c = (uint64_t)cc[0] | ((uint64_t)cc[1] << 32);
+        n1 = (uint64_t)a[0] | ((uint64_t)a[1] << 32);
+        n2 = (uint64_t)b[0] | ((uint64_t)b[1] << 32);
+    } else if constexpr (LAYOUT == kLayI8Row) {
+        const int8_t* s = static_cast<const int8_t*>(src);
+        const uint32_t W = G.words_row;   // 64-site groups per row
+        const uint32_t j = fdiv(g, G.div_row);
+        const uint32_t w = g - j * W;
+        const size_t row = (size_t)j * G.L;
+        const size_t s0 = row + 64u * w;
+        c = load_bits64_i8(s + s0);
+        if constexpr (WHICH == 0) {
+            const size_t nrow = (size_t)(j == 0 ? G.L - 1 : j - 1) * G.L;
+            n1 = load_bits64_i8(s + nrow + 64u * w);
+            const int8_t edge = s[row + (w == 0 ? G.L - 1 : 64u * w - 1)];
+            n2 = (c << 1) | (edge > 0 ? 1ull : 0ull);
+        } else {
+            const size_t nrow = (size_t)(j == G.L - 1 ? 0 : j + 1) * G.L;
+            n1 = load_bits64_i8(s + nrow + 64u * w);
+            const int8_t edge = s[row + (w == W - 1 ? 0 : 64u * w + 64u)];
+            n2 = (c >> 1) | (edge > 0 ? (1ull << 63) : 0ull);
+        }
+    } else {  // kLayI8Any: per-site gather, any L >= 2
+        const int8_t* s = static_cast<const int8_t*>(src);
+        const uint32_t s0 = 64u * g;
+        const uint32_t nv = G.n_sites - s0 < 64u ? G.n_sites - s0 : 64u;
+        uint32_t j = fdiv(s0, G.div_L);
+        uint32_t i = s0 - j * G.L;
+        c = 0; n1 = 0; n2 = 0;
+        for (uint32_t b = 0; b < nv; ++b) {
+            const size_t row = (size_t)j * G.L;
+            const uint64_t bit = 1ull << b;
+            if (s[row + i] > 0) c |= bit;
+            if constexpr (WHICH == 0) {
+                if (s[(size_t)(j == 0 ? G.L - 1 : j - 1) * G.L + i] > 0) n1 |= bit;
+                if (s[row + (i == 0 ? G.L - 1 : i - 1)] > 0) n2 |= bit;
+            } else {
+                if (s[(size_t)(j == G.L - 1 ? 0 : j + 1) * G.L + i] > 0) n1 |= bit;
+                if (s[row + (i == G.L - 1 ? 0 : i + 1)] > 0) n2 |= bit;
+            }
+            if (++i == G.L) { i = 0; ++j; }
+        }
+        valid = nv == 64u ? ~0ull : ((1ull << nv) - 1ull);
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, uint64_t bits, uint64_t valid) {
+    if constexpr (LAYOUT == kLayP64) {
+        static_cast<uint64_t*>(dst)[g] = bits;
+    } else if constexpr (LAYOUT == kLayP32) {
+        uint32_t* d = static_cast<uint32_t*>(dst);
+        d[2 * g] = (uint32_t)bits;
+        d[2 * g + 1] = (uint32_t)(bits >> 32);
+    } else if constexpr (LAYOUT == kLayI8Row) {
+        store_bits64_i8(static_cast<int8_t*>(dst) + (size_t)64u * g, bits);
+    } else {
+        int8_t* d = static_cast<int8_t*>(dst) + (size_t)64u * g;
+        for (int b = 0; b < 64; ++b)
+            if ((valid >> b) & 1ull)
+                d[b] = ((bits >> b) & 1ull) ? 1 : -1;
+    }
+}
+
+// One half-step.  obs (half-step B only, may be null) receives the observable
+// contributions of the written pair through 64-bit atomics; it must hold
+// zeros (or earlier partial sums of the same record) before the launch.
+template <int LAYOUT, int WHICH>
+__global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
+                                                   DrawParams dp, int64_t* __restrict__ obs) {
+    __shared__ TailScratch<kTailCap> tails;
+    __shared__ int64_t red[4 * 4];
+    int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
+    const PlaneMasks pm = make_plane_masks(dp);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < G.n_groups; base += stride) {
+        const uint32_t g = base + threadIdx.x;
+        const bool active = g < G.n_groups;
+        uint64_t c = 0, n1 = 0, n2 = 0, valid = 0;
+        if (active)
+            gather<LAYOUT, WHICH>(src, G, g, c, n1, n2, valid);
+        uint64_t P[8];
+        draw_planes(dp, active ? g : 0u, P);
+        WordDraw wd = compare_planes(P, c, n1, n2, pm, dp.rng_xor);
+        uint64_t lt = wd.lt;
+        resolve_tails<kTailCap>(lt, wd.und & valid, c, n1, n2, 64u * g, dp, tails);
+        if (active) {
+            lt &= valid;
+            scatter<LAYOUT>(dst, G, g, lt, valid);
+            if (WHICH == 1 && obs) {
+                pc += __popcll(lt);
+                d_up += __popcll((lt ^ n1) & valid);
+                d_right += __popcll((lt ^ n2) & valid);
+                d_self += __popcll((lt ^ c) & valid);
+                nsites += __popcll(valid);
+            }
+        }
+    }
+    if (WHICH == 1 && obs) {
+        int64_t v[4] = {pc, d_up + d_right, d_self, nsites};
+        block_sum_i64<4>(v, red);
+        if (threadIdx.x == 0) {
+            const int64_t n = v[3];
+            atomicAdd(reinterpret_cast<unsigned long long*>(obs + 0), (unsigned long long)(2 * v[0] - n));
+            atomicAdd(reinterpret_cast<unsigned long long*>(obs + 1), (unsigned long long)(2 * n - 2 * v[1]));
+            atomicAdd(reinterpret_cast<unsigned long long*>(obs + 2), (unsigned long long)(n - 2 * v[2]));
+        }
+    }
+}
+
+// Random initial lattice: site s is +1 iff r_s(t = 0, tag 1) < P, the same
+// threshold for every site (all six table entries equal P).
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_init_random(void* __restrict__ dst, Geom G, DrawParams dp) {
+    __shared__ TailScratch<kTailCap> tails;
+    const PlaneMasks pm = make_plane_masks(dp);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < G.n_groups; base += stride) {
+        const uint32_t g = base + threadIdx.x;
+        const bool active = g < G.n_groups;
+        uint64_t valid = 0;
+        if (active) {
+            const uint32_t s0 = 64u * g;
+            const uint32_t nv = G.n_sites - s0 < 64u ? G.n_sites - s0 : 64u;
+            valid = nv == 64u ? ~0ull : ((1ull << nv) - 1ull);
+        }
+        uint64_t P[8];
+        draw_planes(dp, active ? g : 0u, P);
+        WordDraw wd = compare_planes(P, 0, 0, 0, pm, dp.rng_xor);
+        uint64_t lt = wd.lt;
+        resolve_tails<kTailCap>(lt, wd.und & valid, 0, 0, 0, 64u * g, dp, tails);
+        if (active)
+            scatter<LAYOUT>(dst, G, g, lt & valid, valid);
+    }
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_init_const(void* __restrict__ dst, Geom G, uint32_t up) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint64_t bits = up ? ~0ull : 0ull;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G.n_groups; g += stride) {
+        const uint32_t s0 = 64u * g;
+        const uint32_t nv = G.n_sites - s0 < 64u ? G.n_sites - s0 : 64u;
+        const uint64_t valid = nv == 64u ? ~0ull : ((1ull << nv) - 1ull);
+        scatter<LAYOUT>(dst, G, g, bits & valid, valid);
+    }
+}
+
+__global__ void k_fill_i64(int64_t* __restrict__ p, size_t n, int64_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+uint32_t grid_for(uint32_t n_groups) {
+    uint32_t blocks = (n_groups + 255u) / 256u;
+    return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
+}
+
+}  // namespace
+
+hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
+                            int64_t* obs, hipStream_t st) {
+    const dim3 grid(grid_for(G.n_groups)), block(256);
+#define SD_HALF(LAY)                                                                                  \
+    case LAY:                                                                                         \
+        if (which == 0)                                                                               \
+            hipLaunchKernelGGL((k_half_step<LAY, 0>), grid, block, 0, st, src, dst, G, dp, nullptr); \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_half_step<LAY, 1>), grid, block, 0, st, src, dst, G, dp, obs);     \
+        break;
+    switch (layout) {
+        SD_HALF(kLayP64)
+        SD_HALF(kLayP32)
+        SD_HALF(kLayI8Row)
+        SD_HALF(kLayI8Any)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef SD_HALF
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int layout, void* dst, const Geom& G, int kind_const_up, bool random, const DrawParams& dp,
+                       hipStream_t st) {
+    const dim3 grid(grid_for(G.n_groups)), block(256);
+#define SD_INIT(LAY)                                                                                    \
+    case LAY:                                                                                           \
+        if (random)                                                                                     \
+            hipLaunchKernelGGL((k_init_random<LAY>), grid, block, 0, st, dst, G, dp);                   \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_init_const<LAY>), grid, block, 0, st, dst, G, (uint32_t)kind_const_up); \
+        break;
+    switch (layout) {
+        SD_INIT(kLayP64)
+        SD_INIT(kLayP32)
+        SD_INIT(kLayI8Row)
+        SD_INIT(kLayI8Any)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef SD_INIT
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace sd

@@ -1,0 +1,76 @@
+// Host side of the trajectory generator and the log-likelihood entry points.
+#include <cmath>
+
+#include "sd_host.hpp"
+#include "sd_loglik.hpp"
+
+using namespace sd;
+
+extern "C" {
+
+sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_t layout, double J, double q, uint64_t seed,
+                        uint32_t stream, uint64_t step0, uint32_t k_steps, void* hip_stream) {
+    if (layout != SD_P64 && layout != SD_P32)
+        return fail(SD_EUNSUPPORTED, "sd_trajectory: trajectories are stored packed (SD_P64 or SD_P32)");
+    if (!layout_supported(L, layout) || !sigma0 || !traj)
+        return fail(SD_EINVAL, "sd_trajectory: bad lattice size or null pointer");
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "sd_trajectory: J and q must be finite");
+    if (step0 + (uint64_t)k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "sd_trajectory: step indices must stay below 2^29");
+    const uintptr_t align = layout == SD_P64 ? 8u : 4u;
+    if ((reinterpret_cast<uintptr_t>(sigma0) | reinterpret_cast<uintptr_t>(traj)) & (align - 1))
+        return fail(SD_EINVAL, "sd_trajectory: pointers not aligned to the word size");
+    const size_t bytes = lattice_bytes(L, layout);
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(sigma0), t0 = reinterpret_cast<uintptr_t>(traj);
+    if (s0 < t0 + bytes * (2 * (size_t)k_steps + 1) && t0 < s0 + bytes && s0 != t0)
+        return fail(SD_EINVAL, "sd_trajectory: sigma0 overlaps the trajectory (other than as its first lattice)");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    uint8_t* base = static_cast<uint8_t*>(traj);
+    hipError_t e = hipSuccess;
+    if (sigma0 != traj)
+        e = hipMemcpyAsync(base, sigma0, bytes, hipMemcpyDeviceToDevice, st);
+    const int klay = layout == SD_P64 ? kLayP64 : kLayP32;
+    const Geom G = make_geom(L, klay);
+    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
+        const uint64_t n = step0 + m;
+        uint8_t* x = base + (2 * (size_t)m) * bytes;
+        DrawParams dp = dynamics_params(J, q, seed, stream, (uint32_t)(2 * n), 0);
+        e = launch_half_step(klay, 0, x, x + bytes, G, dp, nullptr, st);
+        if (e == hipSuccess) {
+            dp.t = (uint32_t)(2 * n + 1);
+            e = launch_half_step(klay, 1, x + bytes, x + 2 * bytes, G, dp, nullptr, st);
+        }
+    }
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_trajectory");
+}
+
+sd_status sd_loglik_counts(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* counts12,
+                           void* hip_stream) {
+    if (!traj || !counts12)
+        return fail(SD_EINVAL, "sd_loglik_counts: null pointer");
+    if (n_traj < 0 || n_lat < 1 || L < 64 || L > 65535 || L % 64 != 0)
+        return fail(SD_EINVAL, "sd_loglik_counts: need n_traj >= 0, n_lat >= 1 and L a multiple of 64");
+    if (reinterpret_cast<uintptr_t>(traj) & 7u)
+        return fail(SD_EINVAL, "sd_loglik_counts: trajectories must be 8-byte aligned");
+    hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, counts12,
+                                        static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_counts");
+}
+
+sd_status sd_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, void* hip_stream) {
+    if (!counts12 || !Jq || !ll)
+        return fail(SD_EINVAL, "sd_loglik_fwd: null pointer");
+    hipError_t e = launch_loglik_fwd(counts12, Jq, ll, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_fwd");
+}
+
+sd_status sd_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
+                        void* hip_stream) {
+    if (!counts12 || !Jq || !grad)
+        return fail(SD_EINVAL, "sd_loglik_bwd: null pointer");
+    hipError_t e = launch_loglik_bwd(counts12, Jq, g_out, grad, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_bwd");
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Internal interface of the batched (many-chain) persistent kernel.
+#pragma once
+
+#include "sd_kernels.hpp"
+
+namespace sd {
+
+// One chain of a batch (device array, built on the host).
+struct ChainDesc {
+    uint32_t T[6];          // threshold table of this chain's (J, q)
+    uint32_t L;             // lattice size, L % 64 == 0
+    uint32_t stream;        // stream id of the chain's randomness
+    FastDiv divW;           // division by L / 64
+    uint64_t sig_offset;    // sigma, in bytes from the lattices base
+    uint64_t tau_offset;    // tau, in bytes from the lattices base
+    uint64_t trace_offset;  // first int64 of the chain's trace
+};
+
+struct BatchArgs {
+    const ChainDesc* chains;
+    const uint32_t* order;   // queue position -> chain index (longest first)
+    uint32_t n_chains;       // chains in this launch's queue
+    uint32_t* counter;       // queue head, zero before the launch; null: run `single` in block 0
+    ChainDesc single;        // the chain of a single-chain launch (offsets unused)
+    uint8_t* single_sig;     // its sigma
+    uint8_t* single_tau;     // its tau
+    uint8_t* lattices;       // base of all lattices
+    int64_t* traces;         // may be null
+    uint32_t key0, key1;
+    uint32_t step0;          // first step index
+    uint32_t k_steps;
+    uint32_t obs_every;
+    uint32_t rng_xor;
+    uint32_t max_words;      // capacity (64-bit words) of each LDS lattice buffer
+    uint32_t tail_cap;       // capacity of the LDS list of undecided sites
+    uint32_t int8_io;        // lattices in global memory are int8 (L % 64 == 0)
+};
+
+size_t batch_lds_bytes(uint32_t max_words, uint32_t tail_cap);
+hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);
+hipError_t batch_kernel_attributes(size_t max_dynamic_lds);
+hipError_t batch_occupancy(uint32_t threads, size_t lds, int* blocks_per_cu);
+
+// Lattices with at most this many 64-site words run in one workgroup with
+// LDS-resident lattices when sd_run is called without SD_FLAG_GLOBAL_KERNELS.
+constexpr uint32_t kSingleLdsMaxWords = 1024;
+
+hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_io, double J, double q,
+                                   uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,
+                                   uint32_t obs_every, uint32_t flags, uint32_t threads, hipStream_t st);
+
+}  // namespace sd

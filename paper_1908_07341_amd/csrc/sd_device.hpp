@@ -1,0 +1,344 @@
+// Device building blocks of the shaken-dynamics kernels (gfx950, wave64).
+//
+// The heat-bath draw of Algorithm 3 ("+1 if rand() < p") is realised as
+// r_s < T[class] with r_s a 32-bit uniform and T a uint32 threshold table.  The
+// uniform of site s at half-step index t is defined by the stream contract:
+//   * sites are grouped 64 at a time in linear order (group g = s / 64,
+//     bit b = s % 64);
+//   * four Philox4x32-10 calls X = Philox(ctr = (stream, t | p<<30, 2*tag, g))
+//     give eight 64-bit planes (plane 2p = X0 | X1<<32, plane 2p+1 = X2 | X3<<32);
+//     bit (31 - m) of r_s is bit b of plane m;
+//   * the low 24 bits of r_s are Y[s % 4] >> 8 with
+//     Y = Philox(ctr = (stream, t, 2*tag + 1, s / 4)).
+// A site is decided by the most significant bit where r_s and T differ, so the
+// kernels compare the eight planes bit-sliced against the thresholds (one lane
+// per 64-site word) and draw the low bits only for the ~1/256 sites whose top
+// byte equals the threshold's.  The result is identical to comparing the full
+// 32-bit r_s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sd {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+constexpr uint32_t kTagDynamics = 0;
+constexpr uint32_t kTagInit = 1;
+
+// Per-launch constants of one draw (one half-step or one random initialisation).
+struct DrawParams {
+    uint32_t T[6];      // thresholds by class idx = 2k + [c = +1]
+    uint32_t key0;      // seed mod 2^32
+    uint32_t key1;      // seed div 2^32
+    uint32_t stream;    // chain id
+    uint32_t t;         // half-step index (< 2^30)
+    uint32_t tag2;      // 2 * tag
+    uint32_t rng_xor;   // 0, or ~0 to replace every uniform r by 2^32 - 1 - r
+};
+
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+
+// Three-way XOR in one VALU op (gfx950 V_BITOP3_B32, truth table 0x96 is
+// symmetric in its operands).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+struct U4 { uint32_t x0, x1, x2, x3; };
+
+// One Philox round whose counter words are all lane-varying.
+__device__ __forceinline__ U4 philox_round(U4 c, uint32_t k0, uint32_t k1) {
+    uint64_t p0 = (uint64_t)kPhiloxM0 * c.x0;
+    uint64_t p1 = (uint64_t)kPhiloxM1 * c.x2;
+    U4 n;
+    n.x0 = xor3(hi32(p1), c.x1, k0);
+    n.x1 = lo32(p1);
+    n.x2 = xor3(hi32(p0), c.x3, k1);
+    n.x3 = lo32(p0);
+    return n;
+}
+
+// Philox4x32-10 for a counter (u0, u1, u2, v3) whose first three words are
+// wavefront-uniform and whose last word v3 varies per lane.  Rounds 1-3 are
+// written out so the uniform parts stay on the scalar unit.
+__device__ __forceinline__ U4 philox10_uuuv(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t v3,
+                                            uint32_t k0, uint32_t k1) {
+    // round 1: both products uniform
+    uint64_t a0 = (uint64_t)kPhiloxM0 * u0;
+    uint64_t a1 = (uint64_t)kPhiloxM1 * u2;
+    uint32_t c0 = hi32(a1) ^ u1 ^ k0;           // uniform
+    uint32_t c1 = lo32(a1);                     // uniform
+    uint32_t c2 = (hi32(a0) ^ k1) ^ v3;         // lane-varying
+    uint32_t c3 = lo32(a0);                     // uniform
+    k0 += kPhiloxW0; k1 += kPhiloxW1;
+    // round 2: product of c0 uniform, of c2 varying
+    uint64_t b0 = (uint64_t)kPhiloxM0 * c0;
+    uint64_t b1 = (uint64_t)kPhiloxM1 * c2;
+    uint32_t d0 = hi32(b1) ^ (c1 ^ k0);
+    uint32_t d1 = lo32(b1);
+    uint32_t d2 = hi32(b0) ^ c3 ^ k1;          // uniform
+    uint32_t d3 = lo32(b0);                    // uniform
+    k0 += kPhiloxW0; k1 += kPhiloxW1;
+    // round 3: product of d0 varying, of d2 uniform
+    uint64_t e0 = (uint64_t)kPhiloxM0 * d0;
+    uint64_t e1 = (uint64_t)kPhiloxM1 * d2;
+    U4 c;
+    c.x0 = d1 ^ (hi32(e1) ^ k0);
+    c.x1 = lo32(e1);                           // uniform
+    c.x2 = hi32(e0) ^ (d3 ^ k1);
+    c.x3 = lo32(e0);
+    k0 += kPhiloxW0; k1 += kPhiloxW1;
+    // round 4: x1 is still uniform
+    {
+        uint64_t p0 = (uint64_t)kPhiloxM0 * c.x0;
+        uint64_t p1 = (uint64_t)kPhiloxM1 * c.x2;
+        U4 n;
+        n.x0 = hi32(p1) ^ (c.x1 ^ k0);
+        n.x1 = lo32(p1);
+        n.x2 = xor3(hi32(p0), c.x3, k1);
+        n.x3 = lo32(p0);
+        c = n;
+    }
+#pragma unroll
+    for (int r = 4; r < 10; ++r) {
+        k0 += kPhiloxW0; k1 += kPhiloxW1;
+        c = philox_round(c, k0, k1);
+    }
+    return c;
+}
+
+// The eight random planes of group g.  The four calls differ only in counter
+// word 1 (t | p<<30), which is uniform, so the compiler shares the
+// lane-varying products of rounds 2 and 3 between them.
+__device__ __forceinline__ void draw_planes(const DrawParams& dp, uint32_t g, uint64_t P[8]) {
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        U4 x = philox10_uuuv(dp.stream, dp.t | (p << 30), dp.tag2, g, dp.key0, dp.key1);
+        P[2 * p] = ((uint64_t)x.x0 | ((uint64_t)x.x1 << 32));
+        P[2 * p + 1] = ((uint64_t)x.x2 | ((uint64_t)x.x3 << 32));
+    }
+}
+
+// Low 24 bits of r_s (already complemented when rng_xor is set).
+__device__ __forceinline__ uint32_t draw_tail24(const DrawParams& dp, uint32_t s) {
+    U4 y = philox10_uuuv(dp.stream, dp.t, dp.tag2 + 1u, s >> 2, dp.key0, dp.key1);
+    uint32_t w = (s & 3u) == 0 ? y.x0 : (s & 3u) == 1 ? y.x1 : (s & 3u) == 2 ? y.x2 : y.x3;
+    return (w ^ dp.rng_xor) >> 8;
+}
+
+__device__ __forceinline__ uint32_t threshold_of(const DrawParams& dp, uint32_t idx) {
+    uint32_t v = dp.T[0];
+    v = idx == 1 ? dp.T[1] : v;
+    v = idx == 2 ? dp.T[2] : v;
+    v = idx == 3 ? dp.T[3] : v;
+    v = idx == 4 ? dp.T[4] : v;
+    v = idx == 5 ? dp.T[5] : v;
+    return v;
+}
+
+// Copy of a wavefront-uniform value held in a vector register.  Loop-invariant
+// uniforms of the inner loops (threshold bit masks) are kept this way so that
+// they do not crowd the scalar register file.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"(x));
+    return v;
+}
+
+// Threshold bits of the eight planes as all-ones / all-zeros masks, one per
+// (plane m, class idx): S[m][idx] = ~0 iff bit (31 - m) of T[idx] is set.
+struct PlaneMasks {
+    uint32_t S[8][6];
+};
+
+__device__ __forceinline__ PlaneMasks make_plane_masks(const DrawParams& dp) {
+    PlaneMasks pm;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            pm.S[m][i] = in_vgpr(0u - ((dp.T[i] >> (31 - m)) & 1u));
+    return pm;
+}
+
+// Bit-sliced comparison of the top 8 bits of every r_s in a 32-site half word
+// against the per-site thresholds.  n1, n2 are the two J-neighbour bits and c
+// the partner bit of each site (bit 1 = spin +1).  Returns in lt the sites
+// already known to satisfy r < T and in und those whose top byte equals the
+// threshold's top byte.
+struct HalfWord {
+    uint32_t lt, und;
+};
+
+__device__ __forceinline__ HalfWord compare_planes_32(const uint32_t P[8], uint32_t c, uint32_t n1,
+                                                      uint32_t n2, const PlaneMasks& pm, uint32_t rng_xor) {
+    const uint32_t k2 = n1 & n2;
+    const uint32_t k1 = n1 ^ n2;
+    const uint32_t k0 = ~(n1 | n2);
+    const uint32_t m0 = k0 & ~c, m1 = k0 & c;
+    const uint32_t m2 = k1 & ~c, m3 = k1 & c;
+    const uint32_t m4 = k2 & ~c, m5 = k2 & c;
+    uint32_t lt = 0, und = ~0u;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const uint32_t tb = (m0 & pm.S[m][0]) | (m1 & pm.S[m][1]) | (m2 & pm.S[m][2]) | (m3 & pm.S[m][3]) |
+                            (m4 & pm.S[m][4]) | (m5 & pm.S[m][5]);
+        const uint32_t r = P[m] ^ rng_xor;
+        lt |= und & tb & ~r;
+        und &= ~(r ^ tb);
+    }
+    return {lt, und};
+}
+
+struct WordDraw {
+    uint64_t lt, und;
+};
+
+__device__ __forceinline__ WordDraw compare_planes(const uint64_t P[8], uint64_t c, uint64_t n1, uint64_t n2,
+                                                   const PlaneMasks& pm, uint32_t rng_xor) {
+    uint32_t Plo[8], Phi[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        Plo[m] = (uint32_t)P[m];
+        Phi[m] = (uint32_t)(P[m] >> 32);
+    }
+    HalfWord lo = compare_planes_32(Plo, (uint32_t)c, (uint32_t)n1, (uint32_t)n2, pm, rng_xor);
+    HalfWord hi = compare_planes_32(Phi, (uint32_t)(c >> 32), (uint32_t)(n1 >> 32), (uint32_t)(n2 >> 32), pm,
+                                    rng_xor);
+    return {(uint64_t)lo.lt | ((uint64_t)hi.lt << 32), (uint64_t)lo.und | ((uint64_t)hi.und << 32)};
+}
+
+__device__ __forceinline__ uint32_t class_at(uint64_t c, uint64_t n1, uint64_t n2, int b) {
+    uint32_t k = (uint32_t)((n1 >> b) & 1u) + (uint32_t)((n2 >> b) & 1u);
+    return 2u * k + (uint32_t)((c >> b) & 1u);
+}
+
+// Decision of one undecided site: its top byte equals the threshold's, so
+// r < T iff the low 24 bits compare below.
+__device__ __forceinline__ bool decide_tail(const DrawParams& dp, uint32_t s, uint32_t idx) {
+    return draw_tail24(dp, s) < (threshold_of(dp, idx) & 0xFFFFFFu);
+}
+
+// Workgroup-shared scratch for resolving undecided sites cooperatively.
+template <int CAP>
+struct TailScratch {
+    uint32_t count;
+    uint32_t site[CAP];
+    uint8_t info[CAP];   // class idx on entry, decision (0/1) on exit
+};
+
+// Resolve the undecided sites of every lane of the workgroup.  Must be called
+// by all threads of the block (it contains barriers).  `und` marks undecided
+// bits of the word whose bit 0 is site `site0`; the decided +1 bits are or-ed
+// into `lt`.  Entries are handed out with one LDS atomic per lane that has
+// undecided bits, resolved one per thread, and read back by their owners in
+// the order they were written.  If more than CAP sites are undecided (never
+// observed: the mean is 0.25 per word) each lane resolves its own bits.
+template <int CAP>
+__device__ __forceinline__ void resolve_tails(uint64_t& lt, uint64_t und, uint64_t c, uint64_t n1, uint64_t n2,
+                                              uint32_t site0, const DrawParams& dp, TailScratch<CAP>& sh) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0)
+        sh.count = 0;
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)__popcll(und);
+    uint32_t base = 0;
+    if (cnt)
+        base = atomicAdd(&sh.count, cnt);
+    __syncthreads();
+    const uint32_t total = sh.count;
+    if (total <= (uint32_t)CAP) {
+        if (cnt) {
+            uint64_t u = und;
+            uint32_t e = base;
+            while (u) {
+                int b = __ffsll((unsigned long long)u) - 1;
+                u &= u - 1;
+                sh.site[e] = site0 + (uint32_t)b;
+                sh.info[e] = (uint8_t)class_at(c, n1, n2, b);
+                ++e;
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < total; e += blockDim.x)
+            sh.info[e] = decide_tail(dp, sh.site[e], sh.info[e]) ? 1 : 0;
+        __syncthreads();
+        if (cnt) {
+            uint64_t u = und;
+            uint32_t e = base;
+            while (u) {
+                int b = __ffsll((unsigned long long)u) - 1;
+                u &= u - 1;
+                if (sh.info[e])
+                    lt |= 1ull << b;
+                ++e;
+            }
+        }
+    } else if (cnt) {
+        uint64_t u = und;
+        while (u) {
+            int b = __ffsll((unsigned long long)u) - 1;
+            u &= u - 1;
+            if (decide_tail(dp, site0 + (uint32_t)b, class_at(c, n1, n2, b)))
+                lt |= 1ull << b;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum of N int64 values, result valid in thread 0.  `red` must hold
+// N * (blockDim.x / 64) entries.
+template <int N>
+__device__ __forceinline__ void block_sum_i64(int64_t (&v)[N], int64_t* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        v[i] = wave_sum_i64(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            red[i * nw + wave] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int64_t s = 0;
+            for (int w = 0; w < nw; ++w)
+                s += red[i * nw + w];
+            v[i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Fast division by a launch-constant divisor d >= 1 (n < 2^32):
+// q = (umulhi(n, mul) + n) >> shift  when add = 1, else umulhi(n, mul) >> shift.
+struct FastDiv {
+    uint32_t d, mul, shift, add;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    uint32_t hi = __umulhi(n, f.mul);
+    if (f.add)
+        return (uint32_t)(((uint64_t)hi + n) >> f.shift);
+    return hi >> f.shift;
+}
+
+}  // namespace sd

@@ -1,0 +1,60 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sd_device.hpp"
+
+namespace sd {
+
+// Kernel-side lattice layouts.  P64 and P32 are the same bytes (bit s of the
+// lattice is bit s % 64 of 64-bit word s / 64); they differ in the word width
+// the kernel works in.  I8Row is the int8 layout when every row is a whole
+// number of 64-site groups (L % 64 == 0); I8Any handles any L >= 2.
+enum KernelLayout : int { kLayP64 = 0, kLayP32 = 1, kLayI8Row = 2, kLayI8Any = 3 };
+
+constexpr uint32_t kMaxBlocks = 2048;
+
+struct Geom {
+    uint32_t L;
+    uint32_t n_sites;     // L * L
+    uint32_t n_groups;    // ceil(n_sites / 64)
+    uint32_t words_row;   // P64: L/64; P32: L/32; I8Row: L/64; I8Any: unused
+    FastDiv div_row;      // division by words_row
+    FastDiv div_L;        // division by L
+};
+
+// Granlund-Montgomery constants for division by d (1 <= d < 2^32).
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d)
+        ++l;
+    uint64_t m = (((1ull << 32) * ((1ull << l) - d)) / d) + 1ull;
+    f.d = d;
+    f.mul = (uint32_t)m;
+    f.shift = l;
+    f.add = 1;
+    return f;
+}
+
+inline uint32_t fdiv_host(uint32_t n, const FastDiv& f) {
+    uint32_t hi = (uint32_t)(((uint64_t)n * f.mul) >> 32);
+    return (uint32_t)(((uint64_t)hi + n) >> f.shift);
+}
+
+hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
+                            int64_t* obs, hipStream_t st);
+hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
+                       hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);
+
+// Observables of a pair and the row correlation, for any layout.
+hipError_t launch_observe(int layout, const void* sigma, const void* tau, const Geom& G, int64_t* out3,
+                          hipStream_t st);
+hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
+                           hipStream_t st);
+
+}  // namespace sd

@@ -1,0 +1,14 @@
+// Internal interface of the log-likelihood kernels.
+#pragma once
+
+#include "sd_kernels.hpp"
+
+namespace sd {
+
+hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_lat, uint32_t L, int64_t* counts12,
+                                hipStream_t st);
+hipError_t launch_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, hipStream_t st);
+hipError_t launch_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
+                             hipStream_t st);
+
+}  // namespace sd

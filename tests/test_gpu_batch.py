@@ -1,0 +1,136 @@
+"""GPU parity of the batched persistent scan and of the single-workgroup LDS
+path of sd_run: every chain bit-identical to the oracle and to sd_run."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1908_07341_amd as sd
+from paper_1908_07341_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SEED = 77
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.lib()
+    p = torch.cuda.get_device_properties(0)
+    print(f"device {p.name} CUs={p.multi_processor_count}", flush=True)
+
+
+def _unpack(buf, off, L, layout):
+    n = sd.sd_lattice_bytes(L, layout)
+    raw = buf[off:off + n].cpu().numpy()
+    if layout == sd.SD_I8:
+        return raw.view(np.int8).reshape(L, L)
+    return inputs.unpack_bits(raw, L)
+
+
+def _chains(n, sizes, seed=3):
+    rng = np.random.default_rng(seed)
+    J = rng.uniform(0.0, 1.5, n)
+    q = rng.uniform(0.0, 2.0, n)
+    L = rng.choice(np.asarray(sizes), n)
+    streams = rng.permutation(1000)[:n]
+    return J, q, L, streams
+
+
+@pytest.mark.parametrize("layout", [sd.SD_P64, sd.SD_I8])
+def test_batch_matches_oracle(oracle, layout):
+    J, q, L, st = _chains(12, [64, 128, 192])
+    k, every = 30, 3
+    plan = sd.sd_batch_plan_create(J, q, L, st, layout=layout, seed=SEED, k_steps=k, obs_every=every)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    tr = torch.full((sd.sd_batch_trace_len(plan),), -5, dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+    print("batch run", layout, flush=True)
+    sd.sd_batch_run(plan, lat, tr, 5)
+    torch.cuda.synchronize()
+    trh = tr.cpu().numpy().reshape(len(J), k // every, 3)
+    for c in range(len(J)):
+        s0 = oracle.init(int(L[c]), oracle.INIT_RANDOM, 0.5, SEED, int(st[c]))
+        rs, rt, ro = oracle.run(s0, J[c], q[c], SEED, int(st[c]), 5, k, obs_every=every)
+        assert np.array_equal(_unpack(lat, sd.sd_batch_chain_offset(plan, c, 0), int(L[c]), layout), rs), c
+        assert np.array_equal(_unpack(lat, sd.sd_batch_chain_offset(plan, c, 1), int(L[c]), layout), rt), c
+        assert np.array_equal(trh[c], ro), c
+    plan.close()
+
+
+def test_batch_equals_plain_runs_and_graph_reuse():
+    J, q, L, st = _chains(40, [128, 256, 512], seed=9)
+    k = 25
+    plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=k, obs_every=1)
+    for b in range(3):
+        print("bucket", b, sd.sd_batch_launch_shape(plan, b), flush=True)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    tr = torch.zeros(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+    plain = lat.clone()
+    plain_tr = torch.zeros_like(tr).view(len(J), k, 3)
+    # two graph launches with different step0, then the same again (graph reuse)
+    sd.sd_batch_run(plan, lat, tr, 0)
+    tr0 = tr.clone()
+    sd.sd_batch_run(plan, lat, tr, k)
+    tr1 = tr.clone()
+    torch.cuda.synchronize()
+    for c in range(len(J)):
+        Lc = int(L[c])
+        nb = sd.sd_lattice_bytes(Lc, sd.SD_P64)
+        so, to = sd.sd_batch_chain_offset(plan, c, 0), sd.sd_batch_chain_offset(plan, c, 1)
+        sig = plain[so:so + nb].view(torch.int64)
+        tau = plain[to:to + nb].view(torch.int64)
+        obs_a = torch.zeros((k, 3), dtype=torch.int64, device="cuda")
+        obs_b = torch.zeros((k, 3), dtype=torch.int64, device="cuda")
+        sd.sd_run(sig, tau, Lc, sd.SD_P64, J[c], q[c], SEED, int(st[c]), 0, k, obs_a, 1)
+        sd.sd_run(sig, tau, Lc, sd.SD_P64, J[c], q[c], SEED, int(st[c]), k, k, obs_b, 1)
+        assert torch.equal(obs_a, tr0.view(len(J), k, 3)[c]), c
+        assert torch.equal(obs_b, tr1.view(len(J), k, 3)[c]), c
+    torch.cuda.synchronize()
+    assert torch.equal(plain, lat)
+    # direct (non-graph) enqueue gives the same
+    lat2 = lat.clone()
+    sd.sd_batch_run_direct(plan, lat2, tr, 2 * k)
+    sd.sd_batch_run(plan, lat, tr1, 2 * k)
+    torch.cuda.synchronize()
+    assert torch.equal(lat2, lat) and torch.equal(tr, tr1)
+    plan.close()
+
+
+def test_batch_autotune_cache(tmp_path):
+    J, q, L, st = _chains(64, [128, 256], seed=4)
+    path = str(tmp_path / "tune.json")
+    plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=4, obs_every=1, tune_cache_path=path)
+    shapes = [sd.sd_batch_launch_shape(plan, b) for b in range(2)]
+    print("tuned", shapes, open(path).read(), flush=True)
+    plan.close()
+    plan2 = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=4, obs_every=1, tune_cache_path=path)
+    assert [sd.sd_batch_launch_shape(plan2, b) for b in range(2)] == shapes
+    plan2.close()
+
+
+@pytest.mark.parametrize("L", [64, 128, 256])
+def test_lds_and_global_paths_agree(L):
+    J, q, k = 0.55, 0.45, 60
+    s0 = inputs.random_lattice(L, L)
+    outs = []
+    for flags in (0, sd.SD_FLAG_GLOBAL_KERNELS):
+        for layout in (sd.SD_P64, sd.SD_I8):
+            sig = sd.new_lattice(L, layout)
+            if layout == sd.SD_I8:
+                sig.copy_(torch.from_numpy(s0))
+            else:
+                sig.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(s0)))
+            tau = sd.new_lattice(L, layout)
+            obs = torch.zeros((k, 3), dtype=torch.int64, device="cuda")
+            sd.sd_run(sig, tau, L, layout, J, q, SEED, 3, 11, k, obs, 1, flags)
+            torch.cuda.synchronize()
+            if layout == sd.SD_I8:
+                got = (sig.cpu().numpy(), tau.cpu().numpy())
+            else:
+                got = (inputs.unpack_bits(sig.cpu().numpy(), L), inputs.unpack_bits(tau.cpu().numpy(), L))
+            outs.append((got[0], got[1], obs.cpu().numpy()))
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(outs[0], o))
