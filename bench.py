@@ -1,0 +1,303 @@
+"""Benchmark of the shaken-dynamics hot path on one MI355X.
+
+Headline (`value`): spin updates per ns of one chain on a 16384 x 16384 torus,
+bit-packed 64 spins per word, random start, J = q = 0.5, observables (M, A, B)
+recorded every 10 steps.  One step = two half-steps = 2 L^2 spin updates.
+W untimed warm-up steps are followed by exactly K timed steps.
+
+Also reported on the same JSON line:
+  roofline      - the half-step kernel against the VALU peak it is bound by
+  cpu_baseline  - the CPU oracle (single thread) on a bounded sample of the
+                  same workload
+  batched_scan  - 4096 chains, (q, J) on a 64 x 64 grid, L in {128, 256, 512},
+                  5000 steps, (M, A, B) every step: one hipGraph launch vs the
+                  same chains run one sd_run each (timed on a sample)
+  loglik        - 256 trajectories of 256^2 lattices, 2000 steps at
+                  (J, q) = (0.45, 0.7): count kernel bandwidth and FP32
+                  gradient error against FP64
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spin updates/ns (1 GPU, L=16384 packed) + batched-scan chain-steps/s vs plain"
+
+# MI355X unit counts used for the ALU roofline: 256 CUs x 4 SIMDs x 16 lanes at
+# 2.4 GHz issue 39.32e12 32-bit VALU lane operations per second.
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+# Algorithmic VALU operations per spin update of the half-step:
+# Philox4x32-10 work of the stream contract, 4 calls per 64 sites plus one tail
+# call per 256 sites, 10 rounds of 2 multiplies + 2 three-way XORs each, and
+# the bit-sliced comparison, 8 planes x (1 select + 3 updates) per 32 sites.
+PHILOX_CALLS_PER_SITE = 4.0 / 64.0 + 1.0 / 256.0
+OPS_PER_SPIN_UPDATE = PHILOX_CALLS_PER_SITE * 10 * 4 + 8 * 4 / 32.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--L", type=int, default=16384)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-scan leg")
+    p.add_argument("--no-loglik", action="store_true", help="skip the log-likelihood leg")
+    p.add_argument("--batch-steps", type=int, default=5000)
+    p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
+    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
+    return p.parse_args()
+
+
+def bench_single(sd, torch, L, K, W):
+    J = q = 0.5
+    obs_every = 10
+    sigma = sd.new_lattice(L, sd.SD_P64)
+    tau = sd.new_lattice(L, sd.SD_P64)
+    sd.sd_init(sigma, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, 0)
+    if W:
+        sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, 0, W, None, 0)
+    obs = torch.zeros((max(K // obs_every, 1), 3), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, W, K, obs, obs_every)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    m = obs[-1, 0].item() / (L * L)
+    # per-launch duration of the half-step kernel: the same K steps of launches,
+    # timed again without observables so that only the two half-step kernels run
+    e2 = torch.cuda.Event(enable_timing=True)
+    e3 = torch.cuda.Event(enable_timing=True)
+    reps = min(K, 200)
+    e2.record(stream)
+    sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, W + K, reps, None, 0)
+    e3.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e2.elapsed_time(e3) / (2 * reps)
+    return dict(wall_s=wall, event_ms=ev_ms, launch_ms=launch_ms, m_final=m)
+
+
+def bench_cpu(L, n_steps):
+    from oracle import oracle as orc
+    orc.build(force=False)
+    s0 = orc.init(L, orc.INIT_RANDOM, 0.5, 1, 0)
+    t0 = time.perf_counter()
+    orc.run(s0, 0.5, 0.5, 1, 0, 0, n_steps)
+    dt = time.perf_counter() - t0
+    ups = 2.0 * L * L * n_steps / dt
+    return {"value": ups / 1e9, "unit": "spin updates/ns", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} full step(s) of the {L}x{L} chain (J=q=0.5, random start) on one host core "
+                      f"in {dt:.1f} s", "seconds": dt}
+
+
+def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
+    qv, Jv, Lv = inputs.scan_table()
+    n = len(qv)
+    streams = np.arange(n, dtype=np.uint32)
+    seed = 1
+    t_plan = time.perf_counter()
+    plan = sd.sd_batch_plan_create(Jv, qv, Lv, streams, layout=sd.SD_P64, seed=seed, k_steps=K, obs_every=1,
+                                   tune_cache_path=tune_cache)
+    t_plan = time.perf_counter() - t_plan
+    shapes = []
+    b = 0
+    while True:
+        try:
+            shapes.append(sd.sd_batch_launch_shape(plan, b))
+        except sd.ShakenError:
+            break
+        b += 1
+    lat = torch.empty(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    traces = torch.empty(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+    start = lat.clone()
+    torch.cuda.synchronize()
+    # first launch captures and instantiates the graph (untimed), the second is timed
+    sd.sd_batch_run(plan, lat, traces, 0)
+    torch.cuda.synchronize()
+    lat.copy_(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sd.sd_batch_run(plan, lat, traces, 0)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batch_rate = n * K / t_batch
+    # plain: the same chains, one sd_run each, on a sample covering every size
+    rng = np.random.default_rng(0)
+    sample = []
+    for size in sorted(set(Lv.tolist())):
+        idx = np.flatnonzero(Lv == size)
+        sample += rng.choice(idx, size=min(plain_sample // 3, len(idx)), replace=False).tolist()
+    sample_cost = 0.0
+    identical = True
+    t_plain = 0.0
+    for c in sample:
+        Lc = int(Lv[c])
+        nb = sd.sd_lattice_bytes(Lc, sd.SD_P64)
+        so, to = sd.sd_batch_chain_offset(plan, c, 0), sd.sd_batch_chain_offset(plan, c, 1)
+        sig = start[so:so + nb].clone().view(torch.int64)
+        tau = torch.empty_like(sig)
+        obs = torch.empty((K, 3), dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sd.sd_run(sig, tau, Lc, sd.SD_P64, float(Jv[c]), float(qv[c]), seed, int(streams[c]), 0, K, obs, 1)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        sample_cost += Lc * Lc
+        identical &= bool(torch.equal(sig, lat[so:so + nb].view(torch.int64)))
+        identical &= bool(torch.equal(obs.view(-1), traces.view(n, K * 3)[c]))
+    # scale the sample's time to the whole batch by lattice area
+    total_cost = float((Lv.astype(np.float64) ** 2).sum())
+    plain_est = t_plain * total_cost / sample_cost
+    plain_rate = n * K / plain_est
+    plan.close()
+    return {
+        "workload": f"{n} chains, q in [0,2] x J in [0,1.5] on a 64x64 grid, L from {{128,256,512}} "
+                    f"(numpy default_rng(1)), packed-64, random starts, {K} steps, (M,A,B) every step",
+        "chain_steps_per_s": batch_rate, "seconds": t_batch,
+        "plain_chain_steps_per_s": plain_rate, "plain_seconds_estimated": plain_est,
+        "plain_sample_chains": len(sample), "plain_sample_seconds": t_plain,
+        "speedup_vs_plain": batch_rate / plain_rate, "bit_identical_on_sample": identical,
+        "spin_updates_per_ns": 2.0 * float((Lv.astype(np.float64) ** 2).sum()) * K / t_batch / 1e9,
+        "plan_seconds": t_plan, "launch_shapes": [list(s) for s in shapes],
+    }
+
+
+def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
+    from paper_1908_07341_amd import autograd as AG
+    J, q = 0.45, 0.7
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    n_lat = 2 * k + 1
+    traj = torch.empty((n_traj, n_lat, nb // 8), dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    for a in range(n_traj):
+        s0 = traj[a, 0]
+        sd.sd_init(s0, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, a)
+        sd.sd_trajectory(s0, traj[a], L, sd.SD_P64, J, q, 1, a, 0, k)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    counts = torch.empty(12, dtype=torch.int64, device="cuda")
+    sd.sd_loglik_counts(traj, n_traj, n_lat, L, counts)   # warm-up
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        sd.sd_loglik_counts(traj, n_traj, n_lat, L, counts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = traj.numel() * 8 / (ms * 1e-3) / 1e9
+    # gradient at the ascent start, against FP64 from the same integer counts
+    Jq = torch.tensor([0.2, 0.2], dtype=torch.float32, device="cuda", requires_grad=True)
+    ll = AG.loglik(Jq, counts)
+    (g,) = torch.autograd.grad(ll, Jq)
+    ch = counts.cpu().numpy()
+    g64 = _fp64_grad(ch, 0.2, 0.2)
+    rel = float(np.max(np.abs(g.cpu().numpy().astype(np.float64) - g64) / np.abs(g64)))
+    # gradient ascent on LL / N from (0.2, 0.2)
+    N = float(ch.sum())
+    x = torch.tensor([0.2, 0.2], dtype=torch.float32, device="cuda", requires_grad=True)
+    for _ in range(300):
+        (gg,) = torch.autograd.grad(AG.loglik(x, counts) / N, x)
+        with torch.no_grad():
+            x += 0.5 * gg
+    est = x.detach().cpu().numpy().tolist()
+    del traj
+    return {"workload": f"{n_traj} trajectories of {L}x{L}, {k} steps at (J,q)=({J},{q}), random starts",
+            "transitions": int(N), "trajectory_GB": n_traj * n_lat * nb / 1e9, "generate_seconds": t_gen,
+            "counts_ms": ms, "counts_GBps": gbs, "counts_hbm_frac": gbs / HBM_PEAK_GBS,
+            "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est}
+
+
+def _fp64_grad(c, J, q):
+    gJ = gq = 0.0
+    for k in range(3):
+        for cp in range(2):
+            a, b = 2 * k - 2, 2 * cp - 1
+            h = float(np.float32(J)) * a + float(np.float32(q)) * b
+            d = float(c[2 * (2 * k + cp) + 1] - c[2 * (2 * k + cp)])
+            N = float(c[2 * (2 * k + cp) + 1] + c[2 * (2 * k + cp)])
+            gJ += a * (d - N * math.tanh(h))
+            gq += b * (d - N * math.tanh(h))
+    return np.array([gJ, gq])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the shaken-dynamics path here is "
+                                   "built and measured for a single MI355X (see DESIGN.md for how it would "
+                                   "shard)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1908_07341_amd as sd
+    from paper_1908_07341_amd import inputs
+    sd.lib()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    L, K, W = args.L, args.steps, args.warmup
+    log(f"[bench] single chain L={L} K={K} W={W}")
+    r = bench_single(sd, torch, L, K, W)
+    updates = 2.0 * L * L * K
+    value = updates / (r["wall_s"] * 1e9)
+    log(f"[bench] {value:.1f} spin updates/ns; half-step launch {r['launch_ms']*1e3:.1f} us")
+    per_launch_updates = L * L
+    achieved = OPS_PER_SPIN_UPDATE * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "spin updates/ns", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": r["wall_s"] * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"single chain {L}x{L} periodic, bit-packed 64 spins/word, random start (p=0.5), "
+                               f"J=0.5, q=0.5, observables (M,A,B) every 10 steps",
+                   "L": L, "layout": "P64", "J": 0.5, "q": 0.5, "obs_every": 10, "seed": 1},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_half_step (P64)", "launch_us": r["launch_ms"] * 1e3,
+                     "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
+                     "hbm_algorithmic_GBps": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9,
+                     "hbm_frac": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "m_final": r["m_final"],
+    }
+    if not args.no_batch:
+        log(f"[bench] batched scan, {args.batch_steps} steps")
+        out["batched_scan"] = bench_batched(sd, torch, inputs, args.batch_steps, args.plain_sample, args.tune_cache)
+        log(f"[bench] batched {out['batched_scan']['chain_steps_per_s']:.3g} chain-steps/s, "
+            f"x{out['batched_scan']['speedup_vs_plain']:.1f} vs plain")
+    if not args.no_loglik:
+        log("[bench] log-likelihood")
+        out["loglik"] = bench_loglik(sd, torch)
+        log(f"[bench] counts {out['loglik']['counts_GBps']:.0f} GB/s")
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle, {args.cpu_steps} step(s) at L={L}")
+        out["cpu_baseline"] = bench_cpu(L, args.cpu_steps)
+        log(f"[bench] CPU {out['cpu_baseline']['value']:.4f} spin updates/ns")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

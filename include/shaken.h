@@ -242,7 +242,7 @@ SD_API sd_status sd_batch_init(sd_batch_plan* plan, void* lattices, int32_t kind
  * seed, stream, step0 and k_steps, and its trace rows equal sd_run's obs rows.
  * lattices (device, 16-byte aligned) and traces (device, or NULL when the plan
  * records nothing) follow the plan's layout.  The graph is captured on the
- * first call and reused while (lattices, traces, step0, stream) stay the same.
+ * first call and reused while (lattices, traces, step0) stay the same.
  */
 SD_API sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0,
                               void* hip_stream);

@@ -42,7 +42,7 @@ struct sd_batch_plan {
     void* g_lattices = nullptr;
     int64_t* g_traces = nullptr;
     uint64_t g_step0 = 0;
-    hipStream_t g_stream = nullptr;
+    hipStream_t capture = nullptr;   // stream the graph is captured on
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> events;
 };
@@ -199,7 +199,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_c
             }
             return best_ms / 1e3;
         };
-        best = tune_pick({128, 256, 512, 1024}, measure);
+        best = tune_pick({128, 256, 512}, measure);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -223,6 +223,7 @@ hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_
     std::memset(&a, 0, sizeof a);
     a.counter = nullptr;
     threshold_table(J, q, a.single.T);
+    a.single.paired = thresholds_paired(a.single.T) ? 1u : 0u;
     a.single.L = (uint32_t)L;
     a.single.stream = stream;
     a.single.divW = make_fastdiv((uint32_t)L / 64u);
@@ -302,6 +303,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         }
         ChainDesc& d = p->descs[(size_t)c];
         threshold_table(in.J, in.q, d.T);
+        d.paired = thresholds_paired(d.T) ? 1u : 0u;
         d.L = (uint32_t)in.L;
         d.stream = in.stream;
         d.divW = make_fastdiv((uint32_t)in.L / 64u);
@@ -341,6 +343,8 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         e = hipMemcpy(p->d_descs, p->descs.data(), sizeof(ChainDesc) * p->descs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_order, order.data(), sizeof(uint32_t) * order.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     for (size_t b = 0; b < p->buckets.size() && e == hipSuccess; ++b) {
         hipStream_t s = nullptr;
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -424,14 +428,16 @@ sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uin
         return fail(SD_EINVAL, "sd_batch_run: lattices must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipSuccess;
-    if (!(plan->have_graph && plan->g_lattices == lattices && plan->g_traces == traces && plan->g_step0 == step0 &&
-          plan->g_stream == st)) {
+    if (!(plan->have_graph && plan->g_lattices == lattices && plan->g_traces == traces && plan->g_step0 == step0)) {
+        // capture on the plan's own stream (the caller's may be the legacy
+        // default stream, which cannot be captured); the graph is then
+        // launched on the caller's stream and ordered after its earlier work
         release_graph(plan);
-        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess)
             return hip_fail(e, "sd_batch_run: begin capture");
-        hipError_t ee = enqueue_batch(plan, lattices, traces, step0, st);
-        e = hipStreamEndCapture(st, &plan->graph);
+        hipError_t ee = enqueue_batch(plan, lattices, traces, step0, plan->capture);
+        e = hipStreamEndCapture(plan->capture, &plan->graph);
         if (ee != hipSuccess)
             e = ee;
         if (e == hipSuccess)
@@ -444,7 +450,6 @@ sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uin
         plan->g_lattices = lattices;
         plan->g_traces = traces;
         plan->g_step0 = step0;
-        plan->g_stream = st;
     }
     e = hipGraphLaunch(plan->exec, st);
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run: graph launch");
@@ -470,6 +475,8 @@ void sd_batch_plan_destroy(sd_batch_plan* plan) {
     release_graph(plan);
     for (hipStream_t s : plan->side)
         (void)hipStreamDestroy(s);
+    if (plan->capture)
+        (void)hipStreamDestroy(plan->capture);
     for (hipEvent_t ev : plan->events)
         (void)hipEventDestroy(ev);
     if (plan->d_descs)

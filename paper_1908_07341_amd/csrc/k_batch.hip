@@ -50,10 +50,11 @@ struct TailList {
     uint8_t* info;
     uint32_t cap;
     uint32_t* count;   // two counters, used alternately by consecutive half-steps
+    const uint32_t* T; // the chain's thresholds, in LDS
 };
 
 // One half-step of the workgroup's chain, src -> dst in LDS.
-template <int WHICH>
+template <int WHICH, bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams& dp, const PlaneMasks& pm,
                                               TailList& tl, uint32_t parity) {
     uint32_t* cnt = tl.count + parity;
@@ -64,7 +65,7 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams
             gather_lds<WHICH>(h, g, c, n1, n2);
             uint64_t P[8];
             draw_planes(dp, g, P);
-            WordDraw wd = compare_planes(P, c, n1, n2, pm, dp.rng_xor);
+            WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
             uint64_t lt = wd.lt;
             uint64_t u = wd.und;
             if (u) {
@@ -76,7 +77,7 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams
                     if (slot < tl.cap) {
                         tl.site[slot] = 64u * g + (uint32_t)b;
                         tl.info[slot] = (uint8_t)idx;
-                    } else if (decide_tail(dp, 64u * g + (uint32_t)b, idx)) {
+                    } else if (decide_tail_thr(dp, 64u * g + (uint32_t)b, tl.T[idx])) {
                         lt |= 1ull << b;
                     }
                     ++slot;
@@ -89,7 +90,7 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams
     const uint32_t total = *cnt < tl.cap ? *cnt : tl.cap;
     for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
         const uint32_t s = tl.site[e];
-        if (decide_tail(dp, s, tl.info[e]))
+        if (decide_tail_thr(dp, s, tl.T[tl.info[e]]))
             atomicOr(reinterpret_cast<unsigned long long*>(h.dst + (s >> 6)), 1ull << (s & 63u));
     }
     if (threadIdx.x == 0)
@@ -132,11 +133,30 @@ __device__ __forceinline__ uint32_t lds_bits4_to_bytes(uint32_t n) {
     return z | ((w << 8) - w);
 }
 
-__global__ __launch_bounds__(1024) void k_batch_chains(BatchArgs a) {
+template <bool PAIRED, bool COMPLEMENT>
+__device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA, const HalfCtx& hB, DrawParams dp,
+                                       const PlaneMasks& pm, TailList& tl, int64_t* trace, int64_t* red) {
+    uint32_t parity = 0;
+    for (uint32_t m = 0; m < a.k_steps; ++m) {
+        const uint32_t n = a.step0 + m;
+        dp.t = 2u * n;
+        lds_half_step<0, PAIRED, COMPLEMENT>(hA, dp, pm, tl, parity);
+        parity ^= 1u;
+        dp.t = 2u * n + 1u;
+        lds_half_step<1, PAIRED, COMPLEMENT>(hB, dp, pm, tl, parity);
+        parity ^= 1u;
+        if (trace && (m + 1) % a.obs_every == 0)
+            lds_observe(hB.dst, hA.dst, hA, trace + 3u * (size_t)((m + 1) / a.obs_every - 1), red);
+    }
+}
+
+template <bool COMPLEMENT>
+__global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t s_chain;
     __shared__ uint32_t s_count[2];
-    __shared__ int64_t red[3 * 16];
+    __shared__ uint32_t s_T[6];
+    __shared__ int64_t red[3 * 8];
     uint64_t* sig = smem;
     uint64_t* tau = smem + a.max_words;
     TailList tl;
@@ -144,6 +164,7 @@ __global__ __launch_bounds__(1024) void k_batch_chains(BatchArgs a) {
     tl.info = reinterpret_cast<uint8_t*>(tl.site + a.tail_cap);
     tl.cap = a.tail_cap;
     tl.count = s_count;
+    tl.T = s_T;
 
     for (uint32_t iter = 0;; ++iter) {
         ChainDesc cd;
@@ -193,6 +214,11 @@ __global__ __launch_bounds__(1024) void k_batch_chains(BatchArgs a) {
             s_count[0] = 0;
             s_count[1] = 0;
         }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                s_T[i] = cd.T[i];
+        }
         __syncthreads();
 
         DrawParams dp;
@@ -203,22 +229,14 @@ __global__ __launch_bounds__(1024) void k_batch_chains(BatchArgs a) {
         dp.key1 = a.key1;
         dp.stream = cd.stream;
         dp.tag2 = 0;
-        dp.rng_xor = a.rng_xor;
+        dp.rng_xor = COMPLEMENT ? 0xFFFFFFFFu : 0u;
         const PlaneMasks pm = make_plane_masks(dp);
         int64_t* trace = a.traces ? a.traces + cd.trace_offset : nullptr;
 
-        uint32_t parity = 0;
-        for (uint32_t m = 0; m < a.k_steps; ++m) {
-            const uint32_t n = a.step0 + m;
-            dp.t = 2u * n;
-            lds_half_step<0>(hA, dp, pm, tl, parity);
-            parity ^= 1u;
-            dp.t = 2u * n + 1u;
-            lds_half_step<1>(hB, dp, pm, tl, parity);
-            parity ^= 1u;
-            if (trace && (m + 1) % a.obs_every == 0)
-                lds_observe(sig, tau, hA, trace + 3u * (size_t)((m + 1) / a.obs_every - 1), red);
-        }
+        if (cd.paired)
+            run_steps<true, COMPLEMENT>(a, hA, hB, dp, pm, tl, trace, red);
+        else
+            run_steps<false, COMPLEMENT>(a, hA, hB, dp, pm, tl, trace, red);
 
         // write sigma and tau back
         if (a.int8_io) {
@@ -266,7 +284,10 @@ size_t batch_lds_bytes(uint32_t max_words, uint32_t tail_cap) {
 
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st) {
     const size_t lds = batch_lds_bytes(a.max_words, a.tail_cap);
-    hipLaunchKernelGGL(k_batch_chains, dim3(blocks), dim3(threads), lds, st, a);
+    if (a.rng_xor)
+        hipLaunchKernelGGL(k_batch_chains<true>, dim3(blocks), dim3(threads), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_batch_chains<false>, dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -276,12 +297,16 @@ hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st) {
 }
 
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_chains),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_chains<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
+    if (e != hipSuccess)
+        return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_chains<true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
 }
 
 hipError_t batch_occupancy(uint32_t threads, size_t lds, int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains, (int)threads, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false>, (int)threads, lds);
 }
 
 }  // namespace sd

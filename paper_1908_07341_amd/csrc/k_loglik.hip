@@ -24,6 +24,25 @@ namespace {
 // ---------------------------------------------------------------------------
 // Counts
 // ---------------------------------------------------------------------------
+// One lane per 64-site word g of one trajectory and a chunk of consecutive
+// transitions [m0, m1): every lattice of the chunk is read once from HBM by the
+// lane owning the word (the neighbour words come from the caches, since the
+// lanes of a workgroup walk the same lattices together).  kUnroll lattices are
+// loaded ahead so that several loads are in flight per lane.
+constexpr uint32_t kChunk = 64;
+constexpr int kUnroll = 4;
+
+__device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, int64_t (&acc)[12]) {
+    const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
+    const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const int64_t plus = __popcll(cls[i] & y);
+        acc[2 * i + 1] += plus;
+        acc[2 * i] += __popcll(cls[i]) - plus;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restrict__ traj, uint32_t n_traj,
                                                         uint32_t n_lat, uint32_t L, FastDiv divW,
                                                         unsigned long long* __restrict__ counts) {
@@ -33,11 +52,14 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
     const uint32_t blocks_per_traj = (n_words + blockDim.x - 1) / blockDim.x;
     const uint32_t a = blockIdx.x / blocks_per_traj;
     const uint32_t g = (blockIdx.x % blocks_per_traj) * blockDim.x + threadIdx.x;
+    const uint32_t m0 = blockIdx.y * kChunk;
+    const uint32_t n_trans = n_lat - 1;
+    const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     int64_t acc[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0;
-    if (a < n_traj && g < n_words) {
+    if (a < n_traj && g < n_words && m0 < m1) {
         const uint32_t j = fdiv(g, divW);
         const uint32_t w = g - j * W;
         const uint32_t down = (j == 0 ? L - 1 : j - 1) * W + w;
@@ -45,26 +67,34 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
         const uint32_t prev = j * W + (w == 0 ? W - 1 : w - 1);
         const uint32_t next = j * W + (w == W - 1 ? 0 : w + 1);
         const uint64_t* X = traj + (size_t)a * n_lat * n_words;
-        uint64_t c = X[g];
-        for (uint32_t m = 0; m + 1 < n_lat; ++m) {
+        uint64_t c = X[(size_t)m0 * n_words + g];
+        uint32_t m = m0;
+        for (; m + kUnroll <= m1; m += kUnroll) {
+            uint64_t y[kUnroll], nb1[kUnroll], nb2[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t* Xm = X + (size_t)(m + u) * n_words;
+                y[u] = Xm[n_words + g];
+                const bool even = ((m + u) & 1u) == 0;
+                nb1[u] = Xm[even ? down : up];
+                nb2[u] = Xm[even ? prev : next];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const bool even = ((m + u) & 1u) == 0;
+                const uint64_t n2 = even ? ((c << 1) | (nb2[u] >> 63)) : ((c >> 1) | (nb2[u] << 63));
+                count_transition(c, nb1[u], n2, y[u], acc);
+                c = y[u];
+            }
+        }
+        for (; m < m1; ++m) {
             const uint64_t* Xm = X + (size_t)m * n_words;
             const uint64_t y = Xm[n_words + g];
-            uint64_t n1, n2;
-            if ((m & 1u) == 0) {
-                n1 = Xm[down];
-                n2 = (c << 1) | (Xm[prev] >> 63);
-            } else {
-                n1 = Xm[up];
-                n2 = (c >> 1) | (Xm[next] << 63);
-            }
-            const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
-            const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                const int64_t plus = __popcll(cls[i] & y);
-                acc[2 * i + 1] += plus;
-                acc[2 * i] += __popcll(cls[i]) - plus;
-            }
+            const bool even = (m & 1u) == 0;
+            const uint64_t n1 = Xm[even ? down : up];
+            const uint64_t w2 = Xm[even ? prev : next];
+            const uint64_t n2 = even ? ((c << 1) | (w2 >> 63)) : ((c >> 1) | (w2 << 63));
+            count_transition(c, n1, n2, y, acc);
             c = y;
         }
     }
@@ -240,9 +270,13 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     const uint32_t n_words = L * (L / 64u);
     const uint32_t bpt = (n_words + 255u) / 256u;
     const uint64_t blocks = (uint64_t)bpt * n_traj;
-    if (blocks == 0)
+    const uint32_t chunks = (n_lat - 1 + kChunk - 1) / kChunk;
+    if (blocks == 0 || chunks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st, static_cast<const uint64_t*>(traj),
+    if (blocks > 0x7FFFFFFFull || chunks > 65535u)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks, chunks), dim3(256), 0, st,
+                       static_cast<const uint64_t*>(traj),
                        n_traj, n_lat, L, make_fastdiv(L / 64u), reinterpret_cast<unsigned long long*>(counts12));
     return hipGetLastError();
 }

@@ -168,7 +168,7 @@ __device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, ui
 // One half-step.  obs (half-step B only, may be null) receives the observable
 // contributions of the written pair through 64-bit atomics; it must hold
 // zeros (or earlier partial sums of the same record) before the launch.
-template <int LAYOUT, int WHICH>
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT>
 __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
                                                    DrawParams dp, int64_t* __restrict__ obs) {
     __shared__ TailScratch<kTailCap> tails;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
             gather<LAYOUT, WHICH>(src, G, g, c, n1, n2, valid);
         uint64_t P[8];
         draw_planes(dp, active ? g : 0u, P);
-        WordDraw wd = compare_planes(P, c, n1, n2, pm, dp.rng_xor);
+        WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
         uint64_t lt = wd.lt;
         resolve_tails<kTailCap>(lt, wd.und & valid, c, n1, n2, 64u * g, dp, tails);
         if (active) {
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_init_random(void* __restrict__ dst, Geo
         }
         uint64_t P[8];
         draw_planes(dp, active ? g : 0u, P);
-        WordDraw wd = compare_planes(P, 0, 0, 0, pm, dp.rng_xor);
+        WordDraw wd = compare_planes<false, false>(P, 0, 0, 0, pm);
         uint64_t lt = wd.lt;
         resolve_tails<kTailCap>(lt, wd.und & valid, 0, 0, 0, 64u * g, dp, tails);
         if (active)
@@ -261,15 +261,30 @@ uint32_t grid_for(uint32_t n_groups) {
 
 }  // namespace
 
+template <int LAY, int WHICH>
+void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, hipStream_t st, const void* src,
+                           void* dst, const Geom& G, const DrawParams& dp, int64_t* obs) {
+    if (paired && !complement)
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false>), grid, block, 0, st, src, dst, G, dp, obs);
+    else if (paired)
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true>), grid, block, 0, st, src, dst, G, dp, obs);
+    else if (!complement)
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false>), grid, block, 0, st, src, dst, G, dp, obs);
+    else
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true>), grid, block, 0, st, src, dst, G, dp, obs);
+}
+
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
                             int64_t* obs, hipStream_t st) {
     const dim3 grid(grid_for(G.n_groups)), block(256);
-#define SD_HALF(LAY)                                                                                  \
-    case LAY:                                                                                         \
-        if (which == 0)                                                                               \
-            hipLaunchKernelGGL((k_half_step<LAY, 0>), grid, block, 0, st, src, dst, G, dp, nullptr); \
-        else                                                                                          \
-            hipLaunchKernelGGL((k_half_step<LAY, 1>), grid, block, 0, st, src, dst, G, dp, obs);     \
+    const bool paired = thresholds_paired(dp.T);
+    const bool complement = dp.rng_xor != 0;
+#define SD_HALF(LAY)                                                                                       \
+    case LAY:                                                                                              \
+        if (which == 0)                                                                                    \
+            launch_half_step_mode<LAY, 0>(paired, complement, grid, block, st, src, dst, G, dp, nullptr); \
+        else                                                                                               \
+            launch_half_step_mode<LAY, 1>(paired, complement, grid, block, st, src, dst, G, dp, obs);     \
         break;
     switch (layout) {
         SD_HALF(kLayP64)

@@ -10,6 +10,7 @@ struct ChainDesc {
     uint32_t T[6];          // threshold table of this chain's (J, q)
     uint32_t L;             // lattice size, L % 64 == 0
     uint32_t stream;        // stream id of the chain's randomness
+    uint32_t paired;        // thresholds_paired(T): the compare may use the paired form
     FastDiv divW;           // division by L / 64
     uint64_t sig_offset;    // sigma, in bytes from the lattices base
     uint64_t tau_offset;    // tau, in bytes from the lattices base

@@ -153,6 +153,10 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 
 // Threshold bits of the eight planes as all-ones / all-zeros masks, one per
 // (plane m, class idx): S[m][idx] = ~0 iff bit (31 - m) of T[idx] is set.
+// Classes idx and 5 - idx have opposite fields (k -> 2 - k, c -> -c), so
+// T[5 - idx] = 2^32 - T[idx]; when no T[idx] has its low 24 bits all zero the
+// top bytes of the pair are bitwise complements and only the three "leader"
+// classes 0, 1, 2 are needed (paired form, see compare_planes_32).
 struct PlaneMasks {
     uint32_t S[8][6];
 };
@@ -167,31 +171,61 @@ __device__ __forceinline__ PlaneMasks make_plane_masks(const DrawParams& dp) {
     return pm;
 }
 
+// True when every class pair (idx, 5 - idx) has complementary top bytes, i.e.
+// no threshold has its low 24 bits all zero (host-side check).
+inline bool thresholds_paired(const uint32_t T[6]) {
+    for (int i = 0; i < 6; ++i)
+        if ((T[i] & 0xFFFFFFu) == 0u)
+            return false;
+    return true;
+}
+
 // Bit-sliced comparison of the top 8 bits of every r_s in a 32-site half word
 // against the per-site thresholds.  n1, n2 are the two J-neighbour bits and c
 // the partner bit of each site (bit 1 = spin +1).  Returns in lt the sites
 // already known to satisfy r < T and in und those whose top byte equals the
-// threshold's top byte.
+// threshold's top byte.  COMPLEMENT replaces every r by its complement.
+//
+// Paired form: with Q0 = (n1 == n2 == c) (classes 0 and 5), Q2 = n1 ^ n2
+// (classes 2 and 3) and the rest (classes 1 and 4), and nl = majority(n1, n2, c)
+// marking the classes 3, 4, 5, the threshold bit of plane m is
+//   nl ^ (Q2 ? S[m][2] : Q0 ? S[m][0] : S[m][1]).
+// General form: the union of the class masks whose threshold bit is set.
 struct HalfWord {
     uint32_t lt, und;
 };
 
-__device__ __forceinline__ HalfWord compare_planes_32(const uint32_t P[8], uint32_t c, uint32_t n1,
-                                                      uint32_t n2, const PlaneMasks& pm, uint32_t rng_xor) {
-    const uint32_t k2 = n1 & n2;
-    const uint32_t k1 = n1 ^ n2;
-    const uint32_t k0 = ~(n1 | n2);
-    const uint32_t m0 = k0 & ~c, m1 = k0 & c;
-    const uint32_t m2 = k1 & ~c, m3 = k1 & c;
-    const uint32_t m4 = k2 & ~c, m5 = k2 & c;
+template <bool PAIRED, bool COMPLEMENT>
+__device__ __forceinline__ HalfWord compare_planes_32(const uint32_t P[8], uint32_t c, uint32_t n1, uint32_t n2,
+                                                      const PlaneMasks& pm) {
     uint32_t lt = 0, und = ~0u;
+    if constexpr (PAIRED) {
+        const uint32_t q0 = ~((n1 ^ c) | (n2 ^ c));
+        const uint32_t q2 = n1 ^ n2;
+        const uint32_t nl = (n1 & n2) | (c & (n1 | n2));
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const uint32_t tb = (m0 & pm.S[m][0]) | (m1 & pm.S[m][1]) | (m2 & pm.S[m][2]) | (m3 & pm.S[m][3]) |
-                            (m4 & pm.S[m][4]) | (m5 & pm.S[m][5]);
-        const uint32_t r = P[m] ^ rng_xor;
-        lt |= und & tb & ~r;
-        und &= ~(r ^ tb);
+        for (int m = 0; m < 8; ++m) {
+            const uint32_t a = (q0 & pm.S[m][0]) | (~q0 & pm.S[m][1]);
+            const uint32_t tb = nl ^ ((q2 & pm.S[m][2]) | (~q2 & a));
+            const uint32_t r = COMPLEMENT ? ~P[m] : P[m];
+            lt |= und & tb & ~r;
+            und &= ~(r ^ tb);
+        }
+    } else {
+        const uint32_t k2 = n1 & n2;
+        const uint32_t k1 = n1 ^ n2;
+        const uint32_t k0 = ~(n1 | n2);
+        const uint32_t m0 = k0 & ~c, m1 = k0 & c;
+        const uint32_t m2 = k1 & ~c, m3 = k1 & c;
+        const uint32_t m4 = k2 & ~c, m5 = k2 & c;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const uint32_t tb = (m0 & pm.S[m][0]) | (m1 & pm.S[m][1]) | (m2 & pm.S[m][2]) |
+                                (m3 & pm.S[m][3]) | (m4 & pm.S[m][4]) | (m5 & pm.S[m][5]);
+            const uint32_t r = COMPLEMENT ? ~P[m] : P[m];
+            lt |= und & tb & ~r;
+            und &= ~(r ^ tb);
+        }
     }
     return {lt, und};
 }
@@ -200,17 +234,18 @@ struct WordDraw {
     uint64_t lt, und;
 };
 
+template <bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ WordDraw compare_planes(const uint64_t P[8], uint64_t c, uint64_t n1, uint64_t n2,
-                                                   const PlaneMasks& pm, uint32_t rng_xor) {
+                                                   const PlaneMasks& pm) {
     uint32_t Plo[8], Phi[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         Plo[m] = (uint32_t)P[m];
         Phi[m] = (uint32_t)(P[m] >> 32);
     }
-    HalfWord lo = compare_planes_32(Plo, (uint32_t)c, (uint32_t)n1, (uint32_t)n2, pm, rng_xor);
-    HalfWord hi = compare_planes_32(Phi, (uint32_t)(c >> 32), (uint32_t)(n1 >> 32), (uint32_t)(n2 >> 32), pm,
-                                    rng_xor);
+    HalfWord lo = compare_planes_32<PAIRED, COMPLEMENT>(Plo, (uint32_t)c, (uint32_t)n1, (uint32_t)n2, pm);
+    HalfWord hi = compare_planes_32<PAIRED, COMPLEMENT>(Phi, (uint32_t)(c >> 32), (uint32_t)(n1 >> 32),
+                                                        (uint32_t)(n2 >> 32), pm);
     return {(uint64_t)lo.lt | ((uint64_t)hi.lt << 32), (uint64_t)lo.und | ((uint64_t)hi.und << 32)};
 }
 
@@ -219,10 +254,14 @@ __device__ __forceinline__ uint32_t class_at(uint64_t c, uint64_t n1, uint64_t n
     return 2u * k + (uint32_t)((c >> b) & 1u);
 }
 
-// Decision of one undecided site: its top byte equals the threshold's, so
-// r < T iff the low 24 bits compare below.
+// Decision of one undecided site with threshold thr: its top byte equals the
+// threshold's, so r < thr iff the low 24 bits compare below.
+__device__ __forceinline__ bool decide_tail_thr(const DrawParams& dp, uint32_t s, uint32_t thr) {
+    return draw_tail24(dp, s) < (thr & 0xFFFFFFu);
+}
+
 __device__ __forceinline__ bool decide_tail(const DrawParams& dp, uint32_t s, uint32_t idx) {
-    return draw_tail24(dp, s) < (threshold_of(dp, idx) & 0xFFFFFFu);
+    return decide_tail_thr(dp, s, threshold_of(dp, idx));
 }
 
 // Workgroup-shared scratch for resolving undecided sites cooperatively.

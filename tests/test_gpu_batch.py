@@ -33,6 +33,10 @@ def _chains(n, sizes, seed=3):
     rng = np.random.default_rng(seed)
     J = rng.uniform(0.0, 1.5, n)
     q = rng.uniform(0.0, 2.0, n)
+    # two chains whose tables contain 2^31 exactly (h = 0 for some class):
+    # they take the general threshold form inside the batched kernel
+    J[0], q[0] = 0.25, 0.5
+    J[1], q[1] = 0.0, 0.0
     L = rng.choice(np.asarray(sizes), n)
     streams = rng.permutation(1000)[:n]
     return J, q, L, streams
