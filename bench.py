@@ -45,6 +45,49 @@ PHILOX_CALLS_PER_SITE = 4.0 / 64.0 + 1.0 / 256.0
 OPS_PER_SPIN_UPDATE = PHILOX_CALLS_PER_SITE * 10 * 4 + 8 * 4 / 32.0
 
 
+# Sources whose content determines the half-step kernel; a traffic figure from
+# hardware counters is reported only while their hash matches the one recorded
+# with the counters.
+KERNEL_SOURCES = ["paper_1908_07341_amd/csrc/k_update.hip", "paper_1908_07341_amd/csrc/sd_device.hpp",
+                  "paper_1908_07341_amd/csrc/sd_kernels.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_half_step_L16384_traffic.json")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per half-step launch from the committed counter summary, or
+    None when there is none or the kernel changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def calibrate_copy(torch, mib: int = 512) -> None:
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiling run."""
+    n = mib * 1024 * 1024
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {n} bytes")
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -62,6 +105,8 @@ def parse():
     p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run one 512 MiB device copy first (counter calibration runs)")
     return p.parse_args()
 
 
@@ -144,7 +189,10 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     batch_rate = n * K / t_batch
-    # plain: the same chains, one sd_run each, on a sample covering every size
+    # plain: the same chains, one sd_run each (with sd_run's launch choice tuned
+    # for each size), on a sample covering every size
+    for size in sorted(set(Lv.tolist())):
+        sd.sd_tune(int(size), sd.SD_P64, tune_cache)
     rng = np.random.default_rng(0)
     sample = []
     for size in sorted(set(Lv.tolist())):
@@ -182,6 +230,7 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
         "speedup_vs_plain": batch_rate / plain_rate, "bit_identical_on_sample": identical,
         "spin_updates_per_ns": 2.0 * float((Lv.astype(np.float64) ** 2).sum()) * K / t_batch / 1e9,
         "plan_seconds": t_plan, "launch_shapes": [list(s) for s in shapes],
+        "plain_run_choices": {int(z): list(sd.sd_tuned_choice(int(z), sd.SD_P64)) for z in sorted(set(Lv.tolist()))},
     }
 
 
@@ -260,6 +309,11 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     L, K, W = args.L, args.steps, args.warmup
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+    t0 = time.perf_counter()
+    sd.sd_tune(L, sd.SD_P64, args.tune_cache)
+    log(f"[bench] sd_tune L={L}: choice {sd.sd_tuned_choice(L, sd.SD_P64)} in {time.perf_counter() - t0:.2f} s")
     log(f"[bench] single chain L={L} K={K} W={W}")
     r = bench_single(sd, torch, L, K, W)
     updates = 2.0 * L * L * K
@@ -276,7 +330,7 @@ def main():
                                f"J=0.5, q=0.5, observables (M,A,B) every 10 steps",
                    "L": L, "layout": "P64", "J": 0.5, "q": 0.5, "obs_every": 10, "seed": 1},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(),
                      "kernel": "k_half_step (P64)", "launch_us": r["launch_ms"] * 1e3,
                      "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
                      "hbm_algorithmic_GBps": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9,

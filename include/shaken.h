@@ -126,6 +126,26 @@ SD_API sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, doubl
                  uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
                  uint32_t flags, void* hip_stream);
 
+/*
+ * Measure and fix how sd_run executes chains of this (L, layout) on the
+ * current device: the single-workgroup LDS-resident kernel (workgroup size
+ * 128/256/512, lattices up to the device's LDS) or one grid-wide launch per
+ * half-step (64- or 32-bit word kernels when L % 64 == 0 — the same bytes —
+ * and the number of workgroups).  Each candidate runs a few steps on scratch
+ * lattices (allocated and freed here) with HIP events; the fastest is used by
+ * every later sd_run of this process with these (L, layout) and stored under
+ * a "run:<arch>:L=..:layout=.." key in the JSON file tune_cache_path (NULL:
+ * not stored); a later sd_tune finding the key there takes it without
+ * measuring.  Synchronises the stream.  Results of sd_run do not depend on
+ * the choice.
+ */
+SD_API sd_status sd_tune(int32_t L, int32_t layout, const char* tune_cache_path, void* hip_stream);
+
+/* The choice sd_run currently uses for (L, layout): mode 0 = built-in rule,
+ * 1 = LDS kernel, 2 = grid kernels; word width; workgroups; workgroup size. */
+SD_API sd_status sd_tuned_choice(int32_t L, int32_t layout, int32_t* mode, int32_t* width, int32_t* blocks,
+                                 int32_t* threads);
+
 /* (M, A, B) of an arbitrary pair of device lattices into out3 (device, 3 int64). */
 SD_API sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,
                      void* hip_stream);

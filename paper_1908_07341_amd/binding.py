@@ -52,6 +52,9 @@ SIGNATURES = {
     "sd_loglik_counts": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "sd_tune": (_I32, [_I32, _I32, ctypes.c_char_p, _VP]),
+    "sd_tuned_choice": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                               ctypes.POINTER(_I32)]),
     "sd_debug_fastdiv": (_U32, [_U32, _U32]),
 }
 
@@ -225,6 +228,18 @@ def sd_batch_run_direct(plan: sd_batch_plan, lattices, traces, step0=0, hip_stre
 
 def sd_batch_plan_destroy(plan: sd_batch_plan) -> None:
     plan.close()
+
+
+def sd_tune(L: int, layout: int, tune_cache_path=None, hip_stream=None) -> None:
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().sd_tune(L, layout, path, _stream(hip_stream)))
+
+
+def sd_tuned_choice(L: int, layout: int):
+    """(mode, width, blocks, threads) that sd_run uses for (L, layout)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().sd_tuned_choice(L, layout, *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
 
 
 def sd_debug_fastdiv(n: int, d: int) -> int:

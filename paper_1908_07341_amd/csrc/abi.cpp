@@ -6,8 +6,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
+#include "sd_autotune.hpp"
 #include "sd_batch.hpp"
 #include "sd_host.hpp"
 #include "sd_kernels.hpp"
@@ -127,6 +132,38 @@ sd_status check_lattice(const void* p, int32_t L, int32_t layout, const char* na
     return SD_OK;
 }
 
+// Launch choice of sd_run for one (device, L, layout), set by sd_tune.
+struct RunChoice {
+    int mode = 0;           // 0: built-in rule, 1: single-workgroup LDS kernel, 2: grid kernels
+    int width = 64;         // packed layouts with L % 64 == 0: 64- or 32-bit word kernels
+    uint32_t blocks = 0;    // grid kernels: workgroups (0 = default)
+    uint32_t threads = 256; // LDS kernel: workgroup size
+};
+
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int32_t, int32_t>, RunChoice> g_run_choice;
+
+RunChoice run_choice(int32_t L, int32_t layout) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return RunChoice{};
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_run_choice.find(std::make_tuple(dev, L, layout));
+    return it == g_run_choice.end() ? RunChoice{} : it->second;
+}
+
+// Largest lattice (64-bit words) the single-workgroup LDS kernel may hold.
+uint32_t lds_max_words() {
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return kSingleLdsMaxWords;
+    uint32_t w = kSingleLdsMaxWords;
+    while (batch_lds_bytes(2 * w, 1024) <= (size_t)max_lds - 512)
+        w *= 2;
+    return w;
+}
+
 }  // namespace sd
 
 using namespace sd;
@@ -230,20 +267,24 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     if (overlap(sigma, tau, lattice_bytes(L, layout)))
         return fail(SD_EINVAL, "sd_run: sigma and tau overlap");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, sigma) == kLayI8Row &&
-                                           kernel_layout(L, layout, tau) == kLayI8Row)
-                                              ? kLayI8Row
-                                              : kLayI8Any)
-                                       : kernel_layout(L, layout, sigma);
+    int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, sigma) == kLayI8Row &&
+                                     kernel_layout(L, layout, tau) == kLayI8Row)
+                                        ? kLayI8Row
+                                        : kLayI8Any)
+                                 : kernel_layout(L, layout, sigma);
+    const RunChoice ch = run_choice(L, layout);
+    if (layout != SD_I8 && L % 64 == 0)
+        klay = ch.width == 32 ? kLayP32 : kLayP64;
     const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
     const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
+    const uint32_t lds_words = ch.mode == 1 ? lds_max_words() : kSingleLdsMaxWords;
     const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0)) &&
-                        n_words <= kSingleLdsMaxWords && !(flags & SD_FLAG_GLOBAL_KERNELS);
+                        n_words <= lds_words && ch.mode != 2 && !(flags & SD_FLAG_GLOBAL_KERNELS);
     if (lds_ok) {
         if (k_steps == 0)
             return SD_OK;
         hipError_t e = launch_single_chain_lds(sigma, tau, L, klay == kLayI8Row, J, q, seed, stream, step0, k_steps,
-                                               n_rec ? obs : nullptr, obs_every, flags, 256, st);
+                                               n_rec ? obs : nullptr, obs_every, flags, ch.threads, st);
         return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
     }
     const Geom G = make_geom(L, klay);
@@ -253,14 +294,14 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
         DrawParams dp = dynamics_params(J, q, seed, stream, (uint32_t)(2 * n), flags & SD_FLAG_COMPLEMENT_RNG);
-        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st);
+        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks);
         if (e != hipSuccess)
             break;
         dp.t = (uint32_t)(2 * n + 1);
         int64_t* rec = nullptr;
         if (n_rec && (m + 1) % obs_every == 0)
             rec = obs + 3u * (size_t)((m + 1) / obs_every - 1);
-        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st);
+        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks);
     }
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
 }
@@ -291,6 +332,129 @@ sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax
     const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
     hipError_t e = launch_corr_row(klay, sigma, make_geom(L, klay), rmax, out, static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
+}
+
+sd_status sd_tune(int32_t L, int32_t layout, const char* tune_cache_path, void* hip_stream) {
+    if (!layout_supported(L, layout))
+        return fail(SD_EINVAL, "sd_tune: unsupported (L=%d, layout=%d)", L, layout);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_tune");
+    const std::string key = "run:" + device_arch() + ":L=" + std::to_string(L) + ":layout=" + std::to_string(layout);
+    auto encode = [](const RunChoice& c) -> long {
+        return (long)c.mode | ((long)(c.width == 32) << 2) | ((long)c.blocks << 3) | ((long)(c.threads / 64) << 24);
+    };
+    auto decode = [](long v) {
+        RunChoice c;
+        c.mode = (int)(v & 3);
+        c.width = (v >> 2) & 1 ? 32 : 64;
+        c.blocks = (uint32_t)((v >> 3) & 0x1FFFFF);
+        c.threads = (uint32_t)(((v >> 24) & 0xFF) * 64);
+        if (c.threads == 0)
+            c.threads = 256;
+        return c;
+    };
+    const long cached = tune_cache_get(tune_cache_path, key);
+    if (cached > 0) {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_run_choice[std::make_tuple(dev, L, layout)] = decode(cached);
+        return SD_OK;
+    }
+    // candidates
+    std::vector<RunChoice> cands;
+    const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
+    const bool lds_layout = L % 64 == 0;
+    if (lds_layout && n_words <= lds_max_words())
+        for (uint32_t th : {128u, 256u, 512u}) {
+            RunChoice c;
+            c.mode = 1;
+            c.threads = th;
+            cands.push_back(c);
+        }
+    const uint32_t tiles = (uint32_t)((n_words + 1023u) / 1024u);
+    for (int width : {64, 32}) {
+        if (width == 32 && (layout == SD_I8 || L % 64 != 0))
+            continue;
+        for (uint32_t b : {256u, 512u, 1024u, 2048u, 4096u}) {
+            if (b > 2 * tiles && b != 256u)
+                continue;
+            RunChoice c;
+            c.mode = 2;
+            c.width = width;
+            c.blocks = b;
+            cands.push_back(c);
+        }
+    }
+    // scratch lattices, a short run per candidate
+    const size_t bytes = lattice_bytes(L, layout);
+    void* sig = nullptr;
+    void* tau = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    e = hipMalloc(&sig, bytes);
+    if (e == hipSuccess) e = hipMalloc(&tau, bytes);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    sd_status s = SD_OK;
+    if (e == hipSuccess)
+        s = sd_init(sig, L, layout, SD_INIT_RANDOM, 0.5, 1, 0, hip_stream);
+    const uint32_t k = n_words >= (1u << 20) ? 4u : (n_words >= 4096u ? 16u : 64u);
+    RunChoice best;
+    double best_t = -1.0;
+    for (const RunChoice& c : cands) {
+        if (e != hipSuccess || s != SD_OK)
+            break;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mutex);
+            g_run_choice[std::make_tuple(dev, L, layout)] = c;
+        }
+        float ms = -1.0f;
+        for (int rep = 0; rep < 2 && s == SD_OK; ++rep) {
+            e = hipEventRecord(e0, st);
+            if (e != hipSuccess) break;
+            s = sd_run(sig, tau, L, layout, 0.5, 0.5, 1, 0, 0, k, nullptr, 0, 0, hip_stream);
+            if (s != SD_OK) break;
+            e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess && s == SD_OK && ms > 0.0f && (best_t < 0.0 || ms < best_t)) {
+            best_t = ms;
+            best = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (sig) (void)hipFree(sig);
+    if (tau) (void)hipFree(tau);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        if (best_t > 0.0)
+            g_run_choice[std::make_tuple(dev, L, layout)] = best;
+        else
+            g_run_choice.erase(std::make_tuple(dev, L, layout));
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_tune");
+    if (s != SD_OK)
+        return s;
+    if (best_t > 0.0)
+        tune_cache_put(tune_cache_path, key, encode(best));
+    return SD_OK;
+}
+
+sd_status sd_tuned_choice(int32_t L, int32_t layout, int32_t* mode, int32_t* width, int32_t* blocks,
+                          int32_t* threads) {
+    if (!layout_supported(L, layout))
+        return fail(SD_EINVAL, "sd_tuned_choice: unsupported (L=%d, layout=%d)", L, layout);
+    const RunChoice c = run_choice(L, layout);
+    if (mode) *mode = c.mode;
+    if (width) *width = c.width;
+    if (blocks) *blocks = (int32_t)c.blocks;
+    if (threads) *threads = (int32_t)c.threads;
+    return SD_OK;
 }
 
 uint32_t sd_debug_fastdiv(uint32_t n, uint32_t d) {

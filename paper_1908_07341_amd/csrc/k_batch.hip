@@ -14,7 +14,8 @@
 // site in 256) are appended to an LDS list during the half-step, the decided
 // bits are written straight to the LDS lattice, and after one barrier the list
 // is resolved by the whole workgroup with LDS atomic ORs into the lattice.  A
-// lane whose entries would overflow the list resolves them itself.
+// lane whose entries would overflow the list resolves them itself before the
+// barrier.
 #include "sd_batch.hpp"
 
 namespace sd {
@@ -47,51 +48,99 @@ __device__ __forceinline__ void gather_lds(const HalfCtx& h, uint32_t g, uint64_
 
 struct TailList {
     uint32_t* site;
-    uint8_t* info;
     uint32_t cap;
     uint32_t* count;   // two counters, used alternately by consecutive half-steps
     const uint32_t* T; // the chain's thresholds, in LDS
 };
 
-// One half-step of the workgroup's chain, src -> dst in LDS.
+// Exclusive prefix sum of v across the wavefront and the wavefront total.
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v, uint32_t& total) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t incl = v;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += t;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+constexpr uint32_t kBatchWords = 4;   // words per thread between two slot reservations
+
+// One half-step of the workgroup's chain, src -> dst in LDS.  Each thread
+// handles its words kBatchWords at a time: draws and compares them, writes the
+// decided bits to dst and keeps the undecided masks; then the batch's
+// undecided sites get list slots (one LDS atomic per wavefront).  After a
+// barrier the list is resolved by the whole workgroup (the class of an entry
+// is read back from src) and decisions are or-ed into dst.
 template <int WHICH, bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams& dp, const PlaneMasks& pm,
                                               TailList& tl, uint32_t parity) {
     uint32_t* cnt = tl.count + parity;
-    for (uint32_t base = 0; base < h.n_words; base += blockDim.x) {
-        const uint32_t g = base + threadIdx.x;
-        if (g < h.n_words) {
-            uint64_t c, n1, n2;
-            gather_lds<WHICH>(h, g, c, n1, n2);
-            uint64_t P[8];
-            draw_planes(dp, g, P);
-            WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
-            uint64_t lt = wd.lt;
-            uint64_t u = wd.und;
-            if (u) {
-                uint32_t slot = atomicAdd(cnt, (uint32_t)__popcll(u));
+    const uint32_t span = kBatchWords * blockDim.x;
+    for (uint32_t base = 0; base < h.n_words; base += span) {
+        uint64_t und[kBatchWords];
+        uint32_t chain = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kBatchWords; ++k) {
+            uint32_t g = base + threadIdx.x + k * blockDim.x;
+            // one word at a time (see k_half_step): g depends on the previous word
+            asm volatile("" : "+v"(g) : "v"(chain));
+            und[k] = 0;
+            if (g < h.n_words) {
+                uint64_t c, n1, n2;
+                gather_lds<WHICH>(h, g, c, n1, n2);
+                uint64_t P[8];
+                draw_planes(dp, g, P);
+                const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
+                h.dst[g] = wd.lt;
+                und[k] = wd.und;
+                chain = (uint32_t)wd.lt;
+            }
+        }
+        uint32_t n = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kBatchWords; ++k)
+            n += (uint32_t)__popcll(und[k]);
+        uint32_t wave_total = 0;
+        const uint32_t offset = wave_exclusive_sum(n, wave_total);
+        uint32_t first = 0;
+        if ((threadIdx.x & 63u) == 63u && wave_total)
+            first = atomicAdd(cnt, wave_total);
+        first = __shfl(first, 63, 64);
+        if (n) {
+            uint32_t slot = first + offset;
+#pragma unroll
+            for (uint32_t k = 0; k < kBatchWords; ++k) {
+                const uint32_t g = base + threadIdx.x + k * blockDim.x;
+                uint64_t u = und[k];
                 while (u) {
                     const int b = __ffsll((unsigned long long)u) - 1;
                     u &= u - 1;
-                    const uint32_t idx = class_at(c, n1, n2, b);
                     if (slot < tl.cap) {
                         tl.site[slot] = 64u * g + (uint32_t)b;
-                        tl.info[slot] = (uint8_t)idx;
-                    } else if (decide_tail_thr(dp, 64u * g + (uint32_t)b, tl.T[idx])) {
-                        lt |= 1ull << b;
+                    } else {
+                        uint64_t c, n1, n2;
+                        gather_lds<WHICH>(h, g, c, n1, n2);
+                        if (decide_tail_thr(dp, 64u * g + (uint32_t)b, tl.T[class_at(c, n1, n2, b)]))
+                            h.dst[g] |= 1ull << b;   // only this thread writes word g before the barrier
                     }
                     ++slot;
                 }
             }
-            h.dst[g] = lt;
         }
     }
     __syncthreads();
     const uint32_t total = *cnt < tl.cap ? *cnt : tl.cap;
     for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
         const uint32_t s = tl.site[e];
-        if (decide_tail_thr(dp, s, tl.T[tl.info[e]]))
-            atomicOr(reinterpret_cast<unsigned long long*>(h.dst + (s >> 6)), 1ull << (s & 63u));
+        const uint32_t g = s >> 6, b = s & 63u;
+        uint64_t c, n1, n2;
+        gather_lds<WHICH>(h, g, c, n1, n2);
+        if (decide_tail_thr(dp, s, tl.T[class_at(c, n1, n2, (int)b)]))
+            atomicOr(reinterpret_cast<unsigned long long*>(h.dst + g), 1ull << b);
     }
     if (threadIdx.x == 0)
         tl.count[parity ^ 1u] = 0;
@@ -135,7 +184,8 @@ __device__ __forceinline__ uint32_t lds_bits4_to_bytes(uint32_t n) {
 
 template <bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA, const HalfCtx& hB, DrawParams dp,
-                                       const PlaneMasks& pm, TailList& tl, int64_t* trace, int64_t* red) {
+                                          TailList& tl, int64_t* trace, int64_t* red) {
+    const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     uint32_t parity = 0;
     for (uint32_t m = 0; m < a.k_steps; ++m) {
         const uint32_t n = a.step0 + m;
@@ -161,7 +211,6 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     uint64_t* tau = smem + a.max_words;
     TailList tl;
     tl.site = reinterpret_cast<uint32_t*>(tau + a.max_words);
-    tl.info = reinterpret_cast<uint8_t*>(tl.site + a.tail_cap);
     tl.cap = a.tail_cap;
     tl.count = s_count;
     tl.T = s_T;
@@ -230,13 +279,12 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         dp.stream = cd.stream;
         dp.tag2 = 0;
         dp.rng_xor = COMPLEMENT ? 0xFFFFFFFFu : 0u;
-        const PlaneMasks pm = make_plane_masks(dp);
         int64_t* trace = a.traces ? a.traces + cd.trace_offset : nullptr;
 
         if (cd.paired)
-            run_steps<true, COMPLEMENT>(a, hA, hB, dp, pm, tl, trace, red);
+            run_steps<true, COMPLEMENT>(a, hA, hB, dp, tl, trace, red);
         else
-            run_steps<false, COMPLEMENT>(a, hA, hB, dp, pm, tl, trace, red);
+            run_steps<false, COMPLEMENT>(a, hA, hB, dp, tl, trace, red);
 
         // write sigma and tau back
         if (a.int8_io) {
@@ -279,7 +327,7 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
 }  // namespace
 
 size_t batch_lds_bytes(uint32_t max_words, uint32_t tail_cap) {
-    return (size_t)2 * max_words * sizeof(uint64_t) + (size_t)tail_cap * (sizeof(uint32_t) + sizeof(uint8_t));
+    return (size_t)2 * max_words * sizeof(uint64_t) + (size_t)tail_cap * sizeof(uint32_t);
 }
 
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st) {

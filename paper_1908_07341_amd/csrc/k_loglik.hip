@@ -24,14 +24,6 @@ namespace {
 // ---------------------------------------------------------------------------
 // Counts
 // ---------------------------------------------------------------------------
-// One lane per 64-site word g of one trajectory and a chunk of consecutive
-// transitions [m0, m1): every lattice of the chunk is read once from HBM by the
-// lane owning the word (the neighbour words come from the caches, since the
-// lanes of a workgroup walk the same lattices together).  kUnroll lattices are
-// loaded ahead so that several loads are in flight per lane.
-constexpr uint32_t kChunk = 64;
-constexpr int kUnroll = 4;
-
 __device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, int64_t (&acc)[12]) {
     const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
     const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
@@ -43,6 +35,104 @@ __device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64
     }
 }
 
+template <int N>
+__device__ __forceinline__ void flush_counts(int64_t (&acc)[N], int64_t* red, unsigned long long* counts) {
+    block_sum_i64<N>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (acc[i])
+                atomicAdd(counts + i, (unsigned long long)acc[i]);
+    }
+}
+
+// Lattices of at most kStageWords words: one workgroup walks a chunk of
+// kChunk consecutive transitions of one trajectory.  Every lattice is read
+// from HBM exactly once (coalesced, each thread owning the words tid,
+// tid + 256, ...), DEPTH lattices ahead of use; the source lattice of each
+// transition is staged in LDS (double-buffered) so that the neighbour words
+// come from LDS.  One barrier per transition.
+constexpr uint32_t kStageWords = 4096;   // L <= 512
+constexpr uint32_t kChunk = 256;
+
+template <uint32_t WPT, uint32_t DEPTH>
+__global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __restrict__ traj, uint32_t n_lat,
+                                                            uint32_t L, FastDiv divW,
+                                                            unsigned long long* __restrict__ counts) {
+    __shared__ uint64_t buf[2][256 * WPT];
+    __shared__ int64_t red[12 * 4];
+    const uint32_t W = L / 64u;
+    const uint32_t n_words = L * W;
+    const uint32_t a = blockIdx.x;
+    const uint32_t m0 = blockIdx.y * kChunk;
+    const uint32_t n_trans = n_lat - 1;
+    const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
+    const uint64_t* X = traj + (size_t)a * n_lat * n_words;
+    int64_t acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        acc[i] = 0;
+    bool mine[WPT];
+    uint32_t jj[WPT], ww[WPT];
+#pragma unroll
+    for (uint32_t k = 0; k < WPT; ++k) {
+        const uint32_t g = threadIdx.x + 256u * k;
+        mine[k] = g < n_words;
+        jj[k] = fdiv(g, divW);
+        ww[k] = g - jj[k] * W;
+    }
+    // ring[d] holds lattice m + 1 + d while transition m is processed
+    uint64_t cur[WPT], ring[DEPTH][WPT];
+#pragma unroll
+    for (uint32_t k = 0; k < WPT; ++k)
+        cur[k] = mine[k] ? X[(size_t)m0 * n_words + threadIdx.x + 256u * k] : 0;
+#pragma unroll
+    for (uint32_t d = 0; d < DEPTH; ++d)
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k)
+            ring[d][k] = (mine[k] && m0 + 1 + d <= m1)
+                             ? X[(size_t)(m0 + 1 + d) * n_words + threadIdx.x + 256u * k] : 0;
+    for (uint32_t mb = m0; mb < m1; mb += DEPTH) {
+#pragma unroll
+        for (uint32_t d = 0; d < DEPTH; ++d) {
+            const uint32_t m = mb + d;
+            if (m < m1) {
+                uint64_t* S = buf[m & 1u];
+#pragma unroll
+                for (uint32_t k = 0; k < WPT; ++k)
+                    if (mine[k])
+                        S[threadIdx.x + 256u * k] = cur[k];
+                __syncthreads();
+                const bool even = (m & 1u) == 0;
+#pragma unroll
+                for (uint32_t k = 0; k < WPT; ++k) {
+                    if (mine[k]) {
+                        const uint32_t j = jj[k], w = ww[k];
+                        const uint64_t c = cur[k];
+                        uint64_t n1, n2;
+                        if (even) {
+                            n1 = S[(j == 0 ? L - 1 : j - 1) * W + w];
+                            n2 = (c << 1) | (S[j * W + (w == 0 ? W - 1 : w - 1)] >> 63);
+                        } else {
+                            n1 = S[(j == L - 1 ? 0 : j + 1) * W + w];
+                            n2 = (c >> 1) | (S[j * W + (w == W - 1 ? 0 : w + 1)] << 63);
+                        }
+                        count_transition(c, n1, n2, ring[d][k], acc);
+                        cur[k] = ring[d][k];
+                        // refill the slot with lattice m + 1 + DEPTH (the chunk
+                        // needs lattices up to m1)
+                        const uint32_t mf = m + 1 + DEPTH;
+                        ring[d][k] = mf <= m1 ? X[(size_t)mf * n_words + threadIdx.x + 256u * k] : 0;
+                    }
+                }
+            }
+        }
+    }
+    flush_counts<12>(acc, red, counts);
+}
+
+// Any L % 64 == 0: one lane per word of one trajectory, walking all its
+// transitions; neighbour words from the caches.
 __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restrict__ traj, uint32_t n_traj,
                                                         uint32_t n_lat, uint32_t L, FastDiv divW,
                                                         unsigned long long* __restrict__ counts) {
@@ -52,14 +142,11 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
     const uint32_t blocks_per_traj = (n_words + blockDim.x - 1) / blockDim.x;
     const uint32_t a = blockIdx.x / blocks_per_traj;
     const uint32_t g = (blockIdx.x % blocks_per_traj) * blockDim.x + threadIdx.x;
-    const uint32_t m0 = blockIdx.y * kChunk;
-    const uint32_t n_trans = n_lat - 1;
-    const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     int64_t acc[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0;
-    if (a < n_traj && g < n_words && m0 < m1) {
+    if (a < n_traj && g < n_words) {
         const uint32_t j = fdiv(g, divW);
         const uint32_t w = g - j * W;
         const uint32_t down = (j == 0 ? L - 1 : j - 1) * W + w;
@@ -67,27 +154,8 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
         const uint32_t prev = j * W + (w == 0 ? W - 1 : w - 1);
         const uint32_t next = j * W + (w == W - 1 ? 0 : w + 1);
         const uint64_t* X = traj + (size_t)a * n_lat * n_words;
-        uint64_t c = X[(size_t)m0 * n_words + g];
-        uint32_t m = m0;
-        for (; m + kUnroll <= m1; m += kUnroll) {
-            uint64_t y[kUnroll], nb1[kUnroll], nb2[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t* Xm = X + (size_t)(m + u) * n_words;
-                y[u] = Xm[n_words + g];
-                const bool even = ((m + u) & 1u) == 0;
-                nb1[u] = Xm[even ? down : up];
-                nb2[u] = Xm[even ? prev : next];
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const bool even = ((m + u) & 1u) == 0;
-                const uint64_t n2 = even ? ((c << 1) | (nb2[u] >> 63)) : ((c >> 1) | (nb2[u] << 63));
-                count_transition(c, nb1[u], n2, y[u], acc);
-                c = y[u];
-            }
-        }
-        for (; m < m1; ++m) {
+        uint64_t c = X[g];
+        for (uint32_t m = 0; m + 1 < n_lat; ++m) {
             const uint64_t* Xm = X + (size_t)m * n_words;
             const uint64_t y = Xm[n_words + g];
             const bool even = (m & 1u) == 0;
@@ -98,13 +166,7 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
             c = y;
         }
     }
-    block_sum_i64<12>(acc, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < 12; ++i)
-            if (acc[i])
-                atomicAdd(counts + i, (unsigned long long)acc[i]);
-    }
+    flush_counts<12>(acc, red, counts);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,16 +330,25 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     if (e != hipSuccess)
         return e;
     const uint32_t n_words = L * (L / 64u);
-    const uint32_t bpt = (n_words + 255u) / 256u;
-    const uint64_t blocks = (uint64_t)bpt * n_traj;
-    const uint32_t chunks = (n_lat - 1 + kChunk - 1) / kChunk;
-    if (blocks == 0 || chunks == 0)
+    if (n_traj == 0 || n_lat < 2)
         return hipSuccess;
-    if (blocks > 0x7FFFFFFFull || chunks > 65535u)
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(counts12);
+    const uint32_t chunks = (n_lat - 1 + kChunk - 1) / kChunk;
+    if (n_words <= kStageWords && chunks > 65535u)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks, chunks), dim3(256), 0, st,
-                       static_cast<const uint64_t*>(traj),
-                       n_traj, n_lat, L, make_fastdiv(L / 64u), reinterpret_cast<unsigned long long*>(counts12));
+    if (n_words <= 1024u) {
+        hipLaunchKernelGGL((k_loglik_counts_lds<4, 8>), dim3(n_traj, chunks), dim3(256), 0, st,
+                           static_cast<const uint64_t*>(traj), n_lat, L, make_fastdiv(L / 64u), out);
+    } else if (n_words <= kStageWords) {
+        hipLaunchKernelGGL((k_loglik_counts_lds<16, 2>), dim3(n_traj, chunks), dim3(256), 0, st,
+                           static_cast<const uint64_t*>(traj), n_lat, L, make_fastdiv(L / 64u), out);
+    } else {
+        const uint64_t blocks = (uint64_t)((n_words + 255u) / 256u) * n_traj;
+        if (blocks > 0x7FFFFFFFull)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st,
+                           static_cast<const uint64_t*>(traj), n_traj, n_lat, L, make_fastdiv(L / 64u), out);
+    }
     return hipGetLastError();
 }
 

@@ -165,41 +165,149 @@ __device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, ui
     }
 }
 
-// One half-step.  obs (half-step B only, may be null) receives the observable
-// contributions of the written pair through 64-bit atomics; it must hold
-// zeros (or earlier partial sums of the same record) before the launch.
+// One half-step.  The grid walks tiles of kTile consecutive words; thread t
+// owns words t, t + 256, ... of a tile (coalesced), draws and compares them,
+// writes the decided bits to registers and appends the undecided sites of the
+// whole tile to an LDS list.  After one barrier the list is resolved by the
+// whole workgroup, decisions are or-ed into an LDS patch word per tile word,
+// and after a second barrier each owner merges its patches and stores.
+// obs (half-step B only, may be null) receives the observable contributions
+// of the written pair through 64-bit atomics; it must hold zeros (or earlier
+// partial sums of the same record) before the launch.
+constexpr int kWordsPerThread = 2;
+constexpr uint32_t kTile = 256u * kWordsPerThread;
+constexpr uint32_t kListCap = 1024;
+
+struct TileScratch {
+    uint64_t patch[kTile];
+    uint16_t entry[kListCap];   // (tile word << 6) | bit
+    uint8_t cls[kListCap];      // class idx of the entry
+    uint32_t count[2];          // list lengths, used by alternate tiles
+};
+
 template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT>
 __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
                                                    DrawParams dp, int64_t* __restrict__ obs) {
-    __shared__ TailScratch<kTailCap> tails;
+    __shared__ TileScratch sh;
     __shared__ int64_t red[4 * 4];
+    const bool want_obs = WHICH == 1 && obs != nullptr;
     int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
-    const PlaneMasks pm = make_plane_masks(dp);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < G.n_groups; base += stride) {
-        const uint32_t g = base + threadIdx.x;
-        const bool active = g < G.n_groups;
-        uint64_t c = 0, n1 = 0, n2 = 0, valid = 0;
-        if (active)
-            gather<LAYOUT, WHICH>(src, G, g, c, n1, n2, valid);
-        uint64_t P[8];
-        draw_planes(dp, active ? g : 0u, P);
-        WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
-        uint64_t lt = wd.lt;
-        resolve_tails<kTailCap>(lt, wd.und & valid, c, n1, n2, 64u * g, dp, tails);
-        if (active) {
-            lt &= valid;
-            scatter<LAYOUT>(dst, G, g, lt, valid);
-            if (WHICH == 1 && obs) {
-                pc += __popcll(lt);
-                d_up += __popcll((lt ^ n1) & valid);
-                d_right += __popcll((lt ^ n2) & valid);
-                d_self += __popcll((lt ^ c) & valid);
-                nsites += __popcll(valid);
+    const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
+    for (uint32_t i = threadIdx.x; i < kTile; i += blockDim.x)
+        sh.patch[i] = 0;
+    if (threadIdx.x == 0) {
+        sh.count[0] = 0;
+        sh.count[1] = 0;
+    }
+    __syncthreads();
+    const uint32_t n_tiles = (G.n_groups + kTile - 1) / kTile;
+    uint32_t parity = 0;
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, parity ^= 1u) {
+        const uint32_t tile0 = tile * kTile;
+        uint64_t lt[kWordsPerThread], und[kWordsPerThread], c[kWordsPerThread], n1[kWordsPerThread],
+            n2[kWordsPerThread], valid[kWordsPerThread];
+        // all loads of the tile first, so that their latency overlaps the
+        // Philox work of the first words
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; ++k) {
+            const uint32_t g = tile0 + threadIdx.x + 256u * k;
+            c[k] = n1[k] = n2[k] = valid[k] = 0;
+            if (g < G.n_groups)
+                gather<LAYOUT, WHICH>(src, G, g, c[k], n1[k], n2[k], valid[k]);
+        }
+        uint32_t chain = 0;   // orders the words' Philox work, see below
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; ++k) {
+            const uint32_t local = threadIdx.x + 256u * k;
+            uint32_t g = tile0 + local;
+            // The words of a tile are independent; left alone the compiler
+            // interleaves all their Philox evaluations and needs ~280 VGPRs.
+            // An empty asm making g depend on the previous word's result keeps
+            // them one after the other.
+            asm volatile("" : "+v"(g) : "v"(chain));
+            const bool active = g < G.n_groups;
+            uint64_t P[8];
+            draw_planes(dp, active ? g : 0u, P);
+            const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c[k], n1[k], n2[k], pm);
+            lt[k] = wd.lt;
+            und[k] = wd.und & valid[k];
+            chain = (uint32_t)wd.lt;
+        }
+        // reserve list slots for the tile's undecided sites: an exclusive
+        // prefix sum of the per-lane counts across the wavefront and one LDS
+        // atomic per wavefront
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; ++k)
+            cnt += (uint32_t)__popcll(und[k]);
+        const uint32_t lane = threadIdx.x & 63u;
+        uint32_t incl = cnt;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(incl, d, 64);
+            if (lane >= d)
+                incl += t;
+        }
+        const uint32_t wave_total = __shfl(incl, 63, 64);
+        uint32_t base = 0;
+        if (lane == 63 && wave_total)
+            base = atomicAdd(&sh.count[parity], wave_total);
+        base = __shfl(base, 63, 64);
+        if (cnt) {
+            uint32_t slot = base + incl - cnt;
+#pragma unroll
+            for (int k = 0; k < kWordsPerThread; ++k) {
+                const uint32_t local = threadIdx.x + 256u * k;
+                uint64_t u = und[k];
+                while (u) {
+                    const int b = __ffsll((unsigned long long)u) - 1;
+                    u &= u - 1;
+                    const uint32_t idx = class_at(c[k], n1[k], n2[k], b);
+                    if (slot < kListCap) {
+                        sh.entry[slot] = (uint16_t)((local << 6) | (uint32_t)b);
+                        sh.cls[slot] = (uint8_t)idx;
+                    } else if (decide_tail(dp, 64u * (tile0 + local) + (uint32_t)b, idx)) {
+                        lt[k] |= 1ull << b;
+                    }
+                    ++slot;
+                }
             }
         }
+        __syncthreads();
+        const uint32_t listed = sh.count[parity];
+        const uint32_t total = listed < kListCap ? listed : kListCap;
+        // the other counter was last read before the previous tile's second
+        // barrier and is next appended to after this tile's second barrier
+        if (threadIdx.x == 0)
+            sh.count[parity ^ 1u] = 0;
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const uint32_t en = sh.entry[e];
+            const uint32_t local = en >> 6, b = en & 63u;
+            if (decide_tail(dp, 64u * (tile0 + local) + b, sh.cls[e]))
+                atomicOr(reinterpret_cast<unsigned long long*>(&sh.patch[local]), 1ull << b);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; ++k) {
+            const uint32_t local = threadIdx.x + 256u * k;
+            const uint32_t g = tile0 + local;
+            const uint64_t bits = (lt[k] | sh.patch[local]) & valid[k];
+            sh.patch[local] = 0;
+            if (g < G.n_groups) {
+                scatter<LAYOUT>(dst, G, g, bits, valid[k]);
+                if (want_obs) {
+                    pc += __popcll(bits);
+                    d_up += __popcll((bits ^ n1[k]) & valid[k]);
+                    d_right += __popcll((bits ^ n2[k]) & valid[k]);
+                    d_self += __popcll((bits ^ c[k]) & valid[k]);
+                    nsites += __popcll(valid[k]);
+                }
+            }
+        }
+        // each patch word is cleared by its owner before the owner reaches
+        // the next tile's first barrier, hence before any new atomic OR
     }
-    if (WHICH == 1 && obs) {
+    if (want_obs) {
         int64_t v[4] = {pc, d_up + d_right, d_self, nsites};
         block_sum_i64<4>(v, red);
         if (threadIdx.x == 0) {
@@ -216,7 +324,7 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
 template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_init_random(void* __restrict__ dst, Geom G, DrawParams dp) {
     __shared__ TailScratch<kTailCap> tails;
-    const PlaneMasks pm = make_plane_masks(dp);
+    const PlaneMasks pm = make_plane_masks<false>(dp);
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < G.n_groups; base += stride) {
         const uint32_t g = base + threadIdx.x;
@@ -259,6 +367,11 @@ uint32_t grid_for(uint32_t n_groups) {
     return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
 }
 
+uint32_t grid_for_tiles(uint32_t n_groups) {
+    uint32_t tiles = (n_groups + kTile - 1) / kTile;
+    return tiles < kMaxBlocks ? (tiles ? tiles : 1u) : kMaxBlocks;
+}
+
 }  // namespace
 
 template <int LAY, int WHICH>
@@ -275,8 +388,11 @@ void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, 
 }
 
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st) {
-    const dim3 grid(grid_for(G.n_groups)), block(256);
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks) {
+    uint32_t blocks = grid_for_tiles(G.n_groups);
+    if (max_blocks && blocks > max_blocks)
+        blocks = max_blocks;
+    const dim3 grid(blocks), block(256);
     const bool paired = thresholds_paired(dp.T);
     const bool complement = dp.rng_xor != 0;
 #define SD_HALF(LAY)                                                                                       \

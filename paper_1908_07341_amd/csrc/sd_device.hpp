@@ -161,13 +161,15 @@ struct PlaneMasks {
     uint32_t S[8][6];
 };
 
+// With PAIRED only the three leader classes 0, 1, 2 are materialised.
+template <bool PAIRED>
 __device__ __forceinline__ PlaneMasks make_plane_masks(const DrawParams& dp) {
     PlaneMasks pm;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
         for (int i = 0; i < 6; ++i)
-            pm.S[m][i] = in_vgpr(0u - ((dp.T[i] >> (31 - m)) & 1u));
+            pm.S[m][i] = (PAIRED && i >= 3) ? 0u : in_vgpr(0u - ((dp.T[i] >> (31 - m)) & 1u));
     return pm;
 }
 

@@ -45,8 +45,10 @@ inline uint32_t fdiv_host(uint32_t n, const FastDiv& f) {
     return (uint32_t)(((uint64_t)hi + n) >> f.shift);
 }
 
+// max_blocks = 0: the default grid (one workgroup per 1024-word tile, at most
+// kMaxBlocks); otherwise at most max_blocks workgroups walk the tiles.
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st);
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks = 0);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
                        hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);

@@ -138,3 +138,34 @@ def test_lds_and_global_paths_agree(L):
             outs.append((got[0], got[1], obs.cpu().numpy()))
     for o in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(outs[0], o))
+
+
+@pytest.mark.parametrize("L,layout", [(128, sd.SD_P64), (256, sd.SD_I8), (1024, sd.SD_P64), (96, sd.SD_P32)])
+def test_sd_tune_keeps_results_and_caches(tmp_path, L, layout):
+    path = str(tmp_path / "run_tune.json")
+    J, q, k = 0.6, 0.4, 12
+    s0 = inputs.random_lattice(L, 7 * L)
+
+    def run():
+        sig = sd.new_lattice(L, layout)
+        if layout == sd.SD_I8:
+            sig.copy_(torch.from_numpy(s0))
+        else:
+            sig.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(s0)))
+        tau = sd.new_lattice(L, layout)
+        obs = torch.zeros((k, 3), dtype=torch.int64, device="cuda")
+        sd.sd_run(sig, tau, L, layout, J, q, SEED, 1, 0, k, obs, 1)
+        torch.cuda.synchronize()
+        return sig.cpu().numpy().tobytes(), tau.cpu().numpy().tobytes(), obs.cpu().numpy()
+
+    before = run()
+    sd.sd_tune(L, layout, path)
+    choice = sd.sd_tuned_choice(L, layout)
+    print("tuned", L, layout, choice, flush=True)
+    assert choice[0] in (1, 2)
+    after = run()
+    assert before[0] == after[0] and before[1] == after[1] and np.array_equal(before[2], after[2])
+    text = open(path).read()
+    assert f"L={L}:layout={layout}" in text
+    sd.sd_tune(L, layout, path)          # from the cache
+    assert sd.sd_tuned_choice(L, layout) == choice

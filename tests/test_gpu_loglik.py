@@ -33,8 +33,12 @@ def _traj_gpu(L, J, q, n_traj, k, stream0=0):
     return traj
 
 
-def test_trajectory_and_counts_match_oracle(oracle):
-    L, J, q, n_traj, k = 64, 0.45, 0.7, 3, 12
+@pytest.mark.parametrize("L,n_traj,k", [(64, 3, 12), (64, 2, 130), (512, 1, 3), (576, 1, 2)])
+def test_trajectory_and_counts_match_oracle(oracle, L, n_traj, k):
+    # L = 64 and 512 take the LDS-staged count kernel (the k = 130 case spans
+    # two transition chunks with a ragged second one), L = 576 the generic one
+    J, q = 0.45, 0.7
+    print(f"trajectories L={L} n={n_traj} k={k}", flush=True)
     traj = _traj_gpu(L, J, q, n_traj, k)
     torch.cuda.synchronize()
     host = traj.cpu().numpy()
@@ -47,6 +51,9 @@ def test_trajectory_and_counts_match_oracle(oracle):
         ref.append(X)
     counts = AG.loglik_counts(traj, n_traj, 2 * k + 1, L)
     assert np.array_equal(counts.cpu().numpy(), oracle.loglik_counts(np.stack(ref)))
+    # a single lattice has no transitions
+    one = AG.loglik_counts(traj[:1, :1].contiguous(), 1, 1, L)
+    assert not one.any()
 
 
 def _fp64(oracle, counts, J, q):
