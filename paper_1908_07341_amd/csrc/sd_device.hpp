@@ -156,20 +156,33 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 // Classes idx and 5 - idx have opposite fields (k -> 2 - k, c -> -c), so
 // T[5 - idx] = 2^32 - T[idx]; when no T[idx] has its low 24 bits all zero the
 // top bytes of the pair are bitwise complements and only the three "leader"
-// classes 0, 1, 2 are needed (paired form, see compare_planes_32).
+// classes 0, 1, 2 are needed (paired form, see compare_planes_paired).
 struct PlaneMasks {
-    uint32_t S[8][6];
+    uint32_t S[8][6];   // general form: all ones where bit (31 - m) of T[i] is set
+    uint32_t code;      // paired form: bits 3m..3m+2 = bit (31 - m) of T[0], T[1], T[2]
 };
 
-// With PAIRED only the three leader classes 0, 1, 2 are materialised.
+// With PAIRED only the wave-uniform plane codes are formed; otherwise the
+// masks of all six classes are materialised in VGPRs.
 template <bool PAIRED>
 __device__ __forceinline__ PlaneMasks make_plane_masks(const DrawParams& dp) {
     PlaneMasks pm;
+    pm.code = 0;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
-        for (int i = 0; i < 6; ++i)
-            pm.S[m][i] = (PAIRED && i >= 3) ? 0u : in_vgpr(0u - ((dp.T[i] >> (31 - m)) & 1u));
+        for (int i = 0; i < 6; ++i) {
+            const uint32_t bit = (dp.T[i] >> (31 - m)) & 1u;
+            if (PAIRED) {
+                pm.S[m][i] = 0u;
+                if (i < 3)
+                    pm.code |= bit << (3 * m + i);
+            } else {
+                pm.S[m][i] = in_vgpr(0u - bit);
+            }
+        }
+    if (PAIRED)
+        pm.code = __builtin_amdgcn_readfirstlane(pm.code);
     return pm;
 }
 
@@ -189,31 +202,23 @@ inline bool thresholds_paired(const uint32_t T[6]) {
 // threshold's top byte.  COMPLEMENT replaces every r by its complement.
 //
 // Paired form: with Q0 = (n1 == n2 == c) (classes 0 and 5), Q2 = n1 ^ n2
-// (classes 2 and 3) and the rest (classes 1 and 4), and nl = majority(n1, n2, c)
-// marking the classes 3, 4, 5, the threshold bit of plane m is
-//   nl ^ (Q2 ? S[m][2] : Q0 ? S[m][0] : S[m][1]).
+// (classes 2 and 3), W1 = the rest (classes 1 and 4), and nl =
+// majority(n1, n2, c) marking the classes 3, 4, 5, the threshold bit of plane m
+// is nl ^ (Q0 & S[m][0] | W1 & S[m][1] | Q2 & S[m][2]).  The S are uniform, so
+// that word is one of eight per-site candidates, picked by the 3-bit plane code.
+// The scan keeps und (top bits equal so far) and v, the complement of r at the
+// last plane where the site was still undecided: for a decided site that is
+// the first differing plane, where r < T iff r's bit is 0.
 // General form: the union of the class masks whose threshold bit is set.
 struct HalfWord {
     uint32_t lt, und;
 };
 
-template <bool PAIRED, bool COMPLEMENT>
+template <bool COMPLEMENT>
 __device__ __forceinline__ HalfWord compare_planes_32(const uint32_t P[8], uint32_t c, uint32_t n1, uint32_t n2,
                                                       const PlaneMasks& pm) {
     uint32_t lt = 0, und = ~0u;
-    if constexpr (PAIRED) {
-        const uint32_t q0 = ~((n1 ^ c) | (n2 ^ c));
-        const uint32_t q2 = n1 ^ n2;
-        const uint32_t nl = (n1 & n2) | (c & (n1 | n2));
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const uint32_t a = (q0 & pm.S[m][0]) | (~q0 & pm.S[m][1]);
-            const uint32_t tb = nl ^ ((q2 & pm.S[m][2]) | (~q2 & a));
-            const uint32_t r = COMPLEMENT ? ~P[m] : P[m];
-            lt |= und & tb & ~r;
-            und &= ~(r ^ tb);
-        }
-    } else {
+    {
         const uint32_t k2 = n1 & n2;
         const uint32_t k1 = n1 ^ n2;
         const uint32_t k0 = ~(n1 | n2);
@@ -236,18 +241,63 @@ struct WordDraw {
     uint64_t lt, und;
 };
 
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+
+// Paired form on a 64-site word.  The candidates of both 32-bit halves sit in
+// one 16-entry vector so that the uniform pick is an indexed VGPR move.
+template <bool COMPLEMENT>
+__device__ __forceinline__ WordDraw compare_planes_paired(const uint64_t P[8], uint64_t c64, uint64_t n164,
+                                                          uint64_t n264, uint32_t code) {
+    u32x16 cand;
+    uint32_t und[2], v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t c = (uint32_t)(c64 >> (32 * h)), n1 = (uint32_t)(n164 >> (32 * h)),
+                       n2 = (uint32_t)(n264 >> (32 * h));
+        const uint32_t q0 = ~((n1 ^ c) | (n2 ^ c));
+        const uint32_t q2 = n1 ^ n2;
+        const uint32_t nl = (n1 & n2) | (c & (n1 | n2));
+        cand[8 * h + 0] = nl;
+        cand[8 * h + 1] = nl ^ q0;
+        cand[8 * h + 2] = ~(nl ^ (q0 | q2));
+        cand[8 * h + 4] = nl ^ q2;
+        cand[8 * h + 7] = ~nl;
+        cand[8 * h + 6] = ~(nl ^ q0);
+        cand[8 * h + 5] = nl ^ (q0 | q2);
+        cand[8 * h + 3] = ~(nl ^ q2);
+        und[h] = ~0u;
+        v[h] = 0u;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const uint32_t idx = (code >> (3 * m)) & 7u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t tb = cand[idx + 8u * h];
+            const uint32_t r = (uint32_t)((COMPLEMENT ? ~P[m] : P[m]) >> (32 * h));
+            v[h] = (und[h] & ~r) | (~und[h] & v[h]);
+            und[h] &= ~(r ^ tb);
+        }
+    }
+    const uint64_t u = (uint64_t)und[0] | ((uint64_t)und[1] << 32);
+    const uint64_t vv = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+    return {vv & ~u, u};
+}
+
 template <bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ WordDraw compare_planes(const uint64_t P[8], uint64_t c, uint64_t n1, uint64_t n2,
                                                    const PlaneMasks& pm) {
+    if constexpr (PAIRED)
+        return compare_planes_paired<COMPLEMENT>(P, c, n1, n2, pm.code);
     uint32_t Plo[8], Phi[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         Plo[m] = (uint32_t)P[m];
         Phi[m] = (uint32_t)(P[m] >> 32);
     }
-    HalfWord lo = compare_planes_32<PAIRED, COMPLEMENT>(Plo, (uint32_t)c, (uint32_t)n1, (uint32_t)n2, pm);
-    HalfWord hi = compare_planes_32<PAIRED, COMPLEMENT>(Phi, (uint32_t)(c >> 32), (uint32_t)(n1 >> 32),
-                                                        (uint32_t)(n2 >> 32), pm);
+    HalfWord lo = compare_planes_32<COMPLEMENT>(Plo, (uint32_t)c, (uint32_t)n1, (uint32_t)n2, pm);
+    HalfWord hi = compare_planes_32<COMPLEMENT>(Phi, (uint32_t)(c >> 32), (uint32_t)(n1 >> 32),
+                                                (uint32_t)(n2 >> 32), pm);
     return {(uint64_t)lo.lt | ((uint64_t)hi.lt << 32), (uint64_t)lo.und | ((uint64_t)hi.und << 32)};
 }
 
