@@ -165,134 +165,135 @@ __device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, ui
     }
 }
 
-// One half-step.  The grid walks tiles of kTile consecutive words; thread t
-// owns words t, t + 256, ... of a tile (coalesced), draws and compares them,
-// writes the decided bits to registers and appends the undecided sites of the
-// whole tile to an LDS list.  After one barrier the list is resolved by the
-// whole workgroup, decisions are or-ed into an LDS patch word per tile word,
-// and after a second barrier each owner merges its patches and stores.
+// One half-step.  Each wavefront walks tiles of kWaveTile consecutive words;
+// lane l owns words l, l + 64, ... of its tile (coalesced loads and stores).
+// For every word it draws the eight planes and compares them (decided sites
+// in lt, undecided ones in und).  A word with undecided sites (about 22% of
+// them at 1/256 per site) claims one slot of the wavefront's LDS list through
+// a ballot and writes und together with the class bits of its sites.  Once
+// the tile's words are listed, lane e resolves list entries e, e + 64, ...:
+// one tail draw per undecided site, the decided bits replacing und in the
+// slot, which the owner reads back before it stores the word.  All of this is
+// local to the wavefront, so the tile loop has no workgroup barrier.  If a
+// list ever fills up (its capacity is several standard deviations above the
+// mean) the owner resolves the word itself.
 // obs (half-step B only, may be null) receives the observable contributions
 // of the written pair through 64-bit atomics; it must hold zeros (or earlier
 // partial sums of the same record) before the launch.
-constexpr int kWordsPerThread = 2;
-constexpr uint32_t kTile = 256u * kWordsPerThread;
-constexpr uint32_t kListCap = 1024;
+constexpr int kWordsPerLane = 4;
+constexpr uint32_t kWaveTile = 64u * kWordsPerLane;
+constexpr uint32_t kWaveListCap = 32u * kWordsPerLane;
+constexpr int kWavesPerBlock = 4;
 
-struct TileScratch {
-    uint64_t patch[kTile];
-    uint16_t entry[kListCap];   // (tile word << 6) | bit
-    uint8_t cls[kListCap];      // class idx of the entry
-    uint32_t count[2];          // list lengths, used by alternate tiles
+struct WaveList {
+    uint64_t und[kWaveListCap];   // undecided sites on entry, decided +1 sites on exit
+    uint64_t c[kWaveListCap];     // partner bits of the word
+    uint64_t n1[kWaveListCap];    // neighbour bits
+    uint64_t n2[kWaveListCap];
+    uint32_t site0[kWaveListCap]; // index of the word's first site
 };
+
+struct HalfStepScratch {
+    WaveList list[kWavesPerBlock];
+    uint32_t T24[6];              // low 24 bits of the class thresholds
+};
+
+// Decided +1 sites among the undecided sites u of the word starting at site0.
+__device__ __forceinline__ uint64_t resolve_word(const DrawParams& dp, const uint32_t* T24, uint64_t u, uint64_t c,
+                                                 uint64_t n1, uint64_t n2, uint32_t site0) {
+    uint64_t r = 0;
+    while (u) {
+        const int b = __ffsll((unsigned long long)u) - 1;
+        u &= u - 1;
+        if (draw_tail24(dp, site0 + (uint32_t)b) < T24[class_at(c, n1, n2, b)])
+            r |= 1ull << b;
+    }
+    return r;
+}
 
 template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT>
 __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
                                                    DrawParams dp, int64_t* __restrict__ obs) {
-    __shared__ TileScratch sh;
+    __shared__ HalfStepScratch sh;
     __shared__ int64_t red[4 * 4];
     const bool want_obs = WHICH == 1 && obs != nullptr;
     int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
-    for (uint32_t i = threadIdx.x; i < kTile; i += blockDim.x)
-        sh.patch[i] = 0;
+    const uint32_t lane = threadIdx.x & 63u;
+    WaveList& wl = sh.list[threadIdx.x >> 6];
     if (threadIdx.x == 0) {
-        sh.count[0] = 0;
-        sh.count[1] = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            sh.T24[i] = dp.T[i] & 0xFFFFFFu;
     }
     __syncthreads();
-    const uint32_t n_tiles = (G.n_groups + kTile - 1) / kTile;
-    uint32_t parity = 0;
-    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, parity ^= 1u) {
-        const uint32_t tile0 = tile * kTile;
-        uint64_t lt[kWordsPerThread], und[kWordsPerThread], c[kWordsPerThread], n1[kWordsPerThread],
-            n2[kWordsPerThread], valid[kWordsPerThread];
+    const uint32_t n_tiles = (G.n_groups + kWaveTile - 1) / kWaveTile;
+    for (uint32_t tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); tile < n_tiles;
+         tile += gridDim.x * kWavesPerBlock) {
+        const uint32_t tile0 = tile * kWaveTile;
+        uint64_t lt[kWordsPerLane], c[kWordsPerLane], n1[kWordsPerLane], n2[kWordsPerLane], valid[kWordsPerLane];
+        uint32_t slot[kWordsPerLane];
         // all loads of the tile first, so that their latency overlaps the
         // Philox work of the first words
 #pragma unroll
-        for (int k = 0; k < kWordsPerThread; ++k) {
-            const uint32_t g = tile0 + threadIdx.x + 256u * k;
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            const uint32_t g = tile0 + lane + 64u * k;
             c[k] = n1[k] = n2[k] = valid[k] = 0;
             if (g < G.n_groups)
                 gather<LAYOUT, WHICH>(src, G, g, c[k], n1[k], n2[k], valid[k]);
         }
-        uint32_t chain = 0;   // orders the words' Philox work, see below
+        uint32_t listed = 0;   // wavefront-uniform list length
+        uint32_t chain = 0;    // orders the words' Philox work, see below
 #pragma unroll
-        for (int k = 0; k < kWordsPerThread; ++k) {
-            const uint32_t local = threadIdx.x + 256u * k;
-            uint32_t g = tile0 + local;
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            uint32_t g = tile0 + lane + 64u * k;
             // The words of a tile are independent; left alone the compiler
-            // interleaves all their Philox evaluations and needs ~280 VGPRs.
-            // An empty asm making g depend on the previous word's result keeps
-            // them one after the other.
+            // interleaves all their Philox evaluations and needs far more
+            // VGPRs.  An empty asm making g depend on the previous word's
+            // result keeps them one after the other.
             asm volatile("" : "+v"(g) : "v"(chain));
             const bool active = g < G.n_groups;
             uint64_t P[8];
             draw_planes(dp, active ? g : 0u, P);
             const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c[k], n1[k], n2[k], pm);
             lt[k] = wd.lt;
-            und[k] = wd.und & valid[k];
             chain = (uint32_t)wd.lt;
-        }
-        // reserve list slots for the tile's undecided sites: an exclusive
-        // prefix sum of the per-lane counts across the wavefront and one LDS
-        // atomic per wavefront
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kWordsPerThread; ++k)
-            cnt += (uint32_t)__popcll(und[k]);
-        const uint32_t lane = threadIdx.x & 63u;
-        uint32_t incl = cnt;
-#pragma unroll
-        for (uint32_t d = 1; d < 64; d <<= 1) {
-            const uint32_t t = __shfl_up(incl, d, 64);
-            if (lane >= d)
-                incl += t;
-        }
-        const uint32_t wave_total = __shfl(incl, 63, 64);
-        uint32_t base = 0;
-        if (lane == 63 && wave_total)
-            base = atomicAdd(&sh.count[parity], wave_total);
-        base = __shfl(base, 63, 64);
-        if (cnt) {
-            uint32_t slot = base + incl - cnt;
-#pragma unroll
-            for (int k = 0; k < kWordsPerThread; ++k) {
-                const uint32_t local = threadIdx.x + 256u * k;
-                uint64_t u = und[k];
-                while (u) {
-                    const int b = __ffsll((unsigned long long)u) - 1;
-                    u &= u - 1;
-                    const uint32_t idx = class_at(c[k], n1[k], n2[k], b);
-                    if (slot < kListCap) {
-                        sh.entry[slot] = (uint16_t)((local << 6) | (uint32_t)b);
-                        sh.cls[slot] = (uint8_t)idx;
-                    } else if (decide_tail(dp, 64u * (tile0 + local) + (uint32_t)b, idx)) {
-                        lt[k] |= 1ull << b;
-                    }
-                    ++slot;
+            const uint64_t und = wd.und & valid[k];
+            const uint64_t need = __ballot(und != 0);
+            slot[k] = ~0u;
+            if (und != 0) {
+                const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                if (e < kWaveListCap) {
+                    slot[k] = e;
+                    wl.und[e] = und;
+                    wl.c[e] = c[k];
+                    wl.n1[e] = n1[k];
+                    wl.n2[e] = n2[k];
+                    wl.site0[e] = 64u * g;
+                } else {
+                    lt[k] |= resolve_word(dp, sh.T24, und, c[k], n1[k], n2[k], 64u * g);
                 }
             }
+            listed += (uint32_t)__popcll(need);
         }
-        __syncthreads();
-        const uint32_t listed = sh.count[parity];
-        const uint32_t total = listed < kListCap ? listed : kListCap;
-        // the other counter was last read before the previous tile's second
-        // barrier and is next appended to after this tile's second barrier
-        if (threadIdx.x == 0)
-            sh.count[parity ^ 1u] = 0;
-        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-            const uint32_t en = sh.entry[e];
-            const uint32_t local = en >> 6, b = en & 63u;
-            if (decide_tail(dp, 64u * (tile0 + local) + b, sh.cls[e]))
-                atomicOr(reinterpret_cast<unsigned long long*>(&sh.patch[local]), 1ull << b);
-        }
-        __syncthreads();
+        const uint32_t n_list = listed < kWaveListCap ? listed : kWaveListCap;
+        // the list was written by other lanes of this wavefront
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t e = lane; e < n_list; e += 64u)
+            wl.und[e] = resolve_word(dp, sh.T24, wl.und[e], wl.c[e], wl.n1[e], wl.n2[e], wl.site0[e]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int k = 0; k < kWordsPerThread; ++k) {
-            const uint32_t local = threadIdx.x + 256u * k;
-            const uint32_t g = tile0 + local;
-            const uint64_t bits = (lt[k] | sh.patch[local]) & valid[k];
-            sh.patch[local] = 0;
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            const uint32_t g = tile0 + lane + 64u * k;
+            uint64_t bits = lt[k];
+            if (slot[k] != ~0u)
+                bits |= wl.und[slot[k]];
+            bits &= valid[k];
             if (g < G.n_groups) {
                 scatter<LAYOUT>(dst, G, g, bits, valid[k]);
                 if (want_obs) {
@@ -304,8 +305,10 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
                 }
             }
         }
-        // each patch word is cleared by its owner before the owner reaches
-        // the next tile's first barrier, hence before any new atomic OR
+        // the owners' reads above precede, in this wavefront's program order,
+        // the next tile's list writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     if (want_obs) {
         int64_t v[4] = {pc, d_up + d_right, d_self, nsites};
@@ -368,8 +371,9 @@ uint32_t grid_for(uint32_t n_groups) {
 }
 
 uint32_t grid_for_tiles(uint32_t n_groups) {
-    uint32_t tiles = (n_groups + kTile - 1) / kTile;
-    return tiles < kMaxBlocks ? (tiles ? tiles : 1u) : kMaxBlocks;
+    const uint32_t tiles = (n_groups + kWaveTile - 1) / kWaveTile;
+    const uint32_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
 }
 
 }  // namespace
