@@ -85,6 +85,8 @@ Geom make_geom(int32_t L, int klay) {
     }
     G.div_row = make_fastdiv(G.words_row);
     G.div_L = make_fastdiv((uint32_t)L);
+    G.step_rows = 64u / G.words_row;
+    G.step_cols = 64u % G.words_row;
     return G;
 }
 

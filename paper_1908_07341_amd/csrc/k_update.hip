@@ -165,37 +165,82 @@ __device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, ui
     }
 }
 
+// Partner and neighbour bits of the 64-bit-word layouts (P64, I8Row) for the
+// word at row j, column word w of the row.
+template <int LAYOUT, int WHICH>
+__device__ __forceinline__ void gather_row(const void* src, const Geom& G, uint32_t j, uint32_t w, uint64_t& c,
+                                           uint64_t& n1, uint64_t& n2) {
+    const uint32_t W = G.words_row;
+    if constexpr (LAYOUT == kLayP64) {
+        const uint64_t* s = static_cast<const uint64_t*>(src);
+        const uint32_t row = j * W;
+        c = s[row + w];
+        const uint32_t c_lo = (uint32_t)c, c_hi = (uint32_t)(c >> 32);
+        if constexpr (WHICH == 0) {
+            n1 = s[(j == 0 ? G.L - 1 : j - 1) * W + w];                                  // down
+            const uint32_t prev_hi =
+                reinterpret_cast<const uint32_t*>(s + row + (w == 0 ? W - 1 : w - 1))[1];
+            n2 = (uint64_t)__builtin_amdgcn_alignbit(c_lo, prev_hi, 31) |                 // left
+                 ((uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 31) << 32);
+        } else {
+            n1 = s[(j == G.L - 1 ? 0 : j + 1) * W + w];                                  // up
+            const uint32_t next_lo = reinterpret_cast<const uint32_t*>(s + row + (w == W - 1 ? 0 : w + 1))[0];
+            n2 = (uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 1) |                     // right
+                 ((uint64_t)__builtin_amdgcn_alignbit(next_lo, c_hi, 1) << 32);
+        }
+    } else {
+        static_assert(LAYOUT == kLayI8Row, "row walk needs 64-site words");
+        const int8_t* s = static_cast<const int8_t*>(src);
+        const size_t row = (size_t)j * G.L;
+        c = load_bits64_i8(s + row + 64u * w);
+        if constexpr (WHICH == 0) {
+            n1 = load_bits64_i8(s + (size_t)(j == 0 ? G.L - 1 : j - 1) * G.L + 64u * w);
+            const int8_t edge = s[row + (w == 0 ? G.L - 1 : 64u * w - 1)];
+            n2 = (c << 1) | (edge > 0 ? 1ull : 0ull);
+        } else {
+            n1 = load_bits64_i8(s + (size_t)(j == G.L - 1 ? 0 : j + 1) * G.L + 64u * w);
+            const int8_t edge = s[row + (w == W - 1 ? 0 : 64u * w + 64u)];
+            n2 = (c >> 1) | (edge > 0 ? (1ull << 63) : 0ull);
+        }
+    }
+}
+
 // One half-step.  Each wavefront walks tiles of kWaveTile consecutive words;
 // lane l owns words l, l + 64, ... of its tile (coalesced loads and stores).
 // For every word it draws the eight planes and compares them (decided sites
 // in lt, undecided ones in und).  A word with undecided sites (about 22% of
-// them at 1/256 per site) claims one slot of the wavefront's LDS list through
-// a ballot and writes und together with the class bits of its sites.  Once
-// the tile's words are listed, lane e resolves list entries e, e + 64, ...:
-// one tail draw per undecided site, the decided bits replacing und in the
-// slot, which the owner reads back before it stores the word.  All of this is
-// local to the wavefront, so the tile loop has no workgroup barrier.  If a
-// list ever fills up (its capacity is several standard deviations above the
-// mean) the owner resolves the word itself.
+// them at 1/256 per site) claims a slot of the wavefront's LDS list through a
+// ballot and stores und and its tile index there; the list has room for every
+// word of the tile.  Then lane e resolves list entries e, e + 64, ...: it
+// reloads the word's partner and neighbour bits (cache hits), draws one tail
+// per undecided site and leaves the decided +1 sites in the slot, which the
+// owner ors into its word before the store.  All of this is local to the
+// wavefront, so the tile loop has no workgroup barrier.
 // obs (half-step B only, may be null) receives the observable contributions
 // of the written pair through 64-bit atomics; it must hold zeros (or earlier
 // partial sums of the same record) before the launch.
-constexpr int kWordsPerLane = 4;
-constexpr uint32_t kWaveTile = 64u * kWordsPerLane;
-constexpr uint32_t kWaveListCap = 32u * kWordsPerLane;
+// Words per lane and tile: 4 for the paired compare on bit-packed layouts,
+// 2 where the general compare or the int8 loads need more registers.
+constexpr int words_per_lane(int layout, bool paired) {
+    return (paired && (layout == kLayP64 || layout == kLayP32)) ? 4 : 2;
+}
+constexpr int kMaxWordsPerLane = 4;
+constexpr uint32_t kMaxWaveTile = 64u * kMaxWordsPerLane;
 constexpr int kWavesPerBlock = 4;
 
 struct WaveList {
-    uint64_t und[kWaveListCap];   // undecided sites on entry, decided +1 sites on exit
-    uint64_t c[kWaveListCap];     // partner bits of the word
-    uint64_t n1[kWaveListCap];    // neighbour bits
-    uint64_t n2[kWaveListCap];
-    uint32_t site0[kWaveListCap]; // index of the word's first site
+    uint64_t und[kMaxWaveTile + 1];   // undecided sites on entry, decided +1 sites on exit;
+                                      // entry kMaxWaveTile stays zero (slot of unlisted words)
+    uint16_t local[kMaxWaveTile];     // tile index of the listed word
 };
 
 struct HalfStepScratch {
     WaveList list[kWavesPerBlock];
-    uint32_t T24[6];              // low 24 bits of the class thresholds
+    uint32_t T24[6];               // low 24 bits of the class thresholds
+};
+
+struct ObsAcc {
+    int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
 };
 
 // Decided +1 sites among the undecided sites u of the word starting at site0.
@@ -211,16 +256,125 @@ __device__ __forceinline__ uint64_t resolve_word(const DrawParams& dp, const uin
     return r;
 }
 
-template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT>
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One tile of 64 * WPL words.  FULL: every word of the tile holds 64 sites
+// of the lattice (no bounds checks).
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS, bool FULL, int WPL>
+__device__ __forceinline__ void half_step_tile(const void* __restrict__ src, void* __restrict__ dst, const Geom& G,
+                                               const DrawParams& dp, const PlaneMasks& pm, const uint32_t* T24,
+                                               WaveList& wl, uint32_t tile0, uint32_t lane, ObsAcc& acc) {
+    constexpr int kWordsPerLane = WPL;
+    constexpr uint32_t kWaveTile = 64u * kWordsPerLane;
+    constexpr bool kRowWalk = LAYOUT == kLayP64 || LAYOUT == kLayI8Row;
+    uint64_t lt[kWordsPerLane], c[kWordsPerLane], n1[kWordsPerLane], n2[kWordsPerLane], valid[kWordsPerLane];
+    uint32_t slot[kWordsPerLane];
+    // all loads of the tile first, so that their latency overlaps the Philox
+    // work of the first words
+    if constexpr (kRowWalk) {
+        const uint32_t g0 = tile0 + lane;
+        uint32_t j = fdiv(g0, G.div_row);
+        uint32_t w = g0 - j * G.words_row;
+#pragma unroll
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            const uint32_t g = g0 + 64u * k;
+            if (FULL || g < G.n_groups) {
+                gather_row<LAYOUT, WHICH>(src, G, j, w, c[k], n1[k], n2[k]);
+                valid[k] = ~0ull;
+            } else {
+                c[k] = n1[k] = n2[k] = valid[k] = 0;
+            }
+            w += G.step_cols;
+            j += G.step_rows;
+            if (w >= G.words_row) {
+                w -= G.words_row;
+                ++j;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            const uint32_t g = tile0 + lane + 64u * k;
+            c[k] = n1[k] = n2[k] = valid[k] = 0;
+            if (FULL || g < G.n_groups)
+                gather<LAYOUT, WHICH>(src, G, g, c[k], n1[k], n2[k], valid[k]);
+            if (FULL)
+                valid[k] = ~0ull;
+        }
+    }
+    uint32_t listed = 0;   // wavefront-uniform list length
+    uint32_t chain = 0;    // orders the words' Philox work, see below
+#pragma unroll
+    for (int k = 0; k < kWordsPerLane; ++k) {
+        uint32_t g = tile0 + lane + 64u * k;
+        // The words of a tile are independent; left alone the compiler
+        // interleaves all their Philox evaluations and needs far more VGPRs.
+        // An empty asm making g depend on the previous word's result keeps
+        // them one after the other.
+        asm volatile("" : "+v"(g) : "v"(chain));
+        uint64_t P[8];
+        draw_planes(dp, (FULL || g < G.n_groups) ? g : 0u, P);
+        const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c[k], n1[k], n2[k], pm);
+        lt[k] = wd.lt;
+        chain = (uint32_t)wd.lt;
+        const uint64_t und = FULL ? wd.und : (wd.und & valid[k]);
+        const uint64_t need = __ballot(und != 0);
+        slot[k] = kMaxWaveTile;   // the zero entry
+        if (und != 0) {
+            const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            slot[k] = e;
+            wl.und[e] = und;
+            wl.local[e] = (uint16_t)(lane + 64u * k);
+        }
+        listed += (uint32_t)__popcll(need);
+    }
+    wave_sync_lds();
+    for (uint32_t e = lane; e < listed; e += 64u) {
+        const uint32_t g = tile0 + wl.local[e];
+        uint64_t cc, a1, a2, v;
+        gather<LAYOUT, WHICH>(src, G, g, cc, a1, a2, v);
+        wl.und[e] = resolve_word(dp, T24, wl.und[e], cc, a1, a2, 64u * g);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int k = 0; k < kWordsPerLane; ++k) {
+        const uint32_t g = tile0 + lane + 64u * k;
+        const uint64_t bits = FULL ? (lt[k] | wl.und[slot[k]]) : ((lt[k] | wl.und[slot[k]]) & valid[k]);
+        if (FULL || g < G.n_groups) {
+            scatter<LAYOUT>(dst, G, g, bits, valid[k]);
+            if constexpr (OBS) {
+                acc.pc += __popcll(bits);
+                acc.d_up += __popcll((bits ^ n1[k]) & valid[k]);
+                acc.d_right += __popcll((bits ^ n2[k]) & valid[k]);
+                acc.d_self += __popcll((bits ^ c[k]) & valid[k]);
+                acc.nsites += __popcll(valid[k]);
+            }
+        }
+    }
+    // the owners' reads above precede, in this wavefront's program order, the
+    // next tile's list writes
+    wave_sync_lds();
+}
+
+// OBS (half-step B only): obs is non-null and receives the observables.
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
 __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
                                                    DrawParams dp, int64_t* __restrict__ obs) {
+    static_assert(!OBS || WHICH == 1, "observables are folded into half-step B");
+    constexpr uint32_t kWaveTile = 64u * words_per_lane(LAYOUT, PAIRED);
     __shared__ HalfStepScratch sh;
     __shared__ int64_t red[4 * 4];
-    const bool want_obs = WHICH == 1 && obs != nullptr;
-    int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
+    ObsAcc acc;
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     const uint32_t lane = threadIdx.x & 63u;
     WaveList& wl = sh.list[threadIdx.x >> 6];
+    if (lane == 0)
+        wl.und[kMaxWaveTile] = 0;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < 6; ++i)
@@ -228,90 +382,22 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
     }
     __syncthreads();
     const uint32_t n_tiles = (G.n_groups + kWaveTile - 1) / kWaveTile;
+    // tiles whose every word holds 64 lattice sites
+    const uint32_t n_full = (uint32_t)((uint64_t)G.n_sites / (64ull * kWaveTile));
     for (uint32_t tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); tile < n_tiles;
          tile += gridDim.x * kWavesPerBlock) {
-        const uint32_t tile0 = tile * kWaveTile;
-        uint64_t lt[kWordsPerLane], c[kWordsPerLane], n1[kWordsPerLane], n2[kWordsPerLane], valid[kWordsPerLane];
-        uint32_t slot[kWordsPerLane];
-        // all loads of the tile first, so that their latency overlaps the
-        // Philox work of the first words
-#pragma unroll
-        for (int k = 0; k < kWordsPerLane; ++k) {
-            const uint32_t g = tile0 + lane + 64u * k;
-            c[k] = n1[k] = n2[k] = valid[k] = 0;
-            if (g < G.n_groups)
-                gather<LAYOUT, WHICH>(src, G, g, c[k], n1[k], n2[k], valid[k]);
+        if (tile < n_full) {
+            half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, true, words_per_lane(LAYOUT, PAIRED)>(
+                src, dst, G, dp, pm, sh.T24, wl, tile * kWaveTile, lane, acc);
+        } else {
+            // the last, partial tile: 64 words at a time, with bounds checks
+            for (uint32_t sub = tile * kWaveTile; sub < (tile + 1) * kWaveTile; sub += 64u)
+                half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, false, 1>(src, dst, G, dp, pm, sh.T24, wl,
+                                                                                  sub, lane, acc);
         }
-        uint32_t listed = 0;   // wavefront-uniform list length
-        uint32_t chain = 0;    // orders the words' Philox work, see below
-#pragma unroll
-        for (int k = 0; k < kWordsPerLane; ++k) {
-            uint32_t g = tile0 + lane + 64u * k;
-            // The words of a tile are independent; left alone the compiler
-            // interleaves all their Philox evaluations and needs far more
-            // VGPRs.  An empty asm making g depend on the previous word's
-            // result keeps them one after the other.
-            asm volatile("" : "+v"(g) : "v"(chain));
-            const bool active = g < G.n_groups;
-            uint64_t P[8];
-            draw_planes(dp, active ? g : 0u, P);
-            const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c[k], n1[k], n2[k], pm);
-            lt[k] = wd.lt;
-            chain = (uint32_t)wd.lt;
-            const uint64_t und = wd.und & valid[k];
-            const uint64_t need = __ballot(und != 0);
-            slot[k] = ~0u;
-            if (und != 0) {
-                const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-                if (e < kWaveListCap) {
-                    slot[k] = e;
-                    wl.und[e] = und;
-                    wl.c[e] = c[k];
-                    wl.n1[e] = n1[k];
-                    wl.n2[e] = n2[k];
-                    wl.site0[e] = 64u * g;
-                } else {
-                    lt[k] |= resolve_word(dp, sh.T24, und, c[k], n1[k], n2[k], 64u * g);
-                }
-            }
-            listed += (uint32_t)__popcll(need);
-        }
-        const uint32_t n_list = listed < kWaveListCap ? listed : kWaveListCap;
-        // the list was written by other lanes of this wavefront
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t e = lane; e < n_list; e += 64u)
-            wl.und[e] = resolve_word(dp, sh.T24, wl.und[e], wl.c[e], wl.n1[e], wl.n2[e], wl.site0[e]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int k = 0; k < kWordsPerLane; ++k) {
-            const uint32_t g = tile0 + lane + 64u * k;
-            uint64_t bits = lt[k];
-            if (slot[k] != ~0u)
-                bits |= wl.und[slot[k]];
-            bits &= valid[k];
-            if (g < G.n_groups) {
-                scatter<LAYOUT>(dst, G, g, bits, valid[k]);
-                if (want_obs) {
-                    pc += __popcll(bits);
-                    d_up += __popcll((bits ^ n1[k]) & valid[k]);
-                    d_right += __popcll((bits ^ n2[k]) & valid[k]);
-                    d_self += __popcll((bits ^ c[k]) & valid[k]);
-                    nsites += __popcll(valid[k]);
-                }
-            }
-        }
-        // the owners' reads above precede, in this wavefront's program order,
-        // the next tile's list writes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
-    if (want_obs) {
-        int64_t v[4] = {pc, d_up + d_right, d_self, nsites};
+    if constexpr (OBS) {
+        int64_t v[4] = {acc.pc, acc.d_up + acc.d_right, acc.d_self, acc.nsites};
         block_sum_i64<4>(v, red);
         if (threadIdx.x == 0) {
             const int64_t n = v[3];
@@ -370,41 +456,45 @@ uint32_t grid_for(uint32_t n_groups) {
     return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
 }
 
-uint32_t grid_for_tiles(uint32_t n_groups) {
-    const uint32_t tiles = (n_groups + kWaveTile - 1) / kWaveTile;
+uint32_t grid_for_tiles(uint32_t n_groups, uint32_t wave_tile) {
+    const uint32_t tiles = (n_groups + wave_tile - 1) / wave_tile;
     const uint32_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
 }
 
 }  // namespace
 
-template <int LAY, int WHICH>
+template <int LAY, int WHICH, bool OBS>
 void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, hipStream_t st, const void* src,
                            void* dst, const Geom& G, const DrawParams& dp, int64_t* obs) {
     if (paired && !complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
     else if (paired)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
     else if (!complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
     else
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
 }
 
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
                             int64_t* obs, hipStream_t st, uint32_t max_blocks) {
-    uint32_t blocks = grid_for_tiles(G.n_groups);
+    const bool paired = thresholds_paired(dp.T);
+    uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
     if (max_blocks && blocks > max_blocks)
         blocks = max_blocks;
     const dim3 grid(blocks), block(256);
-    const bool paired = thresholds_paired(dp.T);
     const bool complement = dp.rng_xor != 0;
 #define SD_HALF(LAY)                                                                                       \
     case LAY:                                                                                              \
         if (which == 0)                                                                                    \
-            launch_half_step_mode<LAY, 0>(paired, complement, grid, block, st, src, dst, G, dp, nullptr); \
+            launch_half_step_mode<LAY, 0, false>(paired, complement, grid, block, st, src, dst, G, dp,      \
+                                                 nullptr);                                                 \
+        else if (obs == nullptr)                                                                           \
+            launch_half_step_mode<LAY, 1, false>(paired, complement, grid, block, st, src, dst, G, dp,      \
+                                                 nullptr);                                                 \
         else                                                                                               \
-            launch_half_step_mode<LAY, 1>(paired, complement, grid, block, st, src, dst, G, dp, obs);     \
+            launch_half_step_mode<LAY, 1, true>(paired, complement, grid, block, st, src, dst, G, dp, obs); \
         break;
     switch (layout) {
         SD_HALF(kLayP64)

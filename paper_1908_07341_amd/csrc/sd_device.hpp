@@ -420,16 +420,15 @@ __device__ __forceinline__ void block_sum_i64(int64_t (&v)[N], int64_t* red) {
 }
 
 // Fast division by a launch-constant divisor d >= 1 (n < 2^32):
-// q = (umulhi(n, mul) + n) >> shift  when add = 1, else umulhi(n, mul) >> shift.
+// q = (umulhi(n, mul) + n) >> shift, the sum taken in 64 bits.  (add is
+// always 1 for the constants make_fastdiv produces.)
 struct FastDiv {
     uint32_t d, mul, shift, add;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
-    uint32_t hi = __umulhi(n, f.mul);
-    if (f.add)
-        return (uint32_t)(((uint64_t)hi + n) >> f.shift);
-    return hi >> f.shift;
+    const uint32_t hi = __umulhi(n, f.mul);
+    return (uint32_t)(((uint64_t)hi + n) >> f.shift);
 }
 
 }  // namespace sd

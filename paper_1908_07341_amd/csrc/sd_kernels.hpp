@@ -24,6 +24,8 @@ struct Geom {
     uint32_t words_row;   // P64: L/64; P32: L/32; I8Row: L/64; I8Any: unused
     FastDiv div_row;      // division by words_row
     FastDiv div_L;        // division by L
+    uint32_t step_rows;   // 64 = step_rows * words_row + step_cols: moving 64
+    uint32_t step_cols;   // words on in row-major order
 };
 
 // Granlund-Montgomery constants for division by d (1 <= d < 2^32).
