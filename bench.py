@@ -39,10 +39,11 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU operations per spin update of the half-step:
 # Philox4x32-10 work of the stream contract, 4 calls per 64 sites plus one tail
-# call per 256 sites, 10 rounds of 2 multiplies + 2 three-way XORs each, and
-# the bit-sliced comparison, 8 planes x (1 select + 3 updates) per 32 sites.
+# call per undecided site (1/256 of them), 10 rounds of 2 multiplies + 2
+# three-way XORs each, and the bit-sliced comparison, 8 planes x (1 select +
+# 2 logic ops) per 32 sites.
 PHILOX_CALLS_PER_SITE = 4.0 / 64.0 + 1.0 / 256.0
-OPS_PER_SPIN_UPDATE = PHILOX_CALLS_PER_SITE * 10 * 4 + 8 * 4 / 32.0
+OPS_PER_SPIN_UPDATE = PHILOX_CALLS_PER_SITE * 10 * 4 + 8 * 3 / 32.0
 
 
 # Sources whose content determines the half-step kernel; a traffic figure from
@@ -63,16 +64,54 @@ def kernel_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per half-step launch from the committed counter summary, or
-    None when there is none or the kernel changed since it was taken."""
+    """(HBM bytes per half-step launch, kernel it was measured on) from the
+    committed counter summary, or (None, None) when there is none or the
+    kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, None
     if rec.get("kernel_sha256") != kernel_hash():
-        return None
-    return rec.get("bytes_per_launch")
+        return None, None
+    return rec.get("bytes_per_launch"), rec.get("kernel")
+
+
+def traffic_from_counters(fetch_csv: str, write_csv: str, copy_bytes: int = 512 * 1024 * 1024) -> dict:
+    """HBM bytes per launch of the half-step kernels from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of the --calibrate-copy
+    bench.  Each counter is scaled by the factor that maps its reading for the
+    device copy of copy_bytes to the bytes that copy moves."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals, copy = {}, None
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                name, v = row["Kernel_Name"], float(row["Counter_Value"])
+                if name == "__amd_rocclr_copyBuffer" and (copy is None or v > copy):
+                    copy = v
+                elif "k_half_step" in name:
+                    vals.setdefault(name, []).append(v)
+        return {k: sum(v) / len(v) for k, v in vals.items()}, copy
+
+    fetch, fetch_copy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, write_copy = per_kernel(write_csv, "WRITE_SIZE")
+    f_fac = copy_bytes / (fetch_copy * 1024.0)
+    w_fac = copy_bytes / (write_copy * 1024.0)
+    kernels = {}
+    for k in fetch:
+        if k in write:
+            kernels[k] = {"fetch_kib": fetch[k], "write_kib": write[k],
+                          "bytes": f_fac * fetch[k] * 1024.0 + w_fac * write[k] * 1024.0}
+    # the plain half-step A kernel (no observables) stands for the launch
+    main = min((k for k in kernels if "k_half_step<" in k and ", 0, " in k.split("<", 1)[1][:6]),
+               key=lambda k: kernels[k]["bytes"], default=None)
+    return {"kernel_sha256": kernel_hash(), "kernel": main,
+            "bytes_per_launch": kernels[main]["bytes"] if main else None,
+            "fetch_factor": f_fac, "write_factor": w_fac, "copy_bytes": copy_bytes, "kernels": kernels}
 
 
 def calibrate_copy(torch, mib: int = 512) -> None:
@@ -107,6 +146,8 @@ def parse():
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 512 MiB device copy first (counter calibration runs)")
+    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="write the half-step traffic record from two rocprofv3 counter CSVs and exit")
     return p.parse_args()
 
 
@@ -296,6 +337,12 @@ def _fp64_grad(c, J, q):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        rec = traffic_from_counters(*args.traffic_from)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps({"kernel": rec["kernel"], "bytes_per_launch": rec["bytes_per_launch"]}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the shaken-dynamics path here is "
                                    "built and measured for a single MI355X (see DESIGN.md for how it would "
@@ -315,6 +362,7 @@ def main():
     sd.sd_tune(L, sd.SD_P64, args.tune_cache)
     log(f"[bench] sd_tune L={L}: choice {sd.sd_tuned_choice(L, sd.SD_P64)} in {time.perf_counter() - t0:.2f} s")
     log(f"[bench] single chain L={L} K={K} W={W}")
+    choice = sd.sd_tuned_choice(L, sd.SD_P64)
     r = bench_single(sd, torch, L, K, W)
     updates = 2.0 * L * L * K
     value = updates / (r["wall_s"] * 1e9)
@@ -322,6 +370,9 @@ def main():
     per_launch_updates = L * L
     achieved = OPS_PER_SPIN_UPDATE * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e12
     peak = VALU_PEAK_OPS / 1e12
+    traffic, traffic_kernel = measured_traffic()
+    kernel = {0: "built-in rule", 1: "single-workgroup LDS kernel"}.get(
+        choice[0], f"k_half_step on {choice[1]}-bit words, {choice[2]} workgroups")
     out = {
         "metric": METRIC, "value": value, "unit": "spin updates/ns", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": r["wall_s"] * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -330,8 +381,8 @@ def main():
                                f"J=0.5, q=0.5, observables (M,A,B) every 10 steps",
                    "L": L, "layout": "P64", "J": 0.5, "q": 0.5, "obs_every": 10, "seed": 1},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(),
-                     "kernel": "k_half_step (P64)", "launch_us": r["launch_ms"] * 1e3,
+                     "frac": achieved / peak, "traffic": traffic, "traffic_kernel": traffic_kernel,
+                     "kernel": kernel, "tuned_choice": list(choice), "launch_us": r["launch_ms"] * 1e3,
                      "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
                      "hbm_algorithmic_GBps": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9,
                      "hbm_frac": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -166,6 +166,31 @@ uint32_t lds_max_words() {
     return w;
 }
 
+int64_t* partials_workspace(hipStream_t st) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, int64_t*> spaces;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, st);
+    const auto it = spaces.find(key);
+    if (it != spaces.end())
+        return it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    int64_t* p = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&p), kPartialsWords * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    spaces[key] = p;
+    return p;
+}
+
 }  // namespace sd
 
 using namespace sd;
@@ -291,6 +316,7 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     }
     const Geom G = make_geom(L, klay);
     hipError_t e = hipSuccess;
+    int64_t* partials = n_rec ? partials_workspace(st) : nullptr;
     if (n_rec)
         e = launch_fill_i64(obs, (size_t)n_rec * 3u, 0, st);
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
@@ -303,7 +329,7 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
         int64_t* rec = nullptr;
         if (n_rec && (m + 1) % obs_every == 0)
             rec = obs + 3u * (size_t)((m + 1) / obs_every - 1);
-        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks);
+        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks, partials);
     }
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
 }

@@ -35,15 +35,59 @@ __device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64
     }
 }
 
+// The same counts in 32-bit accumulators: tot[i] = sites of class i,
+// plus[i] = those drawn +1 (each popcount folds into its accumulator).  A
+// thread adds at most 64 per word and transition, so 2^26 word-transitions
+// per thread stay exact.
+__device__ __forceinline__ void count_transition32(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, uint32_t (&tot)[6],
+                                                   uint32_t (&plus)[6]) {
+    const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
+    const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const uint64_t a = cls[i], b = cls[i] & y;
+        tot[i] += __popc((uint32_t)a) + __popc((uint32_t)(a >> 32));
+        plus[i] += __popc((uint32_t)b) + __popc((uint32_t)(b >> 32));
+    }
+}
+
+// Workgroup sums of the 12 counts: into partials[12 * block ...] when
+// partials is non-null (k_counts_finish adds them up), else into counts
+// through 64-bit atomics.
 template <int N>
-__device__ __forceinline__ void flush_counts(int64_t (&acc)[N], int64_t* red, unsigned long long* counts) {
+__device__ __forceinline__ void flush_counts(int64_t (&acc)[N], int64_t* red, unsigned long long* counts,
+                                             int64_t* partials, uint32_t block) {
     block_sum_i64<N>(acc, red);
     if (threadIdx.x == 0) {
+        if (partials) {
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            if (acc[i])
-                atomicAdd(counts + i, (unsigned long long)acc[i]);
+            for (int i = 0; i < N; ++i)
+                partials[(size_t)N * block + i] = acc[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                if (acc[i])
+                    atomicAdd(counts + i, (unsigned long long)acc[i]);
+        }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_counts_finish(const int64_t* __restrict__ partials, uint32_t n_blocks,
+                                                        int64_t* __restrict__ counts) {
+    __shared__ int64_t red[12 * 16];
+    int64_t v[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        v[i] = 0;
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            v[i] += partials[12u * b + i];
+    block_sum_i64<12>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            counts[i] = v[i];
 }
 
 // Lattices of at most kStageWords words: one workgroup walks a chunk of
@@ -58,7 +102,8 @@ constexpr uint32_t kChunk = 256;
 template <uint32_t WPT, uint32_t DEPTH>
 __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __restrict__ traj, uint32_t n_lat,
                                                             uint32_t L, FastDiv divW,
-                                                            unsigned long long* __restrict__ counts) {
+                                                            unsigned long long* __restrict__ counts,
+                                                            int64_t* __restrict__ partials) {
     __shared__ uint64_t buf[2][256 * WPT];
     __shared__ int64_t red[12 * 4];
     const uint32_t W = L / 64u;
@@ -68,10 +113,10 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
     const uint32_t n_trans = n_lat - 1;
     const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     const uint64_t* X = traj + (size_t)a * n_lat * n_words;
-    int64_t acc[12];
+    uint32_t tot[6], plus[6];
 #pragma unroll
-    for (int i = 0; i < 12; ++i)
-        acc[i] = 0;
+    for (int i = 0; i < 6; ++i)
+        tot[i] = plus[i] = 0;
     bool mine[WPT];
     uint32_t jj[WPT], ww[WPT];
 #pragma unroll
@@ -117,7 +162,7 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
                             n1 = S[(j == L - 1 ? 0 : j + 1) * W + w];
                             n2 = (c >> 1) | (S[j * W + (w == W - 1 ? 0 : w + 1)] << 63);
                         }
-                        count_transition(c, n1, n2, ring[d][k], acc);
+                        count_transition32(c, n1, n2, ring[d][k], tot, plus);
                         cur[k] = ring[d][k];
                         // refill the slot with lattice m + 1 + DEPTH (the chunk
                         // needs lattices up to m1)
@@ -128,14 +173,21 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
             }
         }
     }
-    flush_counts<12>(acc, red, counts);
+    int64_t acc[12];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        acc[2 * i + 1] = plus[i];
+        acc[2 * i] = (int64_t)tot[i] - (int64_t)plus[i];
+    }
+    flush_counts<12>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Any L % 64 == 0: one lane per word of one trajectory, walking all its
 // transitions; neighbour words from the caches.
 __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restrict__ traj, uint32_t n_traj,
                                                         uint32_t n_lat, uint32_t L, FastDiv divW,
-                                                        unsigned long long* __restrict__ counts) {
+                                                        unsigned long long* __restrict__ counts,
+                                                        int64_t* __restrict__ partials) {
     __shared__ int64_t red[12 * 4];
     const uint32_t W = L / 64u;
     const uint32_t n_words = L * W;
@@ -166,7 +218,7 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
             c = y;
         }
     }
-    flush_counts<12>(acc, red, counts);
+    flush_counts<12>(acc, red, counts, partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,7 +377,7 @@ __global__ void k_loglik_bwd(const int64_t* __restrict__ counts, const float* __
 }  // namespace
 
 hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_lat, uint32_t L, int64_t* counts12,
-                                hipStream_t st) {
+                                hipStream_t st, int64_t* partials, size_t partials_words) {
     hipError_t e = launch_fill_i64(counts12, 12, 0, st);
     if (e != hipSuccess)
         return e;
@@ -336,19 +388,26 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     const uint32_t chunks = (n_lat - 1 + kChunk - 1) / kChunk;
     if (n_words <= kStageWords && chunks > 65535u)
         return hipErrorInvalidValue;
-    if (n_words <= 1024u) {
-        hipLaunchKernelGGL((k_loglik_counts_lds<4, 8>), dim3(n_traj, chunks), dim3(256), 0, st,
-                           static_cast<const uint64_t*>(traj), n_lat, L, make_fastdiv(L / 64u), out);
-    } else if (n_words <= kStageWords) {
-        hipLaunchKernelGGL((k_loglik_counts_lds<16, 2>), dim3(n_traj, chunks), dim3(256), 0, st,
-                           static_cast<const uint64_t*>(traj), n_lat, L, make_fastdiv(L / 64u), out);
-    } else {
-        const uint64_t blocks = (uint64_t)((n_words + 255u) / 256u) * n_traj;
-        if (blocks > 0x7FFFFFFFull)
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st,
-                           static_cast<const uint64_t*>(traj), n_traj, n_lat, L, make_fastdiv(L / 64u), out);
-    }
+    uint64_t blocks;
+    if (n_words <= kStageWords)
+        blocks = (uint64_t)n_traj * chunks;
+    else
+        blocks = (uint64_t)((n_words + 255u) / 256u) * n_traj;
+    if (blocks > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
+    int64_t* part = (partials && 12u * blocks <= partials_words) ? partials : nullptr;
+    const uint64_t* X = static_cast<const uint64_t*>(traj);
+    if (n_words <= 1024u)
+        hipLaunchKernelGGL((k_loglik_counts_lds<4, 8>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat, L,
+                           make_fastdiv(L / 64u), out, part);
+    else if (n_words <= kStageWords)
+        hipLaunchKernelGGL((k_loglik_counts_lds<16, 2>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat, L,
+                           make_fastdiv(L / 64u), out, part);
+    else
+        hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st, X, n_traj, n_lat, L,
+                           make_fastdiv(L / 64u), out, part);
+    if (part)
+        hipLaunchKernelGGL(k_counts_finish, dim3(1), dim3(1024), 0, st, part, (uint32_t)blocks, counts12);
     return hipGetLastError();
 }
 

@@ -361,10 +361,14 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
     wave_sync_lds();
 }
 
-// OBS (half-step B only): obs is non-null and receives the observables.
+// OBS (half-step B only): the workgroup sums of (#+1, #differences to the
+// up and right neighbours, #differences to the partner, #sites) go to
+// partials[4 * blockIdx.x ...] when partials is non-null (k_obs_finish turns
+// them into M, A, B), else straight into obs through 64-bit atomics.
 template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
 __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
-                                                   DrawParams dp, int64_t* __restrict__ obs) {
+                                                   DrawParams dp, int64_t* __restrict__ obs,
+                                                   int64_t* __restrict__ partials) {
     static_assert(!OBS || WHICH == 1, "observables are folded into half-step B");
     constexpr uint32_t kWaveTile = 64u * words_per_lane(LAYOUT, PAIRED);
     __shared__ HalfStepScratch sh;
@@ -399,7 +403,11 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
     if constexpr (OBS) {
         int64_t v[4] = {acc.pc, acc.d_up + acc.d_right, acc.d_self, acc.nsites};
         block_sum_i64<4>(v, red);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && partials) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                partials[4u * blockIdx.x + i] = v[i];
+        } else if (threadIdx.x == 0) {
             const int64_t n = v[3];
             atomicAdd(reinterpret_cast<unsigned long long*>(obs + 0), (unsigned long long)(2 * v[0] - n));
             atomicAdd(reinterpret_cast<unsigned long long*>(obs + 1), (unsigned long long)(2 * n - 2 * v[1]));
@@ -446,6 +454,24 @@ __global__ __launch_bounds__(256) void k_init_const(void* __restrict__ dst, Geom
     }
 }
 
+// Sums the per-workgroup partials of an observables launch into obs (M, A, B).
+__global__ __launch_bounds__(1024) void k_obs_finish(const int64_t* __restrict__ partials, uint32_t n_blocks,
+                                                     int64_t* __restrict__ obs) {
+    __shared__ int64_t red[4 * 16];
+    int64_t v[4] = {0, 0, 0, 0};
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] += partials[4u * b + i];
+    block_sum_i64<4>(v, red);
+    if (threadIdx.x == 0) {
+        const int64_t n = v[3];
+        obs[0] += 2 * v[0] - n;
+        obs[1] += 2 * n - 2 * v[1];
+        obs[2] += n - 2 * v[2];
+    }
+}
+
 __global__ void k_fill_i64(int64_t* __restrict__ p, size_t n, int64_t v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -466,19 +492,23 @@ uint32_t grid_for_tiles(uint32_t n_groups, uint32_t wave_tile) {
 
 template <int LAY, int WHICH, bool OBS>
 void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, hipStream_t st, const void* src,
-                           void* dst, const Geom& G, const DrawParams& dp, int64_t* obs) {
+                           void* dst, const Geom& G, const DrawParams& dp, int64_t* obs, int64_t* partials) {
     if (paired && !complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
+                           partials);
     else if (paired)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
+                           partials);
     else if (!complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
+                           partials);
     else
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs);
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
+                           partials);
 }
 
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st, uint32_t max_blocks) {
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks, int64_t* partials) {
     const bool paired = thresholds_paired(dp.T);
     uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
     if (max_blocks && blocks > max_blocks)
@@ -489,12 +519,13 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
     case LAY:                                                                                              \
         if (which == 0)                                                                                    \
             launch_half_step_mode<LAY, 0, false>(paired, complement, grid, block, st, src, dst, G, dp,      \
-                                                 nullptr);                                                 \
+                                                 nullptr, nullptr);                                        \
         else if (obs == nullptr)                                                                           \
             launch_half_step_mode<LAY, 1, false>(paired, complement, grid, block, st, src, dst, G, dp,      \
-                                                 nullptr);                                                 \
+                                                 nullptr, nullptr);                                        \
         else                                                                                               \
-            launch_half_step_mode<LAY, 1, true>(paired, complement, grid, block, st, src, dst, G, dp, obs); \
+            launch_half_step_mode<LAY, 1, true>(paired, complement, grid, block, st, src, dst, G, dp, obs,  \
+                                                partials);                                                 \
         break;
     switch (layout) {
         SD_HALF(kLayP64)
@@ -505,6 +536,8 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
             return hipErrorInvalidValue;
     }
 #undef SD_HALF
+    if (which == 1 && obs != nullptr && partials != nullptr)
+        hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(1024), 0, st, partials, blocks, obs);
     return hipGetLastError();
 }
 

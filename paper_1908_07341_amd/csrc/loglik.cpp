@@ -53,8 +53,9 @@ sd_status sd_loglik_counts(const void* traj, int32_t n_traj, int32_t n_lat, int3
         return fail(SD_EINVAL, "sd_loglik_counts: need n_traj >= 0, n_lat >= 1 and L a multiple of 64");
     if (reinterpret_cast<uintptr_t>(traj) & 7u)
         return fail(SD_EINVAL, "sd_loglik_counts: trajectories must be 8-byte aligned");
-    hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, counts12,
-                                        static_cast<hipStream_t>(hip_stream));
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, counts12, st,
+                                        partials_workspace(st), kPartialsWords);
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_counts");
 }
 

@@ -17,4 +17,11 @@ uint32_t threshold(double h);
 void threshold_table(double J, double q, uint32_t T[6]);
 DrawParams dynamics_params(double J, double q, uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags);
 
+// Device scratch of kPartialsWords int64 for per-workgroup partial sums, one
+// per (device, stream), allocated on first use and kept for the process.
+// Null when it does not exist yet and cannot be made now (the stream is
+// being captured, or the allocation failed); callers then use atomics.
+constexpr size_t kPartialsWords = 65536;
+int64_t* partials_workspace(hipStream_t st);
+
 }  // namespace sd
