@@ -236,9 +236,11 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
         sd.sd_tune(int(size), sd.SD_P64, tune_cache)
     rng = np.random.default_rng(0)
     sample = []
-    for size in sorted(set(Lv.tolist())):
+    sizes = sorted(set(Lv.tolist()))
+    for size in sizes:
         idx = np.flatnonzero(Lv == size)
-        sample += rng.choice(idx, size=min(plain_sample // 3, len(idx)), replace=False).tolist()
+        per_size = max(1, plain_sample // len(sizes))
+        sample += rng.choice(idx, size=min(per_size, len(idx)), replace=False).tolist()
     sample_cost = 0.0
     identical = True
     t_plain = 0.0
