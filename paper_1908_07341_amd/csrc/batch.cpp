@@ -24,12 +24,12 @@ struct sd_batch_plan {
 
     struct Bucket {
         uint32_t L = 0;
+        uint32_t paired = 1;             // compare form shared by the bucket's chains
         uint32_t max_words = 0;
         uint32_t first = 0, count = 0;   // range in the order array
         uint32_t threads = 256, blocks = 1;
     };
     std::vector<Bucket> buckets;
-    uint32_t tail_cap = 2048;
 
     sd::ChainDesc* d_descs = nullptr;
     uint32_t* d_order = nullptr;
@@ -81,8 +81,8 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     a.obs_every = p->obs_every ? p->obs_every : 1u;
     a.rng_xor = (p->flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
     a.max_words = bk.max_words;
-    a.tail_cap = p->tail_cap;
     a.int8_io = p->layout == SD_I8 ? 1u : 0u;
+    a.paired = bk.paired;
     return a;
 }
 
@@ -116,12 +116,13 @@ hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint
 // Measured choice of the batched kernel's block size for chains of size L: a
 // sample of this plan's chains of that size runs 16 steps on scratch lattices
 // for every candidate; the fastest is kept in the cache file.
-uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_chains, sd_batch_plan* p) {
+uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t paired, uint32_t n_chains,
+                                sd_batch_plan* p) {
     const uint32_t fallback = 256;
     if (!cache_path || !*cache_path)
         return fallback;
-    const std::string key = "batch:" + device_arch() + ":L=" + std::to_string(L) + ":k=" +
-                            std::to_string(p->obs_every ? 1 : 0);
+    const std::string key = "batch:" + device_arch() + ":L=" + std::to_string(L) + ":p=" + std::to_string(paired) +
+                            ":k=" + std::to_string(p->obs_every ? 1 : 0);
     const long cached = tune_cache_get(cache_path, key);
     if (cached > 0)
         return (uint32_t)cached;
@@ -131,7 +132,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_c
         return fallback;
     std::vector<ChainDesc> sample;
     for (const ChainDesc& d : p->descs)
-        if (d.L == L && sample.size() < std::min<uint32_t>(n_chains, 2u * (uint32_t)n_cu))
+        if (d.L == L && d.paired == paired && sample.size() < std::min<uint32_t>(n_chains, 2u * (uint32_t)n_cu))
             sample.push_back(d);
     const uint32_t S = (uint32_t)sample.size();
     const uint32_t k = 16;
@@ -165,8 +166,8 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_c
     if (e == hipSuccess) e = hipEventCreate(&e1);
     long best = -1;
     if (e == hipSuccess) {
-        const size_t lds = batch_lds_bytes(L * (L / 64u), p->tail_cap);
         auto measure = [&](long threads) -> double {
+            const size_t lds = batch_lds_bytes(L * (L / 64u), (uint32_t)threads);
             BatchArgs a;
             std::memset(&a, 0, sizeof a);
             a.chains = dd;
@@ -179,10 +180,10 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_c
             a.k_steps = k;
             a.obs_every = 1;
             a.max_words = L * (L / 64u);
-            a.tail_cap = p->tail_cap;
             a.int8_io = p->layout == SD_I8 ? 1u : 0u;
+            a.paired = paired;
             int per_cu = 0;
-            if (batch_occupancy((uint32_t)threads, lds, &per_cu) != hipSuccess || per_cu < 1)
+            if (batch_occupancy((uint32_t)threads, lds, paired != 0, &per_cu) != hipSuccess || per_cu < 1)
                 return -1.0;
             const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(S, (uint32_t)per_cu * (uint32_t)n_cu));
             float best_ms = -1.0f;
@@ -237,9 +238,9 @@ hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_
     a.obs_every = obs_every ? obs_every : 1u;
     a.rng_xor = (flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
     a.max_words = (uint32_t)L * ((uint32_t)L / 64u);
-    a.tail_cap = 1024;
     a.int8_io = int8_io ? 1u : 0u;
-    hipError_t e = batch_kernel_attributes(batch_lds_bytes(a.max_words, a.tail_cap));
+    a.paired = a.single.paired;
+    hipError_t e = batch_kernel_attributes(batch_lds_bytes(a.max_words, threads));
     if (e != hipSuccess)
         return e;
     return launch_batch_chains(a, 1, threads, st);
@@ -287,7 +288,8 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     p->flags = flags;
     p->descs.resize((size_t)n_chains);
 
-    std::map<uint32_t, std::vector<uint32_t>, std::greater<uint32_t>> by_L;   // largest L first
+    // buckets by (L, paired form): largest L first, paired before unpaired
+    std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>, std::greater<std::pair<uint32_t, uint32_t>>> by_L;
     size_t off = 0;
     for (int32_t c = 0; c < n_chains; ++c) {
         const sd_chain_desc& in = chains[c];
@@ -296,7 +298,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
             return fail(SD_EINVAL, "sd_batch_plan_create: chain %d needs finite J, q and L a multiple of 64", c);
         }
         const size_t words = (size_t)in.L * (in.L / 64);
-        if (batch_lds_bytes((uint32_t)words, p->tail_cap) > (size_t)max_lds) {
+        if (batch_lds_bytes((uint32_t)words, 64) > (size_t)max_lds) {
             delete p;
             return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: chain %d (L=%d) does not fit in %d bytes of LDS", c,
                         in.L, max_lds);
@@ -313,7 +315,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         d.tau_offset = off;
         off = align_up(off + bytes);
         d.trace_offset = (uint64_t)c * p->n_rec * 3u;
-        by_L[(uint32_t)in.L].push_back((uint32_t)c);
+        by_L[std::make_pair((uint32_t)in.L, d.paired)].push_back((uint32_t)c);
     }
     p->lattice_total = off;
 
@@ -321,8 +323,9 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     order.reserve((size_t)n_chains);
     for (auto& kv : by_L) {
         sd_batch_plan::Bucket bk;
-        bk.L = kv.first;
-        bk.max_words = kv.first * (kv.first / 64u);
+        bk.L = kv.first.first;
+        bk.paired = kv.first.second;
+        bk.max_words = bk.L * (bk.L / 64u);
         bk.first = (uint32_t)order.size();
         bk.count = (uint32_t)kv.second.size();
         order.insert(order.end(), kv.second.begin(), kv.second.end());
@@ -332,7 +335,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     size_t max_words = 0;
     for (auto& bk : p->buckets)
         max_words = std::max(max_words, (size_t)bk.max_words);
-    e = batch_kernel_attributes(batch_lds_bytes((uint32_t)max_words, p->tail_cap));
+    e = batch_kernel_attributes(batch_lds_bytes((uint32_t)max_words, 512));
     if (e == hipSuccess)
         e = hipMalloc(&p->d_descs, sizeof(ChainDesc) * p->descs.size());
     if (e == hipSuccess)
@@ -364,10 +367,10 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
 
     // launch shape per bucket: cached / tuned block size, grid = resident blocks
     for (auto& bk : p->buckets) {
-        uint32_t threads = autotune_batch_threads(tune_cache_path, bk.L, bk.count, p);
-        const size_t lds = batch_lds_bytes(bk.max_words, p->tail_cap);
+        uint32_t threads = autotune_batch_threads(tune_cache_path, bk.L, bk.paired, bk.count, p);
+        const size_t lds = batch_lds_bytes(bk.max_words, threads);
         int per_cu = 0;
-        e = batch_occupancy(threads, lds, &per_cu);
+        e = batch_occupancy(threads, lds, bk.paired != 0, &per_cu);
         if (e != hipSuccess || per_cu < 1)
             per_cu = 1;
         uint64_t blocks = (uint64_t)per_cu * (uint64_t)n_cu;

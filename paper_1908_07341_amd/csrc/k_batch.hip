@@ -10,12 +10,17 @@
 // tau back and pops the next chain.  HBM is touched only for the initial and
 // final lattices and the traces.
 //
-// Undecided sites (top byte of the uniform equal to the threshold's, about one
-// site in 256) are appended to an LDS list during the half-step, the decided
-// bits are written straight to the LDS lattice, and after one barrier the list
-// is resolved by the whole workgroup with LDS atomic ORs into the lattice.  A
-// lane whose entries would overflow the list resolves them itself before the
-// barrier.
+// Within a half-step each wavefront takes 64-word tiles of the lattice in
+// turn (one word per lane).  Decided bits go straight to the LDS lattice; a
+// word with undecided sites (top byte of the uniform equal to the threshold's,
+// about one site in 256, so 22% of the words) claims a slot of the
+// wavefront's LDS list through a ballot.  Whenever 64 or more words are
+// listed, and once at the end of the half-step, the wavefront resolves its
+// list (one listed word per lane: one tail draw per undecided site) and ors
+// the decided bits into the lattice words, which no other wavefront touches.
+// So a half-step needs a single workgroup barrier, before the next one reads
+// the lattice.  On recorded steps half-step B also accumulates M, A, B: the
+// owner counts the decided sites of its word, the resolver the rest.
 #include "sd_batch.hpp"
 
 namespace sd {
@@ -46,129 +51,104 @@ __device__ __forceinline__ void gather_lds(const HalfCtx& h, uint32_t g, uint64_
     }
 }
 
-struct TailList {
-    uint32_t* site;
-    uint32_t cap;
-    uint32_t* count;   // two counters, used alternately by consecutive half-steps
-    const uint32_t* T; // the chain's thresholds, in LDS
+// Per-wavefront list of words with undecided sites.  A tile adds at most 64
+// entries and the list is resolved as soon as it holds 64, so it never holds
+// more than 127.
+constexpr uint32_t kWListCap = 128;
+
+struct WaveWordList {
+    uint64_t und[kWListCap];   // undecided sites of the listed word
+    uint32_t g[kWListCap];     // its index in the lattice
 };
 
-// Exclusive prefix sum of v across the wavefront and the wavefront total.
-__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v, uint32_t& total) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t incl = v;
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(incl, d, 64);
-        if (lane >= d)
-            incl += t;
-    }
-    total = __shfl(incl, 63, 64);
-    return incl - v;
-}
+// The chain's per-launch constants in LDS.
+struct ChainShared {
+    uint32_t T24[6];   // low 24 bits of the thresholds
+};
 
-constexpr uint32_t kBatchWords = 4;   // words per thread between two slot reservations
+struct ObsSums {
+    int64_t pc = 0, dpair = 0, dself = 0;   // #+1, #differences to up+right, to the partner
+};
 
-// One half-step of the workgroup's chain, src -> dst in LDS.  Each thread
-// handles its words kBatchWords at a time: draws and compares them, writes the
-// decided bits to dst and keeps the undecided masks; then the batch's
-// undecided sites get list slots (one LDS atomic per wavefront).  After a
-// barrier the list is resolved by the whole workgroup (the class of an entry
-// is read back from src) and decisions are or-ed into dst.
-template <int WHICH, bool PAIRED, bool COMPLEMENT>
-__device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams& dp, const PlaneMasks& pm,
-                                              TailList& tl, uint32_t parity) {
-    uint32_t* cnt = tl.count + parity;
-    const uint32_t span = kBatchWords * blockDim.x;
-    for (uint32_t base = 0; base < h.n_words; base += span) {
-        uint64_t und[kBatchWords];
-        uint32_t chain = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < kBatchWords; ++k) {
-            uint32_t g = base + threadIdx.x + k * blockDim.x;
-            // one word at a time (see k_half_step): g depends on the previous word
-            asm volatile("" : "+v"(g) : "v"(chain));
-            und[k] = 0;
-            if (g < h.n_words) {
-                uint64_t c, n1, n2;
-                gather_lds<WHICH>(h, g, c, n1, n2);
-                uint64_t P[8];
-                draw_planes(dp, g, P);
-                const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
-                h.dst[g] = wd.lt;
-                und[k] = wd.und;
-                chain = (uint32_t)wd.lt;
-            }
-        }
-        uint32_t n = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < kBatchWords; ++k)
-            n += (uint32_t)__popcll(und[k]);
-        uint32_t wave_total = 0;
-        const uint32_t offset = wave_exclusive_sum(n, wave_total);
-        uint32_t first = 0;
-        if ((threadIdx.x & 63u) == 63u && wave_total)
-            first = atomicAdd(cnt, wave_total);
-        first = __shfl(first, 63, 64);
-        if (n) {
-            uint32_t slot = first + offset;
-#pragma unroll
-            for (uint32_t k = 0; k < kBatchWords; ++k) {
-                const uint32_t g = base + threadIdx.x + k * blockDim.x;
-                uint64_t u = und[k];
-                while (u) {
-                    const int b = __ffsll((unsigned long long)u) - 1;
-                    u &= u - 1;
-                    if (slot < tl.cap) {
-                        tl.site[slot] = 64u * g + (uint32_t)b;
-                    } else {
-                        uint64_t c, n1, n2;
-                        gather_lds<WHICH>(h, g, c, n1, n2);
-                        if (decide_tail_thr(dp, 64u * g + (uint32_t)b, tl.T[class_at(c, n1, n2, b)]))
-                            h.dst[g] |= 1ull << b;   // only this thread writes word g before the barrier
-                    }
-                    ++slot;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    const uint32_t total = *cnt < tl.cap ? *cnt : tl.cap;
-    for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-        const uint32_t s = tl.site[e];
-        const uint32_t g = s >> 6, b = s & 63u;
+// Resolves the first n entries of the wavefront's list into the lattice.
+template <int WHICH, bool OBS>
+__device__ __forceinline__ void resolve_list(const HalfCtx& h, const DrawParams& dp, const uint32_t* T24,
+                                             WaveWordList& wl, uint32_t n, ObsSums& acc) {
+    for (uint32_t e = threadIdx.x & 63u; e < n; e += 64u) {
+        const uint32_t g = wl.g[e];
+        const uint64_t und = wl.und[e];
         uint64_t c, n1, n2;
         gather_lds<WHICH>(h, g, c, n1, n2);
-        if (decide_tail_thr(dp, s, tl.T[class_at(c, n1, n2, (int)b)]))
-            atomicOr(reinterpret_cast<unsigned long long*>(h.dst + g), 1ull << b);
+        uint64_t r = 0, u = und;
+        while (u) {
+            const int b = __ffsll((unsigned long long)u) - 1;
+            u &= u - 1;
+            if (draw_tail24(dp, 64u * g + (uint32_t)b) < T24[class_at(c, n1, n2, b)])
+                r |= 1ull << b;
+        }
+        h.dst[g] |= r;   // this lane is the only writer of word g until the barrier
+        if constexpr (OBS) {
+            acc.pc += __popcll(r);
+            acc.dpair += __popcll((r ^ n1) & und) + __popcll((r ^ n2) & und);
+            acc.dself += __popcll((r ^ c) & und);
+        }
     }
-    if (threadIdx.x == 0)
-        tl.count[parity ^ 1u] = 0;
-    __syncthreads();
 }
 
-__device__ __forceinline__ void lds_observe(const uint64_t* sig, const uint64_t* tau, const HalfCtx& h,
-                                            int64_t* out3, int64_t* red) {
-    int64_t pc = 0, dpair = 0, dself = 0;
-    for (uint32_t g = threadIdx.x; g < h.n_words; g += blockDim.x) {
-        const uint32_t j = fdiv(g, h.divW);
-        const uint32_t w = g - j * h.W;
-        const uint64_t s = sig[g], t = tau[g];
-        const uint64_t up = tau[(j == h.L - 1 ? 0 : j + 1) * h.W + w];
-        const uint64_t next = tau[j * h.W + (w == h.W - 1 ? 0 : w + 1)];
-        const uint64_t right = (t >> 1) | (next << 63);
-        pc += __popcll(s);
-        dpair += __popcll(s ^ up) + __popcll(s ^ right);
-        dself += __popcll(s ^ t);
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One half-step of the workgroup's chain, src -> dst in LDS, ending with a
+// workgroup barrier.  OBS (half-step B of a recorded step): accumulate the
+// observables of the new pair (dst, src) in acc.
+template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
+__device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams& dp, const PlaneMasks& pm,
+                                              const uint32_t* T24, WaveWordList& wl, ObsSums& acc) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t n_waves = blockDim.x >> 6;
+    const uint32_t n_tiles = (h.n_words + 63u) / 64u;
+    uint32_t listed = 0;   // wavefront-uniform
+    for (uint32_t tile = threadIdx.x >> 6; tile < n_tiles; tile += n_waves) {
+        const uint32_t g = 64u * tile + lane;
+        const bool active = g < h.n_words;
+        uint64_t c = 0, n1 = 0, n2 = 0;
+        if (active)
+            gather_lds<WHICH>(h, g, c, n1, n2);
+        uint64_t P[8];
+        draw_planes(dp, active ? g : 0u, P);
+        const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
+        const uint64_t und = active ? wd.und : 0ull;
+        if (active) {
+            h.dst[g] = wd.lt;
+            if constexpr (OBS) {
+                acc.pc += __popcll(wd.lt);
+                acc.dpair += __popcll((wd.lt ^ n1) & ~und) + __popcll((wd.lt ^ n2) & ~und);
+                acc.dself += __popcll((wd.lt ^ c) & ~und);
+            }
+        }
+        const uint64_t need = __ballot(und != 0);
+        if (und != 0) {
+            const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            wl.und[e] = und;
+            wl.g[e] = g;
+        }
+        listed += (uint32_t)__popcll(need);
+        if (listed >= 64u) {
+            wave_sync_lds();
+            resolve_list<WHICH, OBS>(h, dp, T24, wl, listed, acc);
+            wave_sync_lds();
+            listed = 0;
+        }
     }
-    int64_t v[3] = {pc, dpair, dself};
-    block_sum_i64<3>(v, red);
-    if (threadIdx.x == 0) {
-        const int64_t n = (int64_t)h.n_words * 64;
-        out3[0] = 2 * v[0] - n;
-        out3[1] = 2 * n - 2 * v[1];
-        out3[2] = n - 2 * v[2];
+    if (listed) {
+        wave_sync_lds();
+        resolve_list<WHICH, OBS>(h, dp, T24, wl, listed, acc);
     }
+    __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t lds_bytes_to_bits4(uint32_t x) {
@@ -182,38 +162,69 @@ __device__ __forceinline__ uint32_t lds_bits4_to_bytes(uint32_t n) {
     return z | ((w << 8) - w);
 }
 
+// Observables of the pair (sig, tau) as sums over the workgroup's threads
+// (a separate pass, used for chains with the general compare).
+__device__ __forceinline__ ObsSums lds_observe(const uint64_t* sig, const uint64_t* tau, const HalfCtx& h) {
+    ObsSums acc;
+    for (uint32_t g = threadIdx.x; g < h.n_words; g += blockDim.x) {
+        const uint32_t j = fdiv(g, h.divW);
+        const uint32_t w = g - j * h.W;
+        const uint64_t s = sig[g], t = tau[g];
+        const uint64_t up = tau[(j == h.L - 1 ? 0 : j + 1) * h.W + w];
+        const uint64_t next = tau[j * h.W + (w == h.W - 1 ? 0 : w + 1)];
+        const uint64_t right = (t >> 1) | (next << 63);
+        acc.pc += __popcll(s);
+        acc.dpair += __popcll(s ^ up) + __popcll(s ^ right);
+        acc.dself += __popcll(s ^ t);
+    }
+    return acc;
+}
+
+// Steps of one chain.  Paired chains fold the observables into half-step B;
+// the general compare (rare: some field is exactly zero) leaves them to a
+// separate pass so that its register count stays low.
 template <bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA, const HalfCtx& hB, DrawParams dp,
-                                          TailList& tl, int64_t* trace, int64_t* red) {
+                                          const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red) {
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
-    uint32_t parity = 0;
     for (uint32_t m = 0; m < a.k_steps; ++m) {
         const uint32_t n = a.step0 + m;
+        ObsSums acc;
         dp.t = 2u * n;
-        lds_half_step<0, PAIRED, COMPLEMENT>(hA, dp, pm, tl, parity);
-        parity ^= 1u;
+        lds_half_step<0, PAIRED, COMPLEMENT, false>(hA, dp, pm, T24, wl, acc);
         dp.t = 2u * n + 1u;
-        lds_half_step<1, PAIRED, COMPLEMENT>(hB, dp, pm, tl, parity);
-        parity ^= 1u;
-        if (trace && (m + 1) % a.obs_every == 0)
-            lds_observe(hB.dst, hA.dst, hA, trace + 3u * (size_t)((m + 1) / a.obs_every - 1), red);
+        if (trace && (m + 1) % a.obs_every == 0) {
+            if constexpr (PAIRED) {
+                lds_half_step<1, PAIRED, COMPLEMENT, true>(hB, dp, pm, T24, wl, acc);
+            } else {
+                lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
+                acc = lds_observe(hB.dst, hA.dst, hA);
+            }
+            int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
+            block_sum_i64<3>(v, red);
+            if (threadIdx.x == 0) {
+                int64_t* out3 = trace + 3u * (size_t)((m + 1) / a.obs_every - 1);
+                const int64_t sites = (int64_t)hA.n_words * 64;
+                out3[0] = 2 * v[0] - sites;
+                out3[1] = 2 * sites - 2 * v[1];
+                out3[2] = sites - 2 * v[2];
+            }
+        } else {
+            lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
+        }
     }
 }
 
-template <bool COMPLEMENT>
+// PAIRED: every chain of the launch has a paired threshold table.
+template <bool COMPLEMENT, bool PAIRED>
 __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t s_chain;
-    __shared__ uint32_t s_count[2];
-    __shared__ uint32_t s_T[6];
+    __shared__ ChainShared s_ch;
     __shared__ int64_t red[3 * 8];
     uint64_t* sig = smem;
     uint64_t* tau = smem + a.max_words;
-    TailList tl;
-    tl.site = reinterpret_cast<uint32_t*>(tau + a.max_words);
-    tl.cap = a.tail_cap;
-    tl.count = s_count;
-    tl.T = s_T;
+    WaveWordList& wl = reinterpret_cast<WaveWordList*>(tau + a.max_words)[threadIdx.x >> 6];
 
     for (uint32_t iter = 0;; ++iter) {
         ChainDesc cd;
@@ -260,13 +271,9 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
                 sig[g] = src[g];
         }
         if (threadIdx.x == 0) {
-            s_count[0] = 0;
-            s_count[1] = 0;
-        }
-        if (threadIdx.x == 0) {
 #pragma unroll
             for (int i = 0; i < 6; ++i)
-                s_T[i] = cd.T[i];
+                s_ch.T24[i] = cd.T[i] & 0xFFFFFFu;
         }
         __syncthreads();
 
@@ -281,10 +288,7 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         dp.rng_xor = COMPLEMENT ? 0xFFFFFFFFu : 0u;
         int64_t* trace = a.traces ? a.traces + cd.trace_offset : nullptr;
 
-        if (cd.paired)
-            run_steps<true, COMPLEMENT>(a, hA, hB, dp, tl, trace, red);
-        else
-            run_steps<false, COMPLEMENT>(a, hA, hB, dp, tl, trace, red);
+        run_steps<PAIRED, COMPLEMENT>(a, hA, hB, dp, s_ch.T24, wl, trace, red);
 
         // write sigma and tau back
         if (a.int8_io) {
@@ -326,16 +330,20 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
 
 }  // namespace
 
-size_t batch_lds_bytes(uint32_t max_words, uint32_t tail_cap) {
-    return (size_t)2 * max_words * sizeof(uint64_t) + (size_t)tail_cap * sizeof(uint32_t);
+size_t batch_lds_bytes(uint32_t max_words, uint32_t threads) {
+    return (size_t)2 * max_words * sizeof(uint64_t) + (size_t)((threads + 63u) / 64u) * sizeof(WaveWordList);
 }
 
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st) {
-    const size_t lds = batch_lds_bytes(a.max_words, a.tail_cap);
-    if (a.rng_xor)
-        hipLaunchKernelGGL(k_batch_chains<true>, dim3(blocks), dim3(threads), lds, st, a);
+    const size_t lds = batch_lds_bytes(a.max_words, threads);
+    if (a.rng_xor && a.paired)
+        hipLaunchKernelGGL((k_batch_chains<true, true>), dim3(blocks), dim3(threads), lds, st, a);
+    else if (a.rng_xor)
+        hipLaunchKernelGGL((k_batch_chains<true, false>), dim3(blocks), dim3(threads), lds, st, a);
+    else if (a.paired)
+        hipLaunchKernelGGL((k_batch_chains<false, true>), dim3(blocks), dim3(threads), lds, st, a);
     else
-        hipLaunchKernelGGL(k_batch_chains<false>, dim3(blocks), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((k_batch_chains<false, false>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -345,16 +353,23 @@ hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st) {
 }
 
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_chains<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
-    if (e != hipSuccess)
-        return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_chains<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
+    const void* kernels[4] = {reinterpret_cast<const void*>(&k_batch_chains<false, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, true>)};
+    for (const void* k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t batch_occupancy(uint32_t threads, size_t lds, int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false>, (int)threads, lds);
+hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, int* blocks_per_cu) {
+    if (paired)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false, true>, (int)threads,
+                                                            lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false, false>, (int)threads, lds);
 }
 
 }  // namespace sd

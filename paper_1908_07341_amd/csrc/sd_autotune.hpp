@@ -24,6 +24,7 @@ std::string device_arch();
 long tune_pick(const std::vector<long>& candidates, const std::function<double(long)>& measure);
 
 // Block size of the batched kernel for chains of size L (see batch.cpp).
-uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t n_chains, sd_batch_plan* plan);
+uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t paired, uint32_t n_chains,
+                                sd_batch_plan* plan);
 
 }  // namespace sd

@@ -33,15 +33,17 @@ struct BatchArgs {
     uint32_t obs_every;
     uint32_t rng_xor;
     uint32_t max_words;      // capacity (64-bit words) of each LDS lattice buffer
-    uint32_t tail_cap;       // capacity of the LDS list of undecided sites
     uint32_t int8_io;        // lattices in global memory are int8 (L % 64 == 0)
+    uint32_t paired;         // every chain of the launch has a paired threshold table
 };
 
-size_t batch_lds_bytes(uint32_t max_words, uint32_t tail_cap);
+// Dynamic LDS of a launch: the two lattice buffers and one list of undecided
+// words per wavefront of a threads-sized workgroup.
+size_t batch_lds_bytes(uint32_t max_words, uint32_t threads);
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds);
-hipError_t batch_occupancy(uint32_t threads, size_t lds, int* blocks_per_cu);
+hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, int* blocks_per_cu);
 
 // Lattices with at most this many 64-site words run in one workgroup with
 // LDS-resident lattices when sd_run is called without SD_FLAG_GLOBAL_KERNELS.
