@@ -283,11 +283,12 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
     nb = sd.sd_lattice_bytes(L, sd.SD_P64)
     n_lat = 2 * k + 1
     traj = torch.empty((n_traj, n_lat, nb // 8), dtype=torch.int64, device="cuda")
-    t0 = time.perf_counter()
+    starts = torch.empty((n_traj, nb // 8), dtype=torch.int64, device="cuda")
     for a in range(n_traj):
-        s0 = traj[a, 0]
-        sd.sd_init(s0, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, a)
-        sd.sd_trajectory(s0, traj[a], L, sd.SD_P64, J, q, 1, a, 0, k)
+        sd.sd_init(starts[a], L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sd.sd_trajectories(starts, traj, n_traj, L, sd.SD_P64, J, q, 1, 0, 0, k)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     counts = torch.empty(12, dtype=torch.int64, device="cuda")

@@ -176,6 +176,22 @@ SD_API sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_
                                uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, void* hip_stream);
 
 /*
+ * n_traj trajectories of one (J, q) at once: trajectory a starts from the
+ * packed lattice sigma0 + a * sd_lattice_bytes(L, layout) (device) with
+ * stream id stream0 + a, and its 2*k_steps + 1 lattices go to
+ * traj + a * (2*k_steps + 1) * sd_lattice_bytes(L, layout), laid out as
+ * sd_trajectory writes them; the result is that of n_traj calls of
+ * sd_trajectory.  When L is a multiple of 64 and a lattice pair fits in LDS
+ * (L <= 512 on gfx950) every trajectory runs in one workgroup of a single
+ * launch with its lattices in LDS; otherwise the trajectories are recorded
+ * one after the other.  The start lattices must not overlap the
+ * trajectories; pointers 8-byte aligned; stream0 + n_traj <= 2^32.
+ */
+SD_API sd_status sd_trajectories(const void* sigma0, void* traj, int32_t n_traj, int32_t L, int32_t layout, double J,
+                                 double q, uint64_t seed, uint32_t stream0, uint64_t step0, uint32_t k_steps,
+                                 void* hip_stream);
+
+/*
  * Sufficient statistics of the log-likelihood of n_traj packed (SD_P64)
  * trajectories of n_lat lattices each (traj[a][m][L][L/64], device, as written
  * by sd_trajectory): counts12[2*idx + [s = +1]] (device, 12 int64) counts the

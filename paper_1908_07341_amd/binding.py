@@ -49,6 +49,7 @@ SIGNATURES = {
     "sd_batch_run_direct": (_I32, [_VP, _VP, _VP, _U64, _VP]),
     "sd_batch_plan_destroy": (None, [_VP]),
     "sd_trajectory": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP]),
+    "sd_trajectories": (_I32, [_VP, _VP, _I32, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP]),
     "sd_loglik_counts": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
@@ -152,6 +153,11 @@ def sd_corr_row(sigma, L, layout, rmax, out, hip_stream=None) -> None:
 def sd_trajectory(sigma0, traj, L, layout, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:
     _check(lib().sd_trajectory(_ptr(sigma0), _ptr(traj), L, layout, float(J), float(q), seed, stream, step0,
                                k_steps, _stream(hip_stream)))
+
+
+def sd_trajectories(sigma0, traj, n_traj, L, layout, J, q, seed, stream0, step0, k_steps, hip_stream=None) -> None:
+    _check(lib().sd_trajectories(_ptr(sigma0), _ptr(traj), n_traj, L, layout, float(J), float(q), seed, stream0, step0,
+                                 k_steps, _stream(hip_stream)))
 
 
 def sd_loglik_counts(traj, n_traj, n_lat, L, counts12, hip_stream=None) -> None:

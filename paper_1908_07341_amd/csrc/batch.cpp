@@ -217,6 +217,33 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
 }
 
 // Single-chain LDS-resident run used by sd_run for small lattices.
+hipError_t launch_trajectories_lds(const void* sigma0, void* traj, uint32_t n_traj, int32_t L, double J, double q,
+                                   uint64_t seed, uint32_t stream0, uint64_t step0, uint32_t k_steps,
+                                   uint32_t threads, hipStream_t st) {
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    threshold_table(J, q, a.single.T);
+    a.single.paired = thresholds_paired(a.single.T) ? 1u : 0u;
+    a.single.L = (uint32_t)L;
+    a.single.stream = stream0;
+    a.single.divW = make_fastdiv((uint32_t)L / 64u);
+    a.single_sig = static_cast<uint8_t*>(const_cast<void*>(sigma0));
+    a.n_uniform = n_traj;
+    a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(seed >> 32);
+    a.step0 = (uint32_t)step0;
+    a.k_steps = k_steps;
+    a.obs_every = 1;
+    a.max_words = (uint32_t)L * ((uint32_t)L / 64u);
+    a.paired = a.single.paired;
+    a.traj = static_cast<uint8_t*>(traj);
+    a.traj_chain_bytes = (2ull * k_steps + 1ull) * a.max_words * sizeof(uint64_t);
+    hipError_t e = batch_kernel_attributes(batch_lds_bytes(a.max_words, threads));
+    if (e != hipSuccess)
+        return e;
+    return launch_batch_chains(a, n_traj, threads, st);
+}
+
 hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_io, double J, double q,
                                    uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,
                                    uint32_t obs_every, uint32_t flags, uint32_t threads, hipStream_t st) {

@@ -183,15 +183,26 @@ __device__ __forceinline__ ObsSums lds_observe(const uint64_t* sig, const uint64
 // Steps of one chain.  Paired chains fold the observables into half-step B;
 // the general compare (rare: some field is exactly zero) leaves them to a
 // separate pass so that its register count stays low.
+// Copy of an LDS lattice to global memory (the workgroup's threads).
+__device__ __forceinline__ void store_lattice(uint64_t* out, const uint64_t* lat, uint32_t n_words) {
+    for (uint32_t g = threadIdx.x; g < n_words; g += blockDim.x)
+        out[g] = lat[g];
+}
+
 template <bool PAIRED, bool COMPLEMENT>
 __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA, const HalfCtx& hB, DrawParams dp,
-                                          const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red) {
+                                          const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red,
+                                          uint64_t* traj) {
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     for (uint32_t m = 0; m < a.k_steps; ++m) {
         const uint32_t n = a.step0 + m;
         ObsSums acc;
         dp.t = 2u * n;
         lds_half_step<0, PAIRED, COMPLEMENT, false>(hA, dp, pm, T24, wl, acc);
+        // (each half-step ends with a barrier, so a copy made here is complete
+        // before the lattice is next overwritten, two half-steps later)
+        if (traj)
+            store_lattice(traj + (size_t)(2u * m + 1u) * hA.n_words, hA.dst, hA.n_words);
         dp.t = 2u * n + 1u;
         if (trace && (m + 1) % a.obs_every == 0) {
             if constexpr (PAIRED) {
@@ -212,6 +223,8 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA,
         } else {
             lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
         }
+        if (traj)
+            store_lattice(traj + (size_t)(2u * m + 2u) * hB.n_words, hB.dst, hB.n_words);
     }
 }
 
@@ -236,6 +249,11 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
             if (qi >= a.n_chains)
                 break;
             cd = a.chains[a.order[qi]];
+        } else if (a.n_uniform) {
+            if (iter > 0 || blockIdx.x >= a.n_uniform)
+                break;
+            cd = a.single;
+            cd.stream += blockIdx.x;
         } else {
             if (iter > 0 || blockIdx.x != 0)
                 break;
@@ -266,7 +284,9 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
                 sig[g] = bits;
             }
         } else {
-            const uint64_t* src = reinterpret_cast<const uint64_t*>(a.counter ? a.lattices + cd.sig_offset : a.single_sig);
+            const uint64_t* src =
+                a.counter ? reinterpret_cast<const uint64_t*>(a.lattices + cd.sig_offset)
+                          : reinterpret_cast<const uint64_t*>(a.single_sig) + (size_t)(a.n_uniform ? blockIdx.x : 0u) * n_words;
             for (uint32_t g = threadIdx.x; g < n_words; g += blockDim.x)
                 sig[g] = src[g];
         }
@@ -287,8 +307,15 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         dp.tag2 = 0;
         dp.rng_xor = COMPLEMENT ? 0xFFFFFFFFu : 0u;
         int64_t* trace = a.traces ? a.traces + cd.trace_offset : nullptr;
+        uint64_t* traj = a.traj ? reinterpret_cast<uint64_t*>(a.traj + (size_t)blockIdx.x * a.traj_chain_bytes) : nullptr;
+        if (traj)
+            store_lattice(traj, sig, n_words);
 
-        run_steps<PAIRED, COMPLEMENT>(a, hA, hB, dp, s_ch.T24, wl, trace, red);
+        run_steps<PAIRED, COMPLEMENT>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj);
+        if (traj) {
+            __syncthreads();
+            continue;
+        }
 
         // write sigma and tau back
         if (a.int8_io) {

@@ -1,6 +1,7 @@
 // Host side of the trajectory generator and the log-likelihood entry points.
 #include <cmath>
 
+#include "sd_batch.hpp"
 #include "sd_host.hpp"
 #include "sd_loglik.hpp"
 
@@ -43,6 +44,52 @@ sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_t layou
         }
     }
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_trajectory");
+}
+
+sd_status sd_trajectories(const void* sigma0, void* traj, int32_t n_traj, int32_t L, int32_t layout, double J,
+                          double q, uint64_t seed, uint32_t stream0, uint64_t step0, uint32_t k_steps,
+                          void* hip_stream) {
+    if (layout != SD_P64 && layout != SD_P32)
+        return fail(SD_EUNSUPPORTED, "sd_trajectories: trajectories are stored packed (SD_P64 or SD_P32)");
+    if (n_traj < 0 || !layout_supported(L, layout) || (n_traj > 0 && (!sigma0 || !traj)))
+        return fail(SD_EINVAL, "sd_trajectories: bad count, lattice size or null pointer");
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "sd_trajectories: J and q must be finite");
+    if (step0 + (uint64_t)k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "sd_trajectories: step indices must stay below 2^29");
+    if ((uint64_t)stream0 + (uint64_t)n_traj > (1ull << 32))
+        return fail(SD_EINVAL, "sd_trajectories: stream ids must stay below 2^32");
+    if ((reinterpret_cast<uintptr_t>(sigma0) | reinterpret_cast<uintptr_t>(traj)) & 7u)
+        return fail(SD_EINVAL, "sd_trajectories: pointers must be 8-byte aligned");
+    if (n_traj == 0)
+        return SD_OK;
+    const size_t bytes = lattice_bytes(L, layout);
+    const size_t per = bytes * (2 * (size_t)k_steps + 1);
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(sigma0), t0 = reinterpret_cast<uintptr_t>(traj);
+    if (s0 < t0 + per * (size_t)n_traj && t0 < s0 + bytes * (size_t)n_traj)
+        return fail(SD_EINVAL, "sd_trajectories: the start lattices overlap the trajectories");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_trajectories");
+    const uint32_t threads = n_words >= 2048u ? 512u : 256u;
+    if (L % 64 == 0 && batch_lds_bytes(n_words, threads) <= (size_t)max_lds) {
+        e = launch_trajectories_lds(sigma0, traj, (uint32_t)n_traj, L, J, q, seed, stream0, step0, k_steps, threads,
+                                    st);
+        return e == hipSuccess ? SD_OK : hip_fail(e, "sd_trajectories");
+    }
+    for (int32_t a = 0; a < n_traj; ++a) {
+        const sd_status r = sd_trajectory(static_cast<const uint8_t*>(sigma0) + (size_t)a * bytes,
+                                          static_cast<uint8_t*>(traj) + (size_t)a * per, L, layout, J, q, seed,
+                                          stream0 + (uint32_t)a, step0, k_steps, hip_stream);
+        if (r != SD_OK)
+            return r;
+    }
+    return SD_OK;
 }
 
 sd_status sd_loglik_counts(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* counts12,

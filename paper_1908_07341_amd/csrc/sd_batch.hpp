@@ -35,6 +35,12 @@ struct BatchArgs {
     uint32_t max_words;      // capacity (64-bit words) of each LDS lattice buffer
     uint32_t int8_io;        // lattices in global memory are int8 (L % 64 == 0)
     uint32_t paired;         // every chain of the launch has a paired threshold table
+    uint32_t n_uniform;      // counter null and n_uniform > 0: workgroup b runs `single` with stream
+                             // single.stream + b from packed sigma single_sig + b * lattice bytes
+    uint8_t* traj;           // non-null: workgroup b writes lattice x of its trajectory (x = 0 the
+                             // start, 2m+1 after half-step A of step m, 2m+2 after B) to
+                             // traj + b * traj_chain_bytes + x * lattice bytes, and skips the write-back
+    uint64_t traj_chain_bytes;
 };
 
 // Dynamic LDS of a launch: the two lattice buffers and one list of undecided
@@ -48,6 +54,12 @@ hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, int* block
 // Lattices with at most this many 64-site words run in one workgroup with
 // LDS-resident lattices when sd_run is called without SD_FLAG_GLOBAL_KERNELS.
 constexpr uint32_t kSingleLdsMaxWords = 1024;
+
+// n_traj packed trajectories of one (J, q) with streams stream0 + a in one
+// launch (workgroup a runs trajectory a); L * L / 64 words must fit in LDS.
+hipError_t launch_trajectories_lds(const void* sigma0, void* traj, uint32_t n_traj, int32_t L, double J, double q,
+                                   uint64_t seed, uint32_t stream0, uint64_t step0, uint32_t k_steps,
+                                   uint32_t threads, hipStream_t st);
 
 hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_io, double J, double q,
                                    uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,

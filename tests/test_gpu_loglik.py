@@ -56,6 +56,32 @@ def test_trajectory_and_counts_match_oracle(oracle, L, n_traj, k):
     assert not one.any()
 
 
+@pytest.mark.parametrize("L,layout,n_traj,k", [(64, sd.SD_P64, 5, 17), (256, sd.SD_P64, 3, 6),
+                                               (512, sd.SD_P32, 2, 3), (96, sd.SD_P32, 2, 4)])
+def test_trajectories_batched_match_single(oracle, L, layout, n_traj, k):
+    # one launch for all trajectories (LDS-resident lattices when L % 64 == 0),
+    # one sd_trajectory call per trajectory otherwise; both equal the
+    # one-by-one recording, and trajectory 0 equals the oracle's
+    J, q, stream0 = 0.6, 0.3, 7
+    print(f"batched trajectories L={L} layout={layout} n={n_traj} k={k}", flush=True)
+    nb = sd.sd_lattice_bytes(L, layout)
+    starts = torch.empty((n_traj, nb), dtype=torch.uint8, device="cuda")
+    for a in range(n_traj):
+        sd.sd_init(starts[a], L, layout, sd.SD_INIT_RANDOM, 0.5, SEED, stream0 + a)
+    got = torch.full((n_traj, 2 * k + 1, nb), 0x5A, dtype=torch.uint8, device="cuda")
+    sd.sd_trajectories(starts, got, n_traj, L, layout, J, q, SEED, stream0, 3, k)
+    ref = torch.empty_like(got)
+    for a in range(n_traj):
+        sd.sd_trajectory(starts[a], ref[a], L, layout, J, q, SEED, stream0 + a, 3, k)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    s0 = oracle.init(L, oracle.INIT_RANDOM, 0.5, SEED, stream0)
+    X = oracle.trajectory(s0, J, q, SEED, stream0, 3, k)
+    host = got[0].cpu().numpy()
+    for m in range(2 * k + 1):
+        assert np.array_equal(inputs.unpack_bits(host[m].view(np.uint64), L), X[m]), m
+
+
 def _fp64(oracle, counts, J, q):
     return oracle.loglik(counts, J, q), oracle.loglik_grad(counts, J, q)
 
