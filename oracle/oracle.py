@@ -69,6 +69,8 @@ def lib():
         L.or_observe.restype = None
         L.or_corr_row.argtypes = [i8p, c.c_int, c.c_int, i64p]
         L.or_corr_row.restype = c.c_int
+        L.or_corr_diag.argtypes = [i8p, c.c_int, c.c_int, i64p]
+        L.or_corr_diag.restype = c.c_int
         L.or_run.argtypes = [i8p, i8p, c.c_int, c.c_double, c.c_double, c.c_uint64, c.c_uint32,
                              c.c_uint64, c.c_uint32, i64p, c.c_uint32]
         L.or_run.restype = c.c_int
@@ -179,6 +181,17 @@ def corr_row(sigma: np.ndarray, rmax: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("rmax out of range")
     return out
+
+
+def corr_diag(sigma: np.ndarray, lmax: int) -> np.ndarray:
+    """[2, lmax+1] int64: row 0 the SW-NE sums sum_x s(i,j) s(i+l,j+l), row 1 the
+    NW-SE sums sum_x s(i,j) s(i+l,j-l) (section 3.3, Table 1)."""
+    sigma = _lat(sigma)
+    out = np.zeros(2 * (lmax + 1), dtype=np.int64)
+    rc = lib().or_corr_diag(_p(sigma, ctypes.c_int8), sigma.shape[0], lmax, _p(out, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("lmax out of range")
+    return out.reshape(2, lmax + 1)
 
 
 def run(sigma: np.ndarray, J: float, q: float, seed: int, stream: int, step0: int, k: int,

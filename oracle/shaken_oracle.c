@@ -327,6 +327,28 @@ OR_EXPORT int or_corr_row(const int8_t* sigma, int L, int rmax, int64_t* out)
     return 0;
 }
 
+/* Diagonal correlation sums of section 3.3 (Table 1), brute force:           */
+/* out[l] = sum_x sigma(i,j) sigma(i+l, j+l)            (SW-NE direction),      */
+/* out[lmax+1+l] = sum_x sigma(i,j) sigma(i+l, j-l)     (NW-SE direction),      */
+/* l = 0 .. lmax, coordinates mod L.                                             */
+OR_EXPORT int or_corr_diag(const int8_t* sigma, int L, int lmax, int64_t* out)
+{
+    if (lmax < 0 || lmax >= L)
+        return -1;
+    for (int l = 0; l <= lmax; ++l) {
+        int64_t up = 0, down = 0;
+        for (int j = 0; j < L; ++j)
+            for (int i = 0; i < L; ++i) {
+                const int64_t s = sigma[or_site(L, i, j)];
+                up += s * sigma[or_site(L, i + l, j + l)];
+                down += s * sigma[or_site(L, i + l, j - l)];
+            }
+        out[l] = up;
+        out[lmax + 1 + l] = down;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Chain driver: k full steps from step index step0, recording (M, A, B) on the */
 /* pair (sigma_n, tau_n) after every obs_every-th step (obs may be NULL).       */

@@ -120,6 +120,31 @@ def test_row_correlation_brute_force(oracle):
         oracle.corr_row(s, L)
 
 
+def test_diagonal_correlation_brute_force(oracle):
+    # section 3.3 / Table 1: SW-NE pairs x, x + (l, l); NW-SE pairs x, x + (l, -l)
+    # (i = column = axis 1, j = row = axis 0 of the array)
+    rng = np.random.default_rng(13)
+    for L in (2, 3, 7, 16):
+        s = rng.choice(np.array([-1, 1], np.int8), size=(L, L))
+        D = oracle.corr_diag(s, L - 1)
+        S = s.astype(np.int64)
+        for l in range(L):
+            assert D[0, l] == (S * np.roll(S, (-l, -l), axis=(0, 1))).sum()
+            assert D[1, l] == (S * np.roll(S, (l, -l), axis=(0, 1))).sum()
+        assert D[0, 0] == D[1, 0] == L * L
+        assert all(D[d, l] == D[d, L - l] for d in range(2) for l in range(1, L))
+    # a lattice constant along the NW-SE diagonals (a function of i + j) has
+    # NW-SE sums L^2 at every l; along SW-NE the same lattice decorrelates
+    L = 6
+    i, j = np.meshgrid(np.arange(L), np.arange(L), indexing="xy")
+    s = np.where((i + j) % 3 == 0, 1, -1).astype(np.int8)
+    D = oracle.corr_diag(s, L - 1)
+    assert np.all(D[1] == L * L)
+    assert D[0, 1] == (s.astype(np.int64) * np.roll(s, (-1, -1), axis=(0, 1))).sum() < L * L
+    with pytest.raises(ValueError):
+        oracle.corr_diag(s, L)
+
+
 def test_init_kinds(oracle):
     L = 64
     assert np.all(oracle.init(L, 0) == 1)
