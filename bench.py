@@ -146,6 +146,8 @@ def parse():
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 512 MiB device copy first (counter calibration runs)")
+    p.add_argument("--table1", action="store_true",
+                   help="only the diagonal-correlation comparison with Table 1 (32x32, all (q, J) rows)")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="write the half-step traffic record from two rocprofv3 counter CSVs and exit")
     return p.parse_args()
@@ -325,6 +327,48 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
             "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est}
 
 
+def bench_table1(sd, torch, burn=2000, n_meas=4000, every=5, L=32):
+    """Time-averaged diagonal correlations C(l) = D(l) / L^2 on a 32x32 torus at
+    every (q, J) row of Table 1 (section 3.3), next to the printed values
+    (tests/golden/table1_diagonal_correlations.txt)."""
+    ells = [1, 2, 4, 8, 16]
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1_diagonal_correlations.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            qs, Js, sup, d, *vals = line.split()
+            paper.setdefault((float(qs), float(Js)), {"supercritical": sup == "1"})[d] = [float(v) for v in vals]
+    layout, lmax = sd.SD_P32, max(ells)
+    rows = []
+    t0 = time.perf_counter()
+    for idx, ((q, J), ref) in enumerate(paper.items()):
+        sigma, tau = sd.new_lattice(L, layout), sd.new_lattice(L, layout)
+        sd.sd_init(sigma, L, layout, sd.SD_INIT_RANDOM, 0.5, 1, idx)
+        sd.sd_run(sigma, tau, L, layout, J, q, 1, idx, 0, burn, None, 0)
+        acc = torch.zeros(2 * (lmax + 1), dtype=torch.int64, device="cuda")
+        out = torch.empty_like(acc)
+        step = burn
+        for _ in range(n_meas):
+            sd.sd_run(sigma, tau, L, layout, J, q, 1, idx, step, every, None, 0)
+            step += every
+            sd.sd_corr_diag(sigma, L, layout, lmax, out)
+            acc += out
+        C = (acc.cpu().numpy().reshape(2, lmax + 1) / (n_meas * L * L))
+        ours = {"NW-SE": [round(float(C[1, l]), 3) for l in ells], "SW-NE": [round(float(C[0, l]), 3) for l in ells]}
+        rows.append({"q": q, "J": J, "supercritical": ref["supercritical"], "ours": ours,
+                     "paper": {"NW-SE": ref["NW-SE"], "SW-NE": ref["SW-NE"]}})
+    torch.cuda.synchronize()
+    agree = sum((r["ours"]["NW-SE"][0] > r["ours"]["SW-NE"][0]) == (r["paper"]["NW-SE"][0] > r["paper"]["SW-NE"][0])
+                for r in rows)
+    mad = float(np.mean([abs(a - b) for r in rows for d in ("NW-SE", "SW-NE")
+                         for a, b in zip(r["ours"][d], r["paper"][d])]))
+    return {"workload": f"{L}x{L} torus, random start, {burn} burn-in steps, {n_meas} measurements every {every} "
+                        f"steps, seed 1, stream = row index", "l": ells, "rows": rows,
+            "sign_of_NWSE_minus_SWNE_at_l1_agrees": f"{agree}/{len(rows)}", "mean_abs_diff_vs_paper": mad,
+            "seconds": time.perf_counter() - t0}
+
+
 def _fp64_grad(c, J, q):
     gJ = gq = 0.0
     for k in range(3):
@@ -358,6 +402,9 @@ def main():
     sd.lib()
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.table1:
+        print(json.dumps({"table1": bench_table1(sd, torch)}), flush=True)
+        return
     L, K, W = args.L, args.steps, args.warmup
     if args.calibrate_copy:
         calibrate_copy(torch)

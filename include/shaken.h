@@ -159,6 +159,15 @@ SD_API sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32
 SD_API sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax, int64_t* out,
                       void* hip_stream);
 
+/*
+ * Diagonal correlation sums of section 3.3 (Table 1) for l = 0 .. lmax
+ * (0 <= lmax < L): out[l] = sum_x sigma_(i,j) sigma_(i+l, j+l) (SW-NE) and
+ * out[lmax + 1 + l] = sum_x sigma_(i,j) sigma_(i+l, j-l) (NW-SE), coordinates
+ * mod L, exact int64 (device, 2 * (lmax + 1) entries).  C = sum / L^2.
+ */
+SD_API sd_status sd_corr_diag(const void* sigma, int32_t L, int32_t layout, int32_t lmax, int64_t* out,
+                              void* hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Trajectories and their log-likelihood (differentiation with respect to     */
 /* (J, q)).                                                                   */

@@ -37,6 +37,7 @@ SIGNATURES = {
     "sd_run": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
     "sd_observe": (_I32, [_VP, _VP, _I32, _I32, _VP, _VP]),
     "sd_corr_row": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_corr_diag": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_batch_plan_create": (_I32, [ctypes.POINTER(_VP), ctypes.POINTER(sd_chain_desc), _I32, _I32, _U64, _U32,
                                      _U32, _U32, ctypes.c_char_p]),
     "sd_batch_lattice_bytes": (ctypes.c_size_t, [_VP]),
@@ -148,6 +149,10 @@ def sd_observe(sigma, tau, L, layout, out3, hip_stream=None) -> None:
 
 def sd_corr_row(sigma, L, layout, rmax, out, hip_stream=None) -> None:
     _check(lib().sd_corr_row(_ptr(sigma), L, layout, rmax, _ptr(out), _stream(hip_stream)))
+
+
+def sd_corr_diag(sigma, L, layout, lmax, out, hip_stream=None) -> None:
+    _check(lib().sd_corr_diag(_ptr(sigma), L, layout, lmax, _ptr(out), _stream(hip_stream)))
 
 
 def sd_trajectory(sigma0, traj, L, layout, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:

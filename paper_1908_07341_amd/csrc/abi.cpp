@@ -362,6 +362,20 @@ sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
 }
 
+sd_status sd_corr_diag(const void* sigma, int32_t L, int32_t layout, int32_t lmax, int64_t* out,
+                       void* hip_stream) {
+    sd_status s = check_lattice(sigma, L, layout, "sd_corr_diag");
+    if (s != SD_OK)
+        return s;
+    if (!out)
+        return fail(SD_EINVAL, "sd_corr_diag: null output");
+    if (lmax < 0 || lmax >= L)
+        return fail(SD_EINVAL, "sd_corr_diag: lmax must satisfy 0 <= lmax < L");
+    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    hipError_t e = launch_corr_diag(klay, sigma, make_geom(L, klay), lmax, out, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_diag");
+}
+
 sd_status sd_tune(int32_t L, int32_t layout, const char* tune_cache_path, void* hip_stream) {
     if (!layout_supported(L, layout))
         return fail(SD_EINVAL, "sd_tune: unsupported (L=%d, layout=%d)", L, layout);

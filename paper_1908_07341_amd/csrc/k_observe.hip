@@ -131,6 +131,54 @@ __global__ __launch_bounds__(256) void k_corr_row(const void* __restrict__ sigma
         atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)acc);
 }
 
+// Diagonal correlation sums (section 3.3, Table 1).  Block (x, y): direction
+// d = x / (lmax + 1) (0: partner (i+l, j+l), SW-NE; 1: partner (i+l, j-l),
+// NW-SE) and l = x % (lmax + 1), rows j = y, y + gridDim.y, ...; the block's
+// count of unequal pairs goes to out[x] as (pairs - 2 * unequal) by one atomic.
+// Packed: rows are L / 32 words (L % 32 == 0); the partner row's bits from
+// column l on are a funnel shift of two of its words.
+template <int PACKED>
+__global__ __launch_bounds__(256) void k_corr_diag(const void* __restrict__ sigma, Geom G, int32_t lmax,
+                                                    int64_t* __restrict__ out) {
+    __shared__ int64_t red[2 * 4];
+    const uint32_t L = G.L;
+    const uint32_t n_l = (uint32_t)lmax + 1u;
+    const uint32_t dir = blockIdx.x / n_l, l = blockIdx.x % n_l;
+    int64_t diff = 0, pairs = 0;
+    if constexpr (PACKED) {
+        const uint32_t* s = static_cast<const uint32_t*>(sigma);
+        const uint32_t W = L / 32u;
+        const uint32_t sh = l & 31u;
+        for (uint32_t j = blockIdx.y; j < L; j += gridDim.y) {
+            const uint32_t jp = dir == 0 ? (j + l) % L : (j + L - l) % L;
+            const uint32_t* row = s + (size_t)j * W;
+            const uint32_t* prow = s + (size_t)jp * W;
+            for (uint32_t k = threadIdx.x; k < W; k += blockDim.x) {
+                uint32_t q0 = k + (l >> 5);
+                q0 = q0 >= W ? q0 - W : q0;
+                const uint32_t q1 = q0 + 1u == W ? 0u : q0 + 1u;
+                const uint32_t rot = sh ? ((prow[q0] >> sh) | (prow[q1] << (32u - sh))) : prow[q0];
+                diff += __popc(row[k] ^ rot);
+                pairs += 32;
+            }
+        }
+    } else {
+        const int8_t* s = static_cast<const int8_t*>(sigma);
+        for (uint32_t j = blockIdx.y; j < L; j += gridDim.y) {
+            const uint32_t jp = dir == 0 ? (j + l) % L : (j + L - l) % L;
+            for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
+                const uint32_t ip = (i + l) % L;
+                diff += (s[(size_t)j * L + i] > 0) != (s[(size_t)jp * L + ip] > 0);
+                pairs += 1;
+            }
+        }
+    }
+    int64_t v[2] = {diff, pairs};
+    block_sum_i64<2>(v, red);
+    if (threadIdx.x == 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(out + blockIdx.x), (unsigned long long)(v[1] - 2 * v[0]));
+}
+
 }  // namespace
 
 hipError_t launch_observe(int layout, const void* sigma, const void* tau, const Geom& G, int64_t* out3,
@@ -150,6 +198,23 @@ hipError_t launch_observe(int layout, const void* sigma, const void* tau, const 
         hipLaunchKernelGGL(k_observe_i8, dim3(blocks ? blocks : 1), dim3(256), 0, st,
                            static_cast<const int8_t*>(sigma), static_cast<const int8_t*>(tau), G, out3);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_diag(int layout, const void* sigma, const Geom& G, int32_t lmax, int64_t* out,
+                            hipStream_t st) {
+    const uint32_t n = 2u * ((uint32_t)lmax + 1u);
+    hipError_t e = launch_fill_i64(out, n, 0, st);
+    if (e != hipSuccess)
+        return e;
+    uint32_t row_blocks = kMaxBlocks / n;
+    row_blocks = row_blocks < G.L ? row_blocks : G.L;
+    row_blocks = row_blocks ? row_blocks : 1u;
+    const dim3 grid(n, row_blocks);
+    if (layout == kLayP64 || layout == kLayP32)
+        hipLaunchKernelGGL((k_corr_diag<1>), grid, dim3(256), 0, st, sigma, G, lmax, out);
+    else
+        hipLaunchKernelGGL((k_corr_diag<0>), grid, dim3(256), 0, st, sigma, G, lmax, out);
     return hipGetLastError();
 }
 

@@ -64,5 +64,7 @@ hipError_t launch_observe(int layout, const void* sigma, const void* tau, const 
                           hipStream_t st);
 hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
                            hipStream_t st);
+hipError_t launch_corr_diag(int layout, const void* sigma, const Geom& G, int32_t lmax, int64_t* out,
+                            hipStream_t st);
 
 }  // namespace sd
