@@ -18,8 +18,9 @@
  *   - layouts: SD_I8 = one int8 per site, +1 -> 0x01, -1 -> 0xFF;
  *     SD_P64 / SD_P32 = one bit per site (1 = +1), bit s of the lattice is
  *     bit s%64 of 64-bit word s/64 (the same bytes for both; P64 needs
- *     L % 64 == 0 and 8-byte alignment, P32 needs L % 32 == 0 and 4-byte
- *     alignment);
+ *     L % 8 == 0, so that L*L fills whole words, and 8-byte alignment; rows
+ *     start on a word only when L % 64 == 0.  P32 needs L % 32 == 0 and
+ *     4-byte alignment);
  *   - randomness: the counter-based stream keyed by (seed, stream, half-step
  *     index t, site s): step n of a chain uses t = 2n (A) and t = 2n+1 (B); the
  *     result is a pure function of the arguments, so run(k1) followed by
@@ -190,7 +191,7 @@ SD_API sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_
  * stream id stream0 + a, and its 2*k_steps + 1 lattices go to
  * traj + a * (2*k_steps + 1) * sd_lattice_bytes(L, layout), laid out as
  * sd_trajectory writes them; the result is that of n_traj calls of
- * sd_trajectory.  When L is a multiple of 64 and a lattice pair fits in LDS
+ * sd_trajectory.  When L is a multiple of 8 and a lattice pair fits in LDS
  * (L <= 512 on gfx950) every trajectory runs in one workgroup of a single
  * launch with its lattices in LDS; otherwise the trajectories are recorded
  * one after the other.  The start lattices must not overlap the
@@ -232,7 +233,7 @@ SD_API sd_status sd_loglik_bwd(const int64_t* counts12, const float* Jq, const f
 /* Batched scan: many independent chains in one persistent launch.            */
 /* ------------------------------------------------------------------------- */
 
-/* One chain of a batch: its couplings, lattice size (a multiple of 64) and
+/* One chain of a batch: its couplings, lattice size (a multiple of 8) and
  * stream id (the chain's randomness is exactly that of sd_run with the same
  * seed and stream). */
 typedef struct {

@@ -262,12 +262,15 @@ def sd_debug_fastdiv(n: int, d: int) -> int:
 # ---------------------------------------------------------------------------
 def new_lattice(L: int, layout: int, device="cuda") -> torch.Tensor:
     """An uninitialised lattice tensor: int8 [L, L] for SD_I8, int64 [L, L/64]
-    for SD_P64, int32 [L, L/32] for SD_P32 (the packed bytes are the same)."""
+    for SD_P64 (flat [L*L/64] when L % 64 != 0: rows do not start on a word),
+    int32 [L, L/32] for SD_P32 (the packed bytes are the same)."""
     nbytes = sd_lattice_bytes(L, layout)
     if nbytes == 0:
         raise ValueError(f"unsupported lattice L={L} layout={layout}")
     if layout == SD_I8:
         return torch.empty((L, L), dtype=torch.int8, device=device)
     if layout == SD_P64:
+        if L % 64:
+            return torch.empty((L * L // 64,), dtype=torch.int64, device=device)
         return torch.empty((L, L // 64), dtype=torch.int64, device=device)
     return torch.empty((L, L // 32), dtype=torch.int32, device=device)

@@ -44,7 +44,7 @@ bool layout_supported(int32_t L, int32_t layout) {
         case SD_P32:
             return L % 32 == 0;
         case SD_P64:
-            return L % 64 == 0;
+            return L % 8 == 0;
         default:
             return false;
     }
@@ -59,12 +59,16 @@ size_t lattice_bytes(int32_t L, int32_t layout) {
 
 int kernel_layout(int32_t L, int32_t layout, const void* p) {
     if (layout == SD_P64)
-        return kLayP64;
+        return L % 64 == 0 ? kLayP64 : kLayBits;
     if (layout == SD_P32)
         return kLayP32;
     const bool aligned = (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
     return (L % 64 == 0 && aligned) ? kLayI8Row : kLayI8Any;
 }
+
+// Kernel layout for the row-oriented reductions (observables, correlations)
+// of a packed lattice: 32-bit rows when L % 32 == 0, else the bit string.
+int packed_rows_layout(int32_t L) { return L % 32 == 0 ? kLayP32 : kLayBits; }
 
 Geom make_geom(int32_t L, int klay) {
     Geom G;
@@ -78,6 +82,9 @@ Geom make_geom(int32_t L, int klay) {
             break;
         case kLayP32:
             G.words_row = (uint32_t)L / 32u;
+            break;
+        case kLayBits:
+            G.words_row = 1;   // rows need not start on a word: neighbours are string windows
             break;
         default:
             G.words_row = 1;
@@ -305,7 +312,8 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
     const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
     const uint32_t lds_words = ch.mode == 1 ? lds_max_words() : kSingleLdsMaxWords;
-    const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0)) &&
+    const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0) ||
+                         klay == kLayBits) &&
                         n_words <= lds_words && ch.mode != 2 && !(flags & SD_FLAG_GLOBAL_KERNELS);
     if (lds_ok) {
         if (k_steps == 0)
@@ -343,7 +351,7 @@ sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layo
         return s;
     if (!out3)
         return fail(SD_EINVAL, "sd_observe: null output");
-    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    const int klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
     hipError_t e = launch_observe(klay, sigma, tau, make_geom(L, klay), out3, static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_observe");
 }
@@ -357,7 +365,7 @@ sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax
         return fail(SD_EINVAL, "sd_corr_row: null output");
     if (rmax < 0 || rmax >= L)
         return fail(SD_EINVAL, "sd_corr_row: rmax must satisfy 0 <= rmax < L");
-    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    const int klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
     hipError_t e = launch_corr_row(klay, sigma, make_geom(L, klay), rmax, out, static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
 }
@@ -371,7 +379,7 @@ sd_status sd_corr_diag(const void* sigma, int32_t L, int32_t layout, int32_t lma
         return fail(SD_EINVAL, "sd_corr_diag: null output");
     if (lmax < 0 || lmax >= L)
         return fail(SD_EINVAL, "sd_corr_diag: lmax must satisfy 0 <= lmax < L");
-    const int klay = layout == SD_I8 ? kLayI8Any : kLayP32;
+    const int klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
     hipError_t e = launch_corr_diag(klay, sigma, make_geom(L, klay), lmax, out, static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_diag");
 }

@@ -52,6 +52,16 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// 64-site words of an L x L lattice (L % 8 == 0).
+uint32_t lattice_words(uint32_t L) { return (uint32_t)(((uint64_t)L * L) / 64u); }
+
+// Division constants of a chain: by the words per row (rows of whole words
+// only; 1 otherwise) and by L.
+void set_divisors(ChainDesc& d, uint32_t L) {
+    d.divW = make_fastdiv(L >= 64u ? L / 64u : 1u);
+    d.divL = make_fastdiv(L);
+}
+
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 void release_graph(sd_batch_plan* p) {
@@ -81,6 +91,7 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     a.obs_every = p->obs_every ? p->obs_every : 1u;
     a.rng_xor = (p->flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
     a.max_words = bk.max_words;
+    a.bits = bk.L % 64u != 0 ? 1u : 0u;
     a.int8_io = p->layout == SD_I8 ? 1u : 0u;
     a.paired = bk.paired;
     return a;
@@ -167,7 +178,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
     long best = -1;
     if (e == hipSuccess) {
         auto measure = [&](long threads) -> double {
-            const size_t lds = batch_lds_bytes(L * (L / 64u), (uint32_t)threads);
+            const size_t lds = batch_lds_bytes(lattice_words(L), (uint32_t)threads);
             BatchArgs a;
             std::memset(&a, 0, sizeof a);
             a.chains = dd;
@@ -179,11 +190,12 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
             a.key0 = 1;
             a.k_steps = k;
             a.obs_every = 1;
-            a.max_words = L * (L / 64u);
+            a.max_words = lattice_words(L);
+            a.bits = L % 64u != 0 ? 1u : 0u;
             a.int8_io = p->layout == SD_I8 ? 1u : 0u;
             a.paired = paired;
             int per_cu = 0;
-            if (batch_occupancy((uint32_t)threads, lds, paired != 0, &per_cu) != hipSuccess || per_cu < 1)
+            if (batch_occupancy((uint32_t)threads, lds, paired != 0, L % 64u != 0, &per_cu) != hipSuccess || per_cu < 1)
                 return -1.0;
             const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(S, (uint32_t)per_cu * (uint32_t)n_cu));
             float best_ms = -1.0f;
@@ -226,7 +238,7 @@ hipError_t launch_trajectories_lds(const void* sigma0, void* traj, uint32_t n_tr
     a.single.paired = thresholds_paired(a.single.T) ? 1u : 0u;
     a.single.L = (uint32_t)L;
     a.single.stream = stream0;
-    a.single.divW = make_fastdiv((uint32_t)L / 64u);
+    set_divisors(a.single, (uint32_t)L);
     a.single_sig = static_cast<uint8_t*>(const_cast<void*>(sigma0));
     a.n_uniform = n_traj;
     a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
@@ -234,7 +246,8 @@ hipError_t launch_trajectories_lds(const void* sigma0, void* traj, uint32_t n_tr
     a.step0 = (uint32_t)step0;
     a.k_steps = k_steps;
     a.obs_every = 1;
-    a.max_words = (uint32_t)L * ((uint32_t)L / 64u);
+    a.max_words = lattice_words((uint32_t)L);
+    a.bits = L % 64 != 0 ? 1u : 0u;
     a.paired = a.single.paired;
     a.traj = static_cast<uint8_t*>(traj);
     a.traj_chain_bytes = (2ull * k_steps + 1ull) * a.max_words * sizeof(uint64_t);
@@ -254,7 +267,7 @@ hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_
     a.single.paired = thresholds_paired(a.single.T) ? 1u : 0u;
     a.single.L = (uint32_t)L;
     a.single.stream = stream;
-    a.single.divW = make_fastdiv((uint32_t)L / 64u);
+    set_divisors(a.single, (uint32_t)L);
     a.single_sig = static_cast<uint8_t*>(sigma);
     a.single_tau = static_cast<uint8_t*>(tau);
     a.traces = obs;
@@ -264,7 +277,8 @@ hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_
     a.k_steps = k_steps;
     a.obs_every = obs_every ? obs_every : 1u;
     a.rng_xor = (flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
-    a.max_words = (uint32_t)L * ((uint32_t)L / 64u);
+    a.max_words = lattice_words((uint32_t)L);
+    a.bits = L % 64 != 0 ? 1u : 0u;
     a.int8_io = int8_io ? 1u : 0u;
     a.paired = a.single.paired;
     hipError_t e = batch_kernel_attributes(batch_lds_bytes(a.max_words, threads));
@@ -320,11 +334,11 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     size_t off = 0;
     for (int32_t c = 0; c < n_chains; ++c) {
         const sd_chain_desc& in = chains[c];
-        if (in.L < 64 || in.L > 65535 || in.L % 64 != 0 || !std::isfinite(in.J) || !std::isfinite(in.q)) {
+        if (in.L < 8 || in.L > 65535 || in.L % 8 != 0 || !std::isfinite(in.J) || !std::isfinite(in.q)) {
             delete p;
-            return fail(SD_EINVAL, "sd_batch_plan_create: chain %d needs finite J, q and L a multiple of 64", c);
+            return fail(SD_EINVAL, "sd_batch_plan_create: chain %d needs finite J, q and L a multiple of 8", c);
         }
-        const size_t words = (size_t)in.L * (in.L / 64);
+        const size_t words = lattice_words((uint32_t)in.L);
         if (batch_lds_bytes((uint32_t)words, 64) > (size_t)max_lds) {
             delete p;
             return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: chain %d (L=%d) does not fit in %d bytes of LDS", c,
@@ -335,7 +349,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         d.paired = thresholds_paired(d.T) ? 1u : 0u;
         d.L = (uint32_t)in.L;
         d.stream = in.stream;
-        d.divW = make_fastdiv((uint32_t)in.L / 64u);
+        set_divisors(d, (uint32_t)in.L);
         const size_t bytes = lattice_bytes(in.L, layout);
         d.sig_offset = off;
         off = align_up(off + bytes);
@@ -352,7 +366,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         sd_batch_plan::Bucket bk;
         bk.L = kv.first.first;
         bk.paired = kv.first.second;
-        bk.max_words = bk.L * (bk.L / 64u);
+        bk.max_words = lattice_words(bk.L);
         bk.first = (uint32_t)order.size();
         bk.count = (uint32_t)kv.second.size();
         order.insert(order.end(), kv.second.begin(), kv.second.end());
@@ -397,7 +411,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         uint32_t threads = autotune_batch_threads(tune_cache_path, bk.L, bk.paired, bk.count, p);
         const size_t lds = batch_lds_bytes(bk.max_words, threads);
         int per_cu = 0;
-        e = batch_occupancy(threads, lds, bk.paired != 0, &per_cu);
+        e = batch_occupancy(threads, lds, bk.paired != 0, bk.L % 64u != 0, &per_cu);
         if (e != hipSuccess || per_cu < 1)
             per_cu = 1;
         uint64_t blocks = (uint64_t)per_cu * (uint64_t)n_cu;

@@ -27,15 +27,24 @@ namespace sd {
 
 namespace {
 
+// BITS: rows need not start on a word (L % 64 != 0, L % 8 == 0); neighbours
+// are windows of the lattice's bit string.
+template <bool BITS>
 struct HalfCtx {
     const uint64_t* src;
     uint64_t* dst;
     uint32_t L, W, n_words;
-    FastDiv divW;
+    FastDiv divW;   // division by W = L / 64 (rows of whole words)
+    FastDiv divL;   // division by L (bit strings)
 };
 
-template <int WHICH>
-__device__ __forceinline__ void gather_lds(const HalfCtx& h, uint32_t g, uint64_t& c, uint64_t& n1, uint64_t& n2) {
+template <int WHICH, bool BITS>
+__device__ __forceinline__ void gather_lds(const HalfCtx<BITS>& h, uint32_t g, uint64_t& c, uint64_t& n1,
+                                           uint64_t& n2) {
+    if constexpr (BITS) {
+        gather_bits<WHICH>(h.src, h.L, h.n_words, h.divL, g, c, n1, n2);
+        return;
+    }
     const uint32_t j = fdiv(g, h.divW);
     const uint32_t w = g - j * h.W;
     const uint32_t row = j * h.W;
@@ -71,8 +80,8 @@ struct ObsSums {
 };
 
 // Resolves the first n entries of the wavefront's list into the lattice.
-template <int WHICH, bool OBS>
-__device__ __forceinline__ void resolve_list(const HalfCtx& h, const DrawParams& dp, const uint32_t* T24,
+template <int WHICH, bool OBS, bool BITS>
+__device__ __forceinline__ void resolve_list(const HalfCtx<BITS>& h, const DrawParams& dp, const uint32_t* T24,
                                              WaveWordList& wl, uint32_t n, ObsSums& acc) {
     for (uint32_t e = threadIdx.x & 63u; e < n; e += 64u) {
         const uint32_t g = wl.g[e];
@@ -104,8 +113,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // One half-step of the workgroup's chain, src -> dst in LDS, ending with a
 // workgroup barrier.  OBS (half-step B of a recorded step): accumulate the
 // observables of the new pair (dst, src) in acc.
-template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
-__device__ __forceinline__ void lds_half_step(const HalfCtx& h, const DrawParams& dp, const PlaneMasks& pm,
+template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS, bool BITS>
+__device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const DrawParams& dp, const PlaneMasks& pm,
                                               const uint32_t* T24, WaveWordList& wl, ObsSums& acc) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n_waves = blockDim.x >> 6;
@@ -164,8 +173,20 @@ __device__ __forceinline__ uint32_t lds_bits4_to_bytes(uint32_t n) {
 
 // Observables of the pair (sig, tau) as sums over the workgroup's threads
 // (a separate pass, used for chains with the general compare).
-__device__ __forceinline__ ObsSums lds_observe(const uint64_t* sig, const uint64_t* tau, const HalfCtx& h) {
+template <bool BITS>
+__device__ __forceinline__ ObsSums lds_observe(const uint64_t* sig, const uint64_t* tau, const HalfCtx<BITS>& h) {
     ObsSums acc;
+    if constexpr (BITS) {
+        for (uint32_t g = threadIdx.x; g < h.n_words; g += blockDim.x) {
+            uint64_t t, up, right;
+            gather_bits<1>(tau, h.L, h.n_words, h.divL, g, t, up, right);
+            const uint64_t sg = sig[g];
+            acc.pc += __popcll(sg);
+            acc.dpair += __popcll(sg ^ up) + __popcll(sg ^ right);
+            acc.dself += __popcll(sg ^ t);
+        }
+        return acc;
+    }
     for (uint32_t g = threadIdx.x; g < h.n_words; g += blockDim.x) {
         const uint32_t j = fdiv(g, h.divW);
         const uint32_t w = g - j * h.W;
@@ -189,8 +210,9 @@ __device__ __forceinline__ void store_lattice(uint64_t* out, const uint64_t* lat
         out[g] = lat[g];
 }
 
-template <bool PAIRED, bool COMPLEMENT>
-__device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA, const HalfCtx& hB, DrawParams dp,
+template <bool PAIRED, bool COMPLEMENT, bool BITS>
+__device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS>& hA, const HalfCtx<BITS>& hB,
+                                          DrawParams dp,
                                           const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red,
                                           uint64_t* traj) {
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
@@ -228,8 +250,9 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx& hA,
     }
 }
 
-// PAIRED: every chain of the launch has a paired threshold table.
-template <bool COMPLEMENT, bool PAIRED>
+// PAIRED: every chain of the launch has a paired threshold table.  BITS: the
+// chains' L are multiples of 8 but not of 64 (bit-string neighbours).
+template <bool COMPLEMENT, bool PAIRED, bool BITS>
 __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t s_chain;
@@ -259,11 +282,12 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
                 break;
             cd = a.single;
         }
-        HalfCtx hA, hB;
+        HalfCtx<BITS> hA, hB;
         hA.L = hB.L = cd.L;
         hA.W = hB.W = cd.L / 64u;
-        hA.n_words = hB.n_words = cd.L * (cd.L / 64u);
+        hA.n_words = hB.n_words = (uint32_t)(((uint64_t)cd.L * cd.L) / 64u);
         hA.divW = hB.divW = cd.divW;
+        hA.divL = hB.divL = cd.divL;
         hA.src = sig; hA.dst = tau;
         hB.src = tau; hB.dst = sig;
         const uint32_t n_words = hA.n_words;
@@ -311,7 +335,7 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         if (traj)
             store_lattice(traj, sig, n_words);
 
-        run_steps<PAIRED, COMPLEMENT>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj);
+        run_steps<PAIRED, COMPLEMENT, BITS>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj);
         if (traj) {
             __syncthreads();
             continue;
@@ -361,16 +385,24 @@ size_t batch_lds_bytes(uint32_t max_words, uint32_t threads) {
     return (size_t)2 * max_words * sizeof(uint64_t) + (size_t)((threads + 63u) / 64u) * sizeof(WaveWordList);
 }
 
+template <bool BITS>
+void launch_batch_chains_t(const BatchArgs& a, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t st) {
+    if (a.rng_xor && a.paired)
+        hipLaunchKernelGGL((k_batch_chains<true, true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+    else if (a.rng_xor)
+        hipLaunchKernelGGL((k_batch_chains<true, false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+    else if (a.paired)
+        hipLaunchKernelGGL((k_batch_chains<false, true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_batch_chains<false, false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+}
+
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st) {
     const size_t lds = batch_lds_bytes(a.max_words, threads);
-    if (a.rng_xor && a.paired)
-        hipLaunchKernelGGL((k_batch_chains<true, true>), dim3(blocks), dim3(threads), lds, st, a);
-    else if (a.rng_xor)
-        hipLaunchKernelGGL((k_batch_chains<true, false>), dim3(blocks), dim3(threads), lds, st, a);
-    else if (a.paired)
-        hipLaunchKernelGGL((k_batch_chains<false, true>), dim3(blocks), dim3(threads), lds, st, a);
+    if (a.bits)
+        launch_batch_chains_t<true>(a, blocks, threads, lds, st);
     else
-        hipLaunchKernelGGL((k_batch_chains<false, false>), dim3(blocks), dim3(threads), lds, st, a);
+        launch_batch_chains_t<false>(a, blocks, threads, lds, st);
     return hipGetLastError();
 }
 
@@ -380,10 +412,14 @@ hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st) {
 }
 
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
-    const void* kernels[4] = {reinterpret_cast<const void*>(&k_batch_chains<false, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<false, true>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, true>)};
+    const void* kernels[8] = {reinterpret_cast<const void*>(&k_batch_chains<false, false, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, true, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, false, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, true, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, false, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, true, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, false, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, true, true>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
         if (e != hipSuccess)
@@ -392,11 +428,12 @@ hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
     return hipSuccess;
 }
 
-hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, int* blocks_per_cu) {
-    if (paired)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false, true>, (int)threads,
-                                                            lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_chains<false, false>, (int)threads, lds);
+hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, bool bits, int* blocks_per_cu) {
+    const void* k = bits ? (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, true, true>)
+                                   : reinterpret_cast<const void*>(&k_batch_chains<false, false, true>))
+                         : (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, true, false>)
+                                   : reinterpret_cast<const void*>(&k_batch_chains<false, false, false>));
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, (int)threads, lds);
 }
 
 }  // namespace sd

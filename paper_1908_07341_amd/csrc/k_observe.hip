@@ -52,6 +52,29 @@ __global__ __launch_bounds__(256) void k_observe_packed(const uint32_t* __restri
     add_obs(out3, pc, dpair, dself, n, red);
 }
 
+// Bit-string layout (any L % 8 == 0): one lane per 64-bit word, the up and
+// right neighbour words as windows of tau.
+__global__ __launch_bounds__(256) void k_observe_bits(const uint64_t* __restrict__ sigma,
+                                                       const uint64_t* __restrict__ tau, Geom G,
+                                                       int64_t* __restrict__ out3) {
+    __shared__ int64_t red[4 * 4];
+    int64_t pc = 0, dpair = 0, dself = 0, n = 0;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G.n_groups; g += gridDim.x * blockDim.x) {
+        uint64_t t, up, right;
+        gather_bits<1>(tau, G.L, G.n_groups, G.div_L, g, t, up, right);
+        const uint64_t sg = sigma[g];
+        pc += __popcll(sg);
+        dpair += __popcll(sg ^ up) + __popcll(sg ^ right);
+        dself += __popcll(sg ^ t);
+        n += 64;
+    }
+    add_obs(out3, pc, dpair, dself, n, red);
+}
+
+__device__ __forceinline__ uint32_t string_bit(const uint64_t* lat, size_t s) {
+    return (uint32_t)(lat[s >> 6] >> (s & 63u)) & 1u;
+}
+
 // int8 layout, any L: one lane per site.
 __global__ __launch_bounds__(256) void k_observe_i8(const int8_t* __restrict__ sigma, const int8_t* __restrict__ tau,
                                                      Geom G, int64_t* __restrict__ out3) {
@@ -79,7 +102,20 @@ constexpr uint32_t kCorrWords = (2 * kCorrMaxL + 64) / 32 + 2;
 
 template <int PACKED>
 __device__ __forceinline__ void stage_row(const void* sigma, const Geom& G, uint32_t j, uint32_t* row, uint32_t nw2) {
-    if constexpr (PACKED) {
+    if constexpr (PACKED == 2) {
+        const uint64_t* s = static_cast<const uint64_t*>(sigma);
+        const size_t row0 = (size_t)j * G.L;
+        for (uint32_t k = threadIdx.x; k < nw2; k += blockDim.x) {
+            uint32_t word = 0;
+            uint32_t col = (uint32_t)(((uint64_t)32u * k) % G.L);
+            for (int b = 0; b < 32; ++b) {
+                word |= string_bit(s, row0 + col) << b;
+                if (++col == G.L)
+                    col = 0;
+            }
+            row[k] = word;
+        }
+    } else if constexpr (PACKED) {
         const uint32_t* s = static_cast<const uint32_t*>(sigma);
         const uint32_t W = G.L / 32u;
         for (uint32_t k = threadIdx.x; k < nw2; k += blockDim.x)
@@ -145,7 +181,7 @@ __global__ __launch_bounds__(256) void k_corr_diag(const void* __restrict__ sigm
     const uint32_t n_l = (uint32_t)lmax + 1u;
     const uint32_t dir = blockIdx.x / n_l, l = blockIdx.x % n_l;
     int64_t diff = 0, pairs = 0;
-    if constexpr (PACKED) {
+    if constexpr (PACKED == 1) {
         const uint32_t* s = static_cast<const uint32_t*>(sigma);
         const uint32_t W = L / 32u;
         const uint32_t sh = l & 31u;
@@ -163,12 +199,18 @@ __global__ __launch_bounds__(256) void k_corr_diag(const void* __restrict__ sigm
             }
         }
     } else {
-        const int8_t* s = static_cast<const int8_t*>(sigma);
         for (uint32_t j = blockIdx.y; j < L; j += gridDim.y) {
             const uint32_t jp = dir == 0 ? (j + l) % L : (j + L - l) % L;
             for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
                 const uint32_t ip = (i + l) % L;
-                diff += (s[(size_t)j * L + i] > 0) != (s[(size_t)jp * L + ip] > 0);
+                const size_t a = (size_t)j * L + i, b = (size_t)jp * L + ip;
+                if constexpr (PACKED == 2) {
+                    const uint64_t* s = static_cast<const uint64_t*>(sigma);
+                    diff += string_bit(s, a) != string_bit(s, b);
+                } else {
+                    const int8_t* s = static_cast<const int8_t*>(sigma);
+                    diff += (s[a] > 0) != (s[b] > 0);
+                }
                 pairs += 1;
             }
         }
@@ -186,7 +228,12 @@ hipError_t launch_observe(int layout, const void* sigma, const void* tau, const 
     hipError_t e = launch_fill_i64(out3, 3, 0, st);
     if (e != hipSuccess)
         return e;
-    if (layout == kLayP64 || layout == kLayP32) {
+    if (layout == kLayBits) {
+        uint32_t blocks = (G.n_groups + 255u) / 256u;
+        blocks = blocks < kMaxBlocks ? blocks : kMaxBlocks;
+        hipLaunchKernelGGL(k_observe_bits, dim3(blocks ? blocks : 1), dim3(256), 0, st,
+                           static_cast<const uint64_t*>(sigma), static_cast<const uint64_t*>(tau), G, out3);
+    } else if (layout == kLayP64 || layout == kLayP32) {
         uint32_t n_words = G.n_sites / 32u;
         uint32_t blocks = (n_words + 255u) / 256u;
         blocks = blocks < kMaxBlocks ? blocks : kMaxBlocks;
@@ -211,7 +258,9 @@ hipError_t launch_corr_diag(int layout, const void* sigma, const Geom& G, int32_
     row_blocks = row_blocks < G.L ? row_blocks : G.L;
     row_blocks = row_blocks ? row_blocks : 1u;
     const dim3 grid(n, row_blocks);
-    if (layout == kLayP64 || layout == kLayP32)
+    if (layout == kLayBits)
+        hipLaunchKernelGGL((k_corr_diag<2>), grid, dim3(256), 0, st, sigma, G, lmax, out);
+    else if (layout == kLayP64 || layout == kLayP32)
         hipLaunchKernelGGL((k_corr_diag<1>), grid, dim3(256), 0, st, sigma, G, lmax, out);
     else
         hipLaunchKernelGGL((k_corr_diag<0>), grid, dim3(256), 0, st, sigma, G, lmax, out);
@@ -228,7 +277,9 @@ hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t
     row_blocks = row_blocks < G.L ? row_blocks : G.L;
     row_blocks = row_blocks ? row_blocks : 1u;
     const dim3 grid(r_chunks, row_blocks);
-    if (layout == kLayP64 || layout == kLayP32)
+    if (layout == kLayBits)
+        hipLaunchKernelGGL((k_corr_row<2>), grid, dim3(256), 0, st, sigma, G, rmax, out);
+    else if (layout == kLayP64 || layout == kLayP32)
         hipLaunchKernelGGL((k_corr_row<1>), grid, dim3(256), 0, st, sigma, G, rmax, out);
     else
         hipLaunchKernelGGL((k_corr_row<0>), grid, dim3(256), 0, st, sigma, G, rmax, out);

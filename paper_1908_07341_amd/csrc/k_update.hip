@@ -123,6 +123,8 @@ __device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t 
             const int8_t edge = s[row + (w == W - 1 ? 0 : 64u * w + 64u)];
             n2 = (c >> 1) | (edge > 0 ? (1ull << 63) : 0ull);
         }
+    } else if constexpr (LAYOUT == kLayBits) {
+        gather_bits<WHICH>(static_cast<const uint64_t*>(src), G.L, G.n_groups, G.div_L, g, c, n1, n2);
     } else {  // kLayI8Any: per-site gather, any L >= 2
         const int8_t* s = static_cast<const int8_t*>(src);
         const uint32_t s0 = 64u * g;
@@ -149,7 +151,7 @@ __device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t 
 
 template <int LAYOUT>
 __device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, uint64_t bits, uint64_t valid) {
-    if constexpr (LAYOUT == kLayP64) {
+    if constexpr (LAYOUT == kLayP64 || LAYOUT == kLayBits) {
         static_cast<uint64_t*>(dst)[g] = bits;
     } else if constexpr (LAYOUT == kLayP32) {
         uint32_t* d = static_cast<uint32_t*>(dst);
@@ -222,7 +224,7 @@ __device__ __forceinline__ void gather_row(const void* src, const Geom& G, uint3
 // Words per lane and tile: 4 for the paired compare on bit-packed layouts,
 // 2 where the general compare or the int8 loads need more registers.
 constexpr int words_per_lane(int layout, bool paired) {
-    return (paired && (layout == kLayP64 || layout == kLayP32)) ? 4 : 2;
+    return (paired && (layout == kLayP64 || layout == kLayP32 || layout == kLayBits)) ? 4 : 2;
 }
 constexpr int kMaxWordsPerLane = 4;
 constexpr uint32_t kMaxWaveTile = 64u * kMaxWordsPerLane;
@@ -532,6 +534,7 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
         SD_HALF(kLayP32)
         SD_HALF(kLayI8Row)
         SD_HALF(kLayI8Any)
+        SD_HALF(kLayBits)
         default:
             return hipErrorInvalidValue;
     }
@@ -556,6 +559,7 @@ hipError_t launch_init(int layout, void* dst, const Geom& G, int kind_const_up, 
         SD_INIT(kLayP32)
         SD_INIT(kLayI8Row)
         SD_INIT(kLayI8Any)
+        SD_INIT(kLayBits)
         default:
             return hipErrorInvalidValue;
     }

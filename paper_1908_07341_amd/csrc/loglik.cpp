@@ -31,7 +31,7 @@ sd_status sd_trajectory(const void* sigma0, void* traj, int32_t L, int32_t layou
     hipError_t e = hipSuccess;
     if (sigma0 != traj)
         e = hipMemcpyAsync(base, sigma0, bytes, hipMemcpyDeviceToDevice, st);
-    const int klay = layout == SD_P64 ? kLayP64 : kLayP32;
+    const int klay = kernel_layout(L, layout, traj);
     const Geom G = make_geom(L, klay);
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
@@ -77,7 +77,7 @@ sd_status sd_trajectories(const void* sigma0, void* traj, int32_t n_traj, int32_
     if (e != hipSuccess)
         return hip_fail(e, "sd_trajectories");
     const uint32_t threads = n_words >= 2048u ? 512u : 256u;
-    if (L % 64 == 0 && batch_lds_bytes(n_words, threads) <= (size_t)max_lds) {
+    if (L % 8 == 0 && batch_lds_bytes(n_words, threads) <= (size_t)max_lds) {
         e = launch_trajectories_lds(sigma0, traj, (uint32_t)n_traj, L, J, q, seed, stream0, step0, k_steps, threads,
                                     st);
         return e == hipSuccess ? SD_OK : hip_fail(e, "sd_trajectories");

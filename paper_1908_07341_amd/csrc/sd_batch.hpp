@@ -12,6 +12,7 @@ struct ChainDesc {
     uint32_t stream;        // stream id of the chain's randomness
     uint32_t paired;        // thresholds_paired(T): the compare may use the paired form
     FastDiv divW;           // division by L / 64
+    FastDiv divL;           // division by L
     uint64_t sig_offset;    // sigma, in bytes from the lattices base
     uint64_t tau_offset;    // tau, in bytes from the lattices base
     uint64_t trace_offset;  // first int64 of the chain's trace
@@ -35,6 +36,7 @@ struct BatchArgs {
     uint32_t max_words;      // capacity (64-bit words) of each LDS lattice buffer
     uint32_t int8_io;        // lattices in global memory are int8 (L % 64 == 0)
     uint32_t paired;         // every chain of the launch has a paired threshold table
+    uint32_t bits;           // the chains' L % 64 != 0 (L % 8 == 0): bit-string neighbours
     uint32_t n_uniform;      // counter null and n_uniform > 0: workgroup b runs `single` with stream
                              // single.stream + b from packed sigma single_sig + b * lattice bytes
     uint8_t* traj;           // non-null: workgroup b writes lattice x of its trajectory (x = 0 the
@@ -49,7 +51,7 @@ size_t batch_lds_bytes(uint32_t max_words, uint32_t threads);
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds);
-hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, int* blocks_per_cu);
+hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, bool bits, int* blocks_per_cu);
 
 // Lattices with at most this many 64-site words run in one workgroup with
 // LDS-resident lattices when sd_run is called without SD_FLAG_GLOBAL_KERNELS.

@@ -431,4 +431,63 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
     return (uint32_t)(((uint64_t)hi + n) >> f.shift);
 }
 
+// ---------------------------------------------------------------------------
+// Packed lattices as one bit string: site s = j*L + i is bit s % 64 of word
+// s / 64 whatever L is.  With L % 8 == 0 the N = L*L sites fill whole words,
+// so every word is a full 64-site group of the stream and the neighbours of a
+// word are 64-bit windows of the string (rows need not start on a word).
+// ---------------------------------------------------------------------------
+
+// Bits p .. p+63 of the string (indices mod N), p < N.
+__device__ __forceinline__ uint64_t bit_window(const uint64_t* lat, uint32_t n_words, uint32_t p) {
+    const uint32_t q = p >> 6, sh = p & 63u;
+    const uint64_t w0 = lat[q];
+    const uint64_t w1 = lat[q + 1u == n_words ? 0u : q + 1u];
+    return sh ? ((w0 >> sh) | (w1 << (64u - sh))) : w0;
+}
+
+// (a + b) mod N for a < N, b < N, in 64-bit arithmetic.
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t N) {
+    const uint64_t t = (uint64_t)a + b;
+    return (uint32_t)(t >= N ? t - N : t);
+}
+
+// Bits b of word g whose site is in column r of its row ((64 g + b) % L == r).
+__device__ __forceinline__ uint64_t column_mask(uint32_t g, uint32_t L, const FastDiv& divL, uint32_t r) {
+    const uint32_t s0 = 64u * g;
+    const uint32_t m = s0 - fdiv(s0, divL) * L;   // column of bit 0
+    uint32_t b = r >= m ? r - m : r + L - m;
+    uint64_t mask = 0;
+    for (; b < 64u; b += L)
+        mask |= 1ull << b;
+    return mask;
+}
+
+// Partner word c and neighbour words n1, n2 of word g (L % 8 == 0).
+// WHICH 0 (half-step A): n1 = down (s - L), n2 = left (s - 1, or s + L - 1 in
+// column 0).  WHICH 1 (half-step B): n1 = up (s + L), n2 = right (s + 1, or
+// s - L + 1 in column L - 1).
+template <int WHICH>
+__device__ __forceinline__ void gather_bits(const uint64_t* lat, uint32_t L, uint32_t n_words, const FastDiv& divL,
+                                            uint32_t g, uint64_t& c, uint64_t& n1, uint64_t& n2) {
+    const uint32_t N = 64u * n_words;
+    const uint32_t s0 = 64u * g;
+    c = lat[g];
+    if constexpr (WHICH == 0) {
+        n1 = bit_window(lat, n_words, add_mod(s0, N - L, N));
+        const uint64_t prev = lat[g == 0 ? n_words - 1u : g - 1u];
+        const uint64_t base = (c << 1) | (prev >> 63);
+        const uint64_t wrap = bit_window(lat, n_words, add_mod(s0, L - 1u, N));
+        const uint64_t col0 = column_mask(g, L, divL, 0u);
+        n2 = (base & ~col0) | (wrap & col0);
+    } else {
+        n1 = bit_window(lat, n_words, add_mod(s0, L, N));
+        const uint64_t next = lat[g + 1u == n_words ? 0u : g + 1u];
+        const uint64_t base = (c >> 1) | (next << 63);
+        const uint64_t wrap = bit_window(lat, n_words, add_mod(s0, N + 1u - L, N));
+        const uint64_t last = column_mask(g, L, divL, L - 1u);
+        n2 = (base & ~last) | (wrap & last);
+    }
+}
+
 }  // namespace sd

@@ -13,6 +13,8 @@ sd_status hip_fail(hipError_t e, const char* what);
 bool layout_supported(int32_t L, int32_t layout);
 size_t lattice_bytes(int32_t L, int32_t layout);
 Geom make_geom(int32_t L, int klay);
+int kernel_layout(int32_t L, int32_t layout, const void* p);
+int packed_rows_layout(int32_t L);
 uint32_t threshold(double h);
 void threshold_table(double J, double q, uint32_t T[6]);
 DrawParams dynamics_params(double J, double q, uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags);

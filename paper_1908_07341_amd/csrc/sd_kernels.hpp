@@ -9,11 +9,13 @@
 
 namespace sd {
 
-// Kernel-side lattice layouts.  P64 and P32 are the same bytes (bit s of the
-// lattice is bit s % 64 of 64-bit word s / 64); they differ in the word width
-// the kernel works in.  I8Row is the int8 layout when every row is a whole
-// number of 64-site groups (L % 64 == 0); I8Any handles any L >= 2.
-enum KernelLayout : int { kLayP64 = 0, kLayP32 = 1, kLayI8Row = 2, kLayI8Any = 3 };
+// Kernel-side lattice layouts.  P64, P32 and Bits are the same bytes (bit s of
+// the lattice is bit s % 64 of 64-bit word s / 64).  P64 and P32 work in
+// 64- or 32-bit words with rows starting on a word (L % 64 == 0, L % 32 == 0);
+// Bits takes neighbours as windows of the bit string (any L % 8 == 0).  I8Row
+// is the int8 layout when every row is a whole number of 64-site groups
+// (L % 64 == 0); I8Any handles any L >= 2.
+enum KernelLayout : int { kLayP64 = 0, kLayP32 = 1, kLayI8Row = 2, kLayI8Any = 3, kLayBits = 4 };
 
 constexpr uint32_t kMaxBlocks = 2048;
 

@@ -44,7 +44,13 @@ def test_lattice_bytes():
     assert sd.sd_lattice_bytes(64, sd.SD_I8) == 4096
     assert sd.sd_lattice_bytes(64, sd.SD_P64) == 512
     assert sd.sd_lattice_bytes(96, sd.SD_P32) == 96 * 96 // 8
-    assert sd.sd_lattice_bytes(96, sd.SD_P64) == 0
+    # P64 is the bit string of the lattice: any L % 8 == 0 (L * L fills whole words)
+    assert sd.sd_lattice_bytes(96, sd.SD_P64) == 96 * 96 // 8
+    assert sd.sd_lattice_bytes(200, sd.SD_P64) == 200 * 200 // 8
+    assert sd.sd_lattice_bytes(8, sd.SD_P64) == 8
+    assert sd.sd_lattice_bytes(100, sd.SD_P64) == 0
+    assert sd.sd_lattice_bytes(4, sd.SD_P64) == 0
+    assert sd.sd_lattice_bytes(40, sd.SD_P32) == 0
     assert sd.sd_lattice_bytes(3, sd.SD_I8) == 9
     assert sd.sd_lattice_bytes(1, sd.SD_I8) == 0
     assert sd.sd_lattice_bytes(65536, sd.SD_I8) == 0
@@ -68,7 +74,7 @@ def test_bad_arguments_rejected_without_device_work():
     fake = ctypes.c_void_p(0x10000)
     assert lib.sd_init(None, 64, sd.SD_I8, 0, 0.5, 1, 0, st) == sd.SD_EINVAL
     assert lib.sd_init(fake, 1, sd.SD_I8, 0, 0.5, 1, 0, st) == sd.SD_EINVAL
-    assert lib.sd_init(fake, 96, sd.SD_P64, 0, 0.5, 1, 0, st) == sd.SD_EINVAL
+    assert lib.sd_init(fake, 100, sd.SD_P64, 0, 0.5, 1, 0, st) == sd.SD_EINVAL
     assert lib.sd_init(fake, 64, sd.SD_I8, 2, 1.5, 1, 0, st) == sd.SD_EINVAL
     assert lib.sd_init(fake, 64, sd.SD_I8, 7, 0.5, 1, 0, st) == sd.SD_EINVAL
     assert b"kind" in lib.sd_last_error()
@@ -85,6 +91,10 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_observe(fake, fake2, 64, sd.SD_I8, None, st) == sd.SD_EINVAL
     assert lib.sd_corr_row(fake, 64, sd.SD_I8, 64, fake2, st) == sd.SD_EINVAL
     assert lib.sd_corr_row(fake, 64, sd.SD_I8, -1, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_diag(fake, 64, sd.SD_I8, 64, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_diag(fake, 64, sd.SD_I8, 3, None, st) == sd.SD_EINVAL
+    assert lib.sd_trajectories(fake, fake2, -1, 64, sd.SD_P64, 0.4, 0.6, 1, 0, 0, 2, st) == sd.SD_EINVAL
+    assert lib.sd_trajectories(fake, fake2, 2, 64, sd.SD_I8, 0.4, 0.6, 1, 0, 0, 2, st) == sd.SD_EUNSUPPORTED
     out = (ctypes.c_uint32 * 6)()
     assert lib.sd_threshold_table(float("inf"), 0.1, out) == sd.SD_EINVAL
     assert lib.sd_threshold_table(0.1, 0.1, None) == sd.SD_EINVAL

@@ -42,9 +42,12 @@ def _chains(n, sizes, seed=3):
     return J, q, L, streams
 
 
+@pytest.mark.parametrize("sizes", [[64, 128, 192], [8, 40, 72, 200]])
 @pytest.mark.parametrize("layout", [sd.SD_P64, sd.SD_I8])
-def test_batch_matches_oracle(oracle, layout):
-    J, q, L, st = _chains(12, [64, 128, 192])
+def test_batch_matches_oracle(oracle, layout, sizes):
+    # the second set of sizes has rows off 64-bit word boundaries (bit-string
+    # neighbours in the batched kernel)
+    J, q, L, st = _chains(12, sizes)
     k, every = 30, 3
     plan = sd.sd_batch_plan_create(J, q, L, st, layout=layout, seed=SEED, k_steps=k, obs_every=every)
     lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
@@ -115,7 +118,7 @@ def test_batch_autotune_cache(tmp_path):
     plan2.close()
 
 
-@pytest.mark.parametrize("L", [64, 128, 256])
+@pytest.mark.parametrize("L", [40, 64, 128, 200, 256])
 def test_lds_and_global_paths_agree(L):
     J, q, k = 0.55, 0.45, 60
     s0 = inputs.random_lattice(L, L)
