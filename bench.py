@@ -146,6 +146,12 @@ def parse():
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 512 MiB device copy first (counter calibration runs)")
+    p.add_argument("--critical-scan", action="store_true",
+                   help="only the critical-curve scan of section 3.1 (moments of m on a (q, J) grid)")
+    p.add_argument("--scan-grid", type=int, default=80)
+    p.add_argument("--scan-L", type=int, default=200)
+    p.add_argument("--scan-warm", type=int, default=300000)
+    p.add_argument("--scan-rec", type=int, default=300000)
     p.add_argument("--table1", action="store_true",
                    help="only the diagonal-correlation comparison with Table 1 (32x32, all (q, J) rows)")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -327,6 +333,73 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
             "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est}
 
 
+def critical_J(q):
+    """J_c(q) of eq. (12): the critical curve of the shaken dynamics."""
+    t = np.tanh(q)
+    return np.arctanh(np.sqrt(t * t + 1.0) - t)
+
+
+def bench_critical_scan(sd, torch, n_grid, L, warm, rec, tune_cache):
+    """Section 3.1: chains on an n_grid x n_grid grid of (q, J) in (0, 2)^2 (cell
+    midpoints), L x L torus from all -1, `warm` steps, then the mean and the
+    variance of m over `rec` steps (per-chain moments kept on the device)."""
+    vals = 2.0 * (np.arange(n_grid) + 0.5) / n_grid
+    qg, Jg = np.meshgrid(vals, vals, indexing="ij")
+    qv, Jv = qg.reshape(-1), Jg.reshape(-1)
+    n = len(qv)
+    Lv = np.full(n, L)
+    streams = np.arange(n, dtype=np.uint32)
+    t0 = time.perf_counter()
+    plan_w = sd.sd_batch_plan_create(Jv, qv, Lv, streams, seed=1, k_steps=warm, obs_every=0,
+                                     tune_cache_path=tune_cache)
+    plan_r = sd.sd_batch_plan_create(Jv, qv, Lv, streams, seed=1, k_steps=rec, obs_every=1,
+                                     flags=sd.SD_FLAG_MOMENTS, tune_cache_path=tune_cache)
+    t_plan = time.perf_counter() - t0
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan_r), dtype=torch.uint8, device="cuda")
+    mom = torch.zeros(sd.sd_batch_trace_len(plan_r), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan_w, lat, sd.SD_INIT_DOWN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sd.sd_batch_run(plan_w, lat, None, 0)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    log(f"[bench] scan warm-up {warm} steps in {t_warm:.1f} s")
+    t0 = time.perf_counter()
+    sd.sd_batch_run(plan_r, lat, mom, warm)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    plan_w.close()
+    plan_r.close()
+    S = mom.cpu().numpy().reshape(n, 5).astype(np.float64)
+    N = float(L * L)
+    mean_m = S[:, 0] / (rec * N)
+    var_m = S[:, 1] / (rec * N * N) - mean_m ** 2
+    mean_abs = S[:, 2] / (rec * N)
+    var_g = var_m.reshape(n_grid, n_grid)
+    per_q = []
+    for a in range(n_grid):
+        b = int(np.argmax(var_g[a]))
+        per_q.append({"q": round(float(vals[a]), 4), "J_at_max_var": round(float(vals[b]), 4),
+                      "J_c": round(float(critical_J(vals[a])), 4), "max_var": round(float(var_g[a, b]), 4)})
+    dev = np.array([abs(r["J_at_max_var"] - r["J_c"]) for r in per_q])
+    big = var_m >= 0.03
+    dist = np.abs(Jv[big] - critical_J(qv[big]))
+    updates = 2.0 * n * N * (warm + rec)
+    return {"workload": f"{n} chains: (q, J) on a {n_grid}x{n_grid} grid of cell midpoints in (0,2)^2, "
+                        f"{L}x{L} torus from all -1, {warm} warm-up + {rec} recorded steps",
+            "seconds_warm": t_warm, "seconds_record": t_rec, "plan_seconds": t_plan,
+            "spin_updates_per_ns": updates / ((t_warm + t_rec) * 1e9),
+            "grid_step": 2.0 / n_grid,
+            "max_var_J_minus_Jc": {"mean": float(dev.mean()), "max": float(dev.max()),
+                                   "within_one_grid_step": int((dev <= 2.0 / n_grid + 1e-9).sum())},
+            "points_var_ge_0.03": int(big.sum()),
+            "their_J_minus_Jc": {"mean": float(dist.mean()) if big.any() else None,
+                                 "max": float(dist.max()) if big.any() else None},
+            "per_q": per_q,
+            "mean_abs_m_far_below_curve": float(mean_abs[Jv < critical_J(qv) - 0.2].mean()),
+            "mean_abs_m_far_above_curve": float(mean_abs[Jv > critical_J(qv) + 0.2].mean())}
+
+
 def bench_table1(sd, torch, burn=2000, n_meas=4000, every=5, L=32):
     """Time-averaged diagonal correlations C(l) = D(l) / L^2 on a 32x32 torus at
     every (q, J) row of Table 1 (section 3.3), next to the printed values
@@ -404,6 +477,11 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.table1:
         print(json.dumps({"table1": bench_table1(sd, torch)}), flush=True)
+        return
+    if args.critical_scan:
+        out = bench_critical_scan(sd, torch, args.scan_grid, args.scan_L, args.scan_warm, args.scan_rec,
+                                  args.tune_cache)
+        print(json.dumps({"critical_scan": out}), flush=True)
         return
     L, K, W = args.L, args.steps, args.warmup
     if args.calibrate_copy:

@@ -66,6 +66,7 @@ typedef enum { SD_INIT_UP = 0, SD_INIT_DOWN = 1, SD_INIT_RANDOM = 2 } sd_init_ki
 
 /* Flags of sd_half_step / sd_run. */
 #define SD_FLAG_COMPLEMENT_RNG 1u /* replace every uniform r by 2^32-1-r (global spin-flip check) */
+#define SD_FLAG_MOMENTS 4u        /* batch plans: keep per-chain sums of the records instead of traces */
 #define SD_FLAG_GLOBAL_KERNELS 2u /* sd_run: always use one grid-wide launch per half-step, never the
                                      single-workgroup LDS-resident kernel used for small lattices */
 
@@ -255,9 +256,13 @@ typedef struct sd_batch_plan sd_batch_plan;
  * picks each group's workgroup size: measured and cached in the JSON file
  * tune_cache_path if that is not NULL (measuring allocates scratch device
  * memory for the duration of the call), 256 otherwise.  layout is SD_P64 or
- * SD_I8.  The plan owns small device tables, side streams and a hipGraph; free
- * it with sd_batch_plan_destroy.  EUNSUPPORTED: a chain whose two lattices do
- * not fit in one workgroup's LDS.
+ * SD_I8.  flags: SD_FLAG_COMPLEMENT_RNG, and SD_FLAG_MOMENTS (needs
+ * obs_every > 0), under which the trace buffer holds instead, per chain, the
+ * 5 int64 sums over the run's recorded steps of M, M^2, |M|, A and B (the
+ * mean and variance of the magnetisation that section 3.1 scans; each
+ * sd_batch_run overwrites them).  The plan owns small device tables, side
+ * streams and a hipGraph; free it with sd_batch_plan_destroy.  EUNSUPPORTED: a
+ * chain whose two lattices do not fit in one workgroup's LDS.
  */
 SD_API sd_status sd_batch_plan_create(sd_batch_plan** plan, const sd_chain_desc* chains_host, int32_t n_chains,
                                       int32_t layout, uint64_t seed, uint32_t k_steps, uint32_t obs_every,

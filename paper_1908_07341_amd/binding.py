@@ -19,6 +19,7 @@ SD_I8, SD_P32, SD_P64 = 0, 1, 2
 SD_INIT_UP, SD_INIT_DOWN, SD_INIT_RANDOM = 0, 1, 2
 SD_FLAG_COMPLEMENT_RNG = 1
 SD_FLAG_GLOBAL_KERNELS = 2
+SD_FLAG_MOMENTS = 4
 
 
 class sd_chain_desc(ctypes.Structure):

@@ -90,6 +90,7 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     a.k_steps = p->k_steps;
     a.obs_every = p->obs_every ? p->obs_every : 1u;
     a.rng_xor = (p->flags & SD_FLAG_COMPLEMENT_RNG) ? 0xFFFFFFFFu : 0u;
+    a.moments = (p->flags & SD_FLAG_MOMENTS) ? 1u : 0u;
     a.max_words = bk.max_words;
     a.bits = bk.L % 64u != 0 ? 1u : 0u;
     a.int8_io = p->layout == SD_I8 ? 1u : 0u;
@@ -303,8 +304,10 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: layout must be SD_P64 or SD_I8");
     if (k_steps >= (1u << 29))
         return fail(SD_EINVAL, "sd_batch_plan_create: k_steps must be below 2^29");
-    if (flags & ~SD_FLAG_COMPLEMENT_RNG)
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_MOMENTS))
         return fail(SD_EINVAL, "sd_batch_plan_create: unknown flags");
+    if ((flags & SD_FLAG_MOMENTS) && !obs_every)
+        return fail(SD_EINVAL, "sd_batch_plan_create: SD_FLAG_MOMENTS needs obs_every > 0");
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess)
@@ -355,7 +358,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         off = align_up(off + bytes);
         d.tau_offset = off;
         off = align_up(off + bytes);
-        d.trace_offset = (uint64_t)c * p->n_rec * 3u;
+        d.trace_offset = (flags & SD_FLAG_MOMENTS) ? (uint64_t)c * kMomentWords : (uint64_t)c * p->n_rec * 3u;
         by_L[std::make_pair((uint32_t)in.L, d.paired)].push_back((uint32_t)c);
     }
     p->lattice_total = off;
@@ -425,7 +428,11 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
 size_t sd_batch_lattice_bytes(const sd_batch_plan* plan) { return plan ? plan->lattice_total : 0; }
 
 size_t sd_batch_trace_len(const sd_batch_plan* plan) {
-    return plan ? (size_t)plan->n_chains * plan->n_rec * 3u : 0;
+    if (!plan)
+        return 0;
+    if (plan->flags & SD_FLAG_MOMENTS)
+        return (size_t)plan->n_chains * kMomentWords;
+    return (size_t)plan->n_chains * plan->n_rec * 3u;
 }
 
 int64_t sd_batch_chain_offset(const sd_batch_plan* plan, int32_t chain, int32_t which) {

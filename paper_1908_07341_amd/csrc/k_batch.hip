@@ -210,11 +210,12 @@ __device__ __forceinline__ void store_lattice(uint64_t* out, const uint64_t* lat
         out[g] = lat[g];
 }
 
+// mom (used by thread 0 only): the chain's running sums in moments mode.
 template <bool PAIRED, bool COMPLEMENT, bool BITS>
 __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS>& hA, const HalfCtx<BITS>& hB,
                                           DrawParams dp,
                                           const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red,
-                                          uint64_t* traj) {
+                                          uint64_t* traj, int64_t (&mom)[kMomentWords]) {
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     for (uint32_t m = 0; m < a.k_steps; ++m) {
         const uint32_t n = a.step0 + m;
@@ -236,11 +237,20 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS
             int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
             block_sum_i64<3>(v, red);
             if (threadIdx.x == 0) {
-                int64_t* out3 = trace + 3u * (size_t)((m + 1) / a.obs_every - 1);
                 const int64_t sites = (int64_t)hA.n_words * 64;
-                out3[0] = 2 * v[0] - sites;
-                out3[1] = 2 * sites - 2 * v[1];
-                out3[2] = sites - 2 * v[2];
+                const int64_t M = 2 * v[0] - sites, A = 2 * sites - 2 * v[1], B = sites - 2 * v[2];
+                if (a.moments) {
+                    mom[0] += M;
+                    mom[1] += M * M;
+                    mom[2] += M < 0 ? -M : M;
+                    mom[3] += A;
+                    mom[4] += B;
+                } else {
+                    int64_t* out3 = trace + 3u * (size_t)((m + 1) / a.obs_every - 1);
+                    out3[0] = M;
+                    out3[1] = A;
+                    out3[2] = B;
+                }
             }
         } else {
             lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
@@ -335,7 +345,13 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         if (traj)
             store_lattice(traj, sig, n_words);
 
-        run_steps<PAIRED, COMPLEMENT, BITS>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj);
+        int64_t mom[kMomentWords] = {0, 0, 0, 0, 0};
+        run_steps<PAIRED, COMPLEMENT, BITS>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj, mom);
+        if (a.moments && trace && threadIdx.x == 0) {
+#pragma unroll
+            for (uint32_t i = 0; i < kMomentWords; ++i)
+                trace[i] = mom[i];
+        }
         if (traj) {
             __syncthreads();
             continue;

@@ -37,6 +37,8 @@ struct BatchArgs {
     uint32_t int8_io;        // lattices in global memory are int8 (L % 64 == 0)
     uint32_t paired;         // every chain of the launch has a paired threshold table
     uint32_t bits;           // the chains' L % 64 != 0 (L % 8 == 0): bit-string neighbours
+    uint32_t moments;        // traces hold, per chain, sum M, sum M^2, sum |M|, sum A, sum B over the
+                             // recorded steps (kMomentWords int64) instead of the records
     uint32_t n_uniform;      // counter null and n_uniform > 0: workgroup b runs `single` with stream
                              // single.stream + b from packed sigma single_sig + b * lattice bytes
     uint8_t* traj;           // non-null: workgroup b writes lattice x of its trajectory (x = 0 the
@@ -47,6 +49,8 @@ struct BatchArgs {
 
 // Dynamic LDS of a launch: the two lattice buffers and one list of undecided
 // words per wavefront of a threads-sized workgroup.
+constexpr uint32_t kMomentWords = 5;
+
 size_t batch_lds_bytes(uint32_t max_words, uint32_t threads);
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);

@@ -172,3 +172,62 @@ def test_sd_tune_keeps_results_and_caches(tmp_path, L, layout):
     assert f"L={L}:layout={layout}" in text
     sd.sd_tune(L, layout, path)          # from the cache
     assert sd.sd_tuned_choice(L, layout) == choice
+
+
+def test_batch_moments_equal_sums_of_traces():
+    # SD_FLAG_MOMENTS keeps, per chain, sum M, sum M^2, sum |M|, sum A, sum B
+    # over the recorded steps: exactly the sums of the records of a trace plan
+    J, q, L, st = _chains(10, [40, 64, 200], seed=21)
+    k, every = 40, 2
+    plans = {}
+    for flags in (0, sd.SD_FLAG_MOMENTS):
+        plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=k, obs_every=every, flags=flags)
+        lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+        tr = torch.full((sd.sd_batch_trace_len(plan),), -3, dtype=torch.int64, device="cuda")
+        sd.sd_batch_init(plan, lat, sd.SD_INIT_DOWN)
+        sd.sd_batch_run(plan, lat, tr, 11)
+        torch.cuda.synchronize()
+        plans[flags] = (lat.cpu(), tr.cpu().numpy())
+        plan.close()
+    assert torch.equal(plans[0][0], plans[sd.SD_FLAG_MOMENTS][0])
+    rec = plans[0][1].reshape(len(J), k // every, 3).astype(np.int64)
+    M, A, B = rec[..., 0], rec[..., 1], rec[..., 2]
+    want = np.stack([M.sum(1), (M * M).sum(1), np.abs(M).sum(1), A.sum(1), B.sum(1)], axis=1)
+    assert np.array_equal(plans[sd.SD_FLAG_MOMENTS][1].reshape(len(J), 5), want)
+
+
+def test_critical_scan_moments_small(oracle):
+    # the section 3.1 pipeline at small scale, against the oracle: from all -1
+    # on a 64 x 64 torus at q = 0.6585 (J_c(q) = 0.6585 by eq. (12)), a warm-up
+    # plan then a moments plan; the sums equal those of the oracle's records,
+    # and m relaxes to 0 below the curve, stays near -1 above it and
+    # fluctuates most near J_c
+    q, L, warm, rec = 0.6585, 64, 4000, 4000
+    Js = np.array([0.3, 0.6585, 1.0])
+    qs = np.full(3, q)
+    Ls = np.full(3, L)
+    st = np.arange(3, dtype=np.uint32)
+    pw = sd.sd_batch_plan_create(Js, qs, Ls, st, seed=5, k_steps=warm, obs_every=0)
+    pr = sd.sd_batch_plan_create(Js, qs, Ls, st, seed=5, k_steps=rec, obs_every=1, flags=sd.SD_FLAG_MOMENTS)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(pr), dtype=torch.uint8, device="cuda")
+    mom = torch.zeros(sd.sd_batch_trace_len(pr), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(pw, lat, sd.SD_INIT_DOWN)
+    sd.sd_batch_run(pw, lat, None, 0)
+    sd.sd_batch_run(pr, lat, mom, warm)
+    torch.cuda.synchronize()
+    got = mom.cpu().numpy().reshape(3, 5)
+    pw.close()
+    pr.close()
+    for c in range(3):
+        s0 = np.full((L, L), -1, np.int8)
+        s1, _, _ = oracle.run(s0, Js[c], q, 5, c, 0, warm)
+        _, _, obs = oracle.run(s1, Js[c], q, 5, c, warm, rec, obs_every=1)
+        M, A, B = (obs[:, i].astype(np.int64) for i in range(3))
+        assert np.array_equal(got[c], [M.sum(), (M * M).sum(), np.abs(M).sum(), A.sum(), B.sum()]), c
+    S = got.astype(np.float64)
+    N = float(L * L)
+    mean = S[:, 0] / (rec * N)
+    var = S[:, 1] / (rec * N * N) - mean ** 2
+    absm = S[:, 2] / (rec * N)
+    assert absm[0] < 0.05 and mean[2] < -0.95
+    assert var[1] > 3 * var[0] and var[1] > 3 * var[2]
