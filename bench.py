@@ -152,6 +152,8 @@ def parse():
     p.add_argument("--scan-L", type=int, default=200)
     p.add_argument("--scan-warm", type=int, default=300000)
     p.add_argument("--scan-rec", type=int, default=300000)
+    p.add_argument("--coalescence", action="store_true",
+                   help="only the coalescence times of section 3.2 (32x32, monotone coupling)")
     p.add_argument("--table1", action="store_true",
                    help="only the diagonal-correlation comparison with Table 1 (32x32, all (q, J) rows)")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -400,6 +402,64 @@ def bench_critical_scan(sd, torch, n_grid, L, warm, rec, tune_cache):
             "mean_abs_m_far_above_curve": float(mean_abs[Jv > critical_J(qv) + 0.2].mean())}
 
 
+def coalescence_times(sd, torch, J, q, L, n_pairs, seed=1, chunk=1000, max_steps=200000, stream0=0):
+    """Coalescence times of the monotone coupling (section 3.2): pair p is a
+    chain from all +1 and one from all -1 sharing stream stream0 + p, so both
+    draw the same uniforms.  The coupling keeps sigma_top >= sigma_bottom site
+    by site, hence the two lattices are equal exactly when their
+    magnetisations are: T_p = first step with M_top = M_bottom (-1 if none
+    within max_steps).  Runs as one batch plan, chunk steps per launch."""
+    n = 2 * n_pairs
+    streams = np.repeat(np.arange(stream0, stream0 + n_pairs, dtype=np.uint32), 2)
+    plan = sd.sd_batch_plan_create(np.full(n, J), np.full(n, q), np.full(n, L), streams, seed=seed, k_steps=chunk,
+                                   obs_every=1)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    tr = torch.zeros(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_DOWN)
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    for p_ in range(n_pairs):
+        off = sd.sd_batch_chain_offset(plan, 2 * p_, 0)
+        lat[off:off + nb].fill_(0xFF)
+    T = torch.full((n_pairs,), -1, dtype=torch.int64, device="cuda")
+    steps = torch.arange(1, chunk + 1, device="cuda")
+    step = 0
+    while step < max_steps:
+        sd.sd_batch_run_direct(plan, lat, tr, step)
+        M = tr.view(n, chunk, 3)[:, :, 0]
+        eq = M[0::2] == M[1::2]
+        first = torch.where(eq, steps, chunk + 1).min(dim=1).values
+        newly = (T < 0) & (first <= chunk)
+        T = torch.where(newly, step + first, T)
+        step += chunk
+        if bool((T >= 0).all()):
+            break
+    plan.close()
+    return T.cpu().numpy()
+
+
+def bench_coalescence(sd, torch, L=32, n_pairs=256):
+    """Mean coalescence time on a 32x32 torus for J = q (the isotropic
+    honeycomb model whose critical point is J = q = 0.6585) and at points
+    just below and above the critical curve J_c(q) of eq. (12)."""
+    rows = []
+    t0 = time.perf_counter()
+    pts = [(x, x) for x in (0.3, 0.4, 0.5, 0.55, 0.6, 0.63, 0.6585, 0.68, 0.7)]
+    for qq in (0.2, 1.0, 2.5):
+        jc = float(critical_J(qq))
+        pts += [(qq, jc - 0.05), (qq, jc), (qq, jc + 0.05)]
+    for idx, (q, J) in enumerate(pts):
+        T = coalescence_times(sd, torch, J, q, L, n_pairs, seed=1, stream0=1000 * idx)
+        done = T[T >= 0]
+        rows.append({"q": round(q, 4), "J": round(J, 4), "J_minus_Jc": round(J - float(critical_J(q)), 4),
+                     "pairs": n_pairs, "coalesced": int(len(done)),
+                     "mean_T": float(done.mean()) if len(done) else None,
+                     "median_T": float(np.median(done)) if len(done) else None,
+                     "max_T": int(done.max()) if len(done) else None})
+        log(f"[bench] coalescence q={q:.4f} J={J:.4f}: {rows[-1]['mean_T']} ({len(done)}/{n_pairs})")
+    return {"workload": f"{L}x{L} torus, {n_pairs} coupled pairs per point (all +1 / all -1, shared stream), "
+                        f"cap 200000 steps", "rows": rows, "seconds": time.perf_counter() - t0}
+
+
 def bench_table1(sd, torch, burn=2000, n_meas=4000, every=5, L=32):
     """Time-averaged diagonal correlations C(l) = D(l) / L^2 on a 32x32 torus at
     every (q, J) row of Table 1 (section 3.3), next to the printed values
@@ -477,6 +537,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.table1:
         print(json.dumps({"table1": bench_table1(sd, torch)}), flush=True)
+        return
+    if args.coalescence:
+        print(json.dumps({"coalescence": bench_coalescence(sd, torch)}), flush=True)
         return
     if args.critical_scan:
         out = bench_critical_scan(sd, torch, args.scan_grid, args.scan_L, args.scan_warm, args.scan_rec,

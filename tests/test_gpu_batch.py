@@ -231,3 +231,44 @@ def test_critical_scan_moments_small(oracle):
     absm = S[:, 2] / (rec * N)
     assert absm[0] < 0.05 and mean[2] < -0.95
     assert var[1] > 3 * var[0] and var[1] > 3 * var[2]
+
+
+def test_coalescence_times_match_oracle(oracle):
+    # section 3.2: chains from all +1 and all -1 sharing a stream stay ordered
+    # site by site, so they have met exactly when their magnetisations agree;
+    # the first such step from the batched records equals the first step at
+    # which the oracle's two lattices are identical
+    L, J, q, n_pairs, chunk, cap = 16, 0.45, 0.45, 8, 25, 1000
+    n = 2 * n_pairs
+    streams = np.repeat(np.arange(300, 300 + n_pairs, dtype=np.uint32), 2)
+    plan = sd.sd_batch_plan_create(np.full(n, J), np.full(n, q), np.full(n, L), streams, seed=SEED,
+                                   k_steps=chunk, obs_every=1)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    tr = torch.zeros(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_DOWN)
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    for p_ in range(n_pairs):
+        off = sd.sd_batch_chain_offset(plan, 2 * p_, 0)
+        lat[off:off + nb].fill_(0xFF)
+    M = []
+    for step in range(0, cap, chunk):
+        sd.sd_batch_run_direct(plan, lat, tr, step)
+        torch.cuda.synchronize()
+        M.append(tr.view(n, chunk, 3)[:, :, 0].cpu().numpy().copy())
+    plan.close()
+    M = np.concatenate(M, axis=1)
+    for p_ in range(n_pairs):
+        eq = np.flatnonzero(M[2 * p_] == M[2 * p_ + 1])
+        t_gpu = int(eq[0]) + 1 if len(eq) else -1
+        top = np.ones((L, L), np.int8)
+        bot = -np.ones((L, L), np.int8)
+        t_ref = -1
+        for step in range(cap):
+            top, _, _ = oracle.run(top, J, q, SEED, 300 + p_, step, 1)
+            bot, _, _ = oracle.run(bot, J, q, SEED, 300 + p_, step, 1)
+            assert np.all(top >= bot)
+            if np.array_equal(top, bot):
+                t_ref = step + 1
+                break
+        assert t_gpu == t_ref, (p_, t_gpu, t_ref)
+        assert t_ref > 0
