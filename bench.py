@@ -142,7 +142,7 @@ def parse():
     p.add_argument("--no-loglik", action="store_true", help="skip the log-likelihood leg")
     p.add_argument("--batch-steps", type=int, default=5000)
     p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
-    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 512 MiB device copy first (counter calibration runs)")

@@ -213,7 +213,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
             }
             return best_ms / 1e3;
         };
-        best = tune_pick({128, 256, 512}, measure);
+        best = tune_pick({64, 128, 256, 512}, measure);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -38,25 +38,34 @@ struct HalfCtx {
     FastDiv divL;   // division by L (bit strings)
 };
 
+// Rows of whole words: the word at row j, column word w (g = j * W + w).
+template <int WHICH, bool BITS>
+__device__ __forceinline__ void gather_lds_at(const HalfCtx<BITS>& h, uint32_t j, uint32_t w, uint64_t& c,
+                                              uint64_t& n1, uint64_t& n2) {
+    const uint32_t row = j * h.W;
+    c = h.src[row + w];
+    const uint32_t c_lo = (uint32_t)c, c_hi = (uint32_t)(c >> 32);
+    if constexpr (WHICH == 0) {
+        n1 = h.src[(j == 0 ? h.L - 1 : j - 1) * h.W + w];
+        const uint32_t prev_hi = (uint32_t)(h.src[row + (w == 0 ? h.W - 1 : w - 1)] >> 32);
+        n2 = (uint64_t)__builtin_amdgcn_alignbit(c_lo, prev_hi, 31) |
+             ((uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 31) << 32);
+    } else {
+        n1 = h.src[(j == h.L - 1 ? 0 : j + 1) * h.W + w];
+        const uint32_t next_lo = (uint32_t)h.src[row + (w == h.W - 1 ? 0 : w + 1)];
+        n2 = (uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 1) |
+             ((uint64_t)__builtin_amdgcn_alignbit(next_lo, c_hi, 1) << 32);
+    }
+}
+
 template <int WHICH, bool BITS>
 __device__ __forceinline__ void gather_lds(const HalfCtx<BITS>& h, uint32_t g, uint64_t& c, uint64_t& n1,
                                            uint64_t& n2) {
     if constexpr (BITS) {
         gather_bits<WHICH>(h.src, h.L, h.n_words, h.divL, g, c, n1, n2);
-        return;
-    }
-    const uint32_t j = fdiv(g, h.divW);
-    const uint32_t w = g - j * h.W;
-    const uint32_t row = j * h.W;
-    c = h.src[g];
-    if constexpr (WHICH == 0) {
-        n1 = h.src[(j == 0 ? h.L - 1 : j - 1) * h.W + w];
-        const uint64_t prev = h.src[row + (w == 0 ? h.W - 1 : w - 1)];
-        n2 = (c << 1) | (prev >> 63);
     } else {
-        n1 = h.src[(j == h.L - 1 ? 0 : j + 1) * h.W + w];
-        const uint64_t next = h.src[row + (w == h.W - 1 ? 0 : w + 1)];
-        n2 = (c >> 1) | (next << 63);
+        const uint32_t j = fdiv(g, h.divW);
+        gather_lds_at<WHICH>(h, j, g - j * h.W, c, n1, n2);
     }
 }
 
@@ -120,12 +129,35 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
     const uint32_t n_waves = blockDim.x >> 6;
     const uint32_t n_tiles = (h.n_words + 63u) / 64u;
     uint32_t listed = 0;   // wavefront-uniform
+    // rows of whole words: (row, column word) of the lane's word, stepped by
+    // the 64 * n_waves words between a wavefront's tiles
+    uint32_t j = 0, w = 0, step_rows = 0, step_cols = 0;
+    if constexpr (!BITS) {
+        const uint32_t g0 = 64u * (threadIdx.x >> 6) + lane;
+        j = fdiv(g0, h.divW);
+        w = g0 - j * h.W;
+        const uint32_t step = 64u * n_waves;
+        step_rows = step / h.W;
+        step_cols = step - step_rows * h.W;
+    }
     for (uint32_t tile = threadIdx.x >> 6; tile < n_tiles; tile += n_waves) {
         const uint32_t g = 64u * tile + lane;
         const bool active = g < h.n_words;
         uint64_t c = 0, n1 = 0, n2 = 0;
-        if (active)
-            gather_lds<WHICH>(h, g, c, n1, n2);
+        if (active) {
+            if constexpr (BITS)
+                gather_lds<WHICH>(h, g, c, n1, n2);
+            else
+                gather_lds_at<WHICH>(h, j, w, c, n1, n2);
+        }
+        if constexpr (!BITS) {
+            w += step_cols;
+            j += step_rows;
+            if (w >= h.W) {
+                w -= h.W;
+                ++j;
+            }
+        }
         uint64_t P[8];
         draw_planes(dp, active ? g : 0u, P);
         const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
@@ -292,12 +324,25 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
                 break;
             cd = a.single;
         }
+        // the chain's geometry is the same for the whole workgroup: keep it in
+        // scalar registers
+        auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
+        auto uni_div = [&](const FastDiv& f) {
+            FastDiv u;
+            u.d = uni(f.d);
+            u.mul = uni(f.mul);
+            u.shift = uni(f.shift);
+            u.add = uni(f.add);
+            return u;
+        };
+        cd.L = uni(cd.L);
+        cd.stream = uni(cd.stream);
         HalfCtx<BITS> hA, hB;
         hA.L = hB.L = cd.L;
         hA.W = hB.W = cd.L / 64u;
         hA.n_words = hB.n_words = (uint32_t)(((uint64_t)cd.L * cd.L) / 64u);
-        hA.divW = hB.divW = cd.divW;
-        hA.divL = hB.divL = cd.divL;
+        hA.divW = hB.divW = uni_div(cd.divW);
+        hA.divL = hB.divL = uni_div(cd.divL);
         hA.src = sig; hA.dst = tau;
         hB.src = tau; hB.dst = sig;
         const uint32_t n_words = hA.n_words;

@@ -310,3 +310,38 @@ def test_diagonal_correlations_table1_qualitative():
     assert small_q[1, 1] > 0.6
     large_q = _diag_average(32, 0.43, 2.5, 400, 10, 16, 2)
     assert abs(large_q[1, 1] - large_q[0, 1]) < 0.2
+
+
+@pytest.mark.parametrize("L,layout", [(64, sd.SD_P64), (256, sd.SD_P64), (1024, sd.SD_P64), (40, sd.SD_P64)])
+def test_run_captured_in_a_graph_replays_like_eager(L, layout):
+    # sd_run enqueues only kernels on the caller's stream, so it can be
+    # captured; every replay of the graph advances the chain by the same steps
+    # as an eager call (the graph fixes step0, so replay r repeats those steps
+    # on the lattice the previous replay left).  Eager work and
+    # synchronisations run between the replays.
+    J, q, k, every = 0.5, 0.5, 6, 3
+    s0 = inputs.random_lattice(L, 91)
+    sig_g, tau_g = to_device(s0, layout), sd.new_lattice(L, layout)
+    sig_e, tau_e = to_device(s0, layout), sd.new_lattice(L, layout)
+    obs_g = torch.zeros((k // every, 3), dtype=torch.int64, device="cuda")
+    obs_e = torch.zeros_like(obs_g)
+    # one eager call first, so that the library's scratch for the observables
+    # exists before the capture
+    warm = sd.new_lattice(L, layout)
+    sd.sd_run(to_device(s0, layout), warm, L, layout, J, q, SEED, 5, 0, every, obs_e, every)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            sd.sd_run(sig_g, tau_g, L, layout, J, q, SEED, 5, 0, k, obs_g, every, hip_stream=side)
+    torch.cuda.synchronize()
+    sig_g.copy_(to_device(s0, layout))
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        sd.sd_run(sig_e, tau_e, L, layout, J, q, SEED, 5, 0, k, obs_e, every)
+        torch.cuda.synchronize()
+        assert torch.equal(sig_g, sig_e) and torch.equal(tau_g, tau_e), (L, r)
+        assert torch.equal(obs_g, obs_e), (L, r)
