@@ -76,6 +76,10 @@ def lib():
         L.or_run.restype = c.c_int
         L.or_loglik_counts.argtypes = [i8p, c.c_int, c.c_int, c.c_int, i64p]
         L.or_loglik_counts.restype = c.c_int
+        L.or_loglik_stats.argtypes = [i8p, c.c_int, c.c_int, c.c_int, i64p]
+        L.or_loglik_stats.restype = c.c_int
+        L.or_loglik_from_stats.argtypes = [i64p, c.c_double, c.c_double, ctypes.POINTER(c.c_double)]
+        L.or_loglik_from_stats.restype = c.c_double
         L.or_loglik.argtypes = [i64p, c.c_double, c.c_double]
         L.or_loglik.restype = c.c_double
         L.or_loglik_grad.argtypes = [i64p, c.c_double, c.c_double, ctypes.POINTER(c.c_double)]
@@ -228,6 +232,26 @@ def loglik_counts(traj: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise ValueError("bad trajectory shape")
     return out
+
+
+def loglik_stats(traj: np.ndarray) -> np.ndarray:
+    """traj: [n_traj, n_lat, L, L] int8 -> 6 int64 paired statistics
+    (S_0, S_1, S_2, Z_0, Z_1, Z_2) of the class pairs (0,5), (1,4), (2,3)."""
+    traj = np.ascontiguousarray(traj, dtype=np.int8)
+    n_traj, n_lat, L, _ = traj.shape
+    out = np.zeros(6, dtype=np.int64)
+    rc = lib().or_loglik_stats(_p(traj, ctypes.c_int8), n_traj, n_lat, L, _p(out, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("bad trajectory shape")
+    return out
+
+
+def loglik_from_stats(stats: np.ndarray, J: float, q: float):
+    """(LL, gradient) in FP64 from the 6 paired statistics."""
+    st = np.ascontiguousarray(stats, dtype=np.int64)
+    g = np.zeros(2, dtype=np.float64)
+    ll = float(lib().or_loglik_from_stats(_p(st, ctypes.c_int64), float(J), float(q), _p(g, ctypes.c_double)))
+    return ll, g
 
 
 def loglik(counts: np.ndarray, J: float, q: float) -> float:

@@ -411,6 +411,70 @@ OR_EXPORT int or_loglik_counts(const int8_t* traj, int n_traj, int n_lat, int L,
     return 0;
 }
 
+/* Paired sufficient statistics.  Classes idx and 5 - idx have opposite fields
+ * (h -> -h); log 2cosh is even and tanh odd, so the log-likelihood and its
+ * gradient depend on each pair j = (j, 5 - j), j = 0, 1, 2, only through
+ *   S_j = number of sites of the pair,
+ *   Z_j = sites of class j drawn +1 plus sites of class 5 - j drawn -1,
+ * by a site loop over every transition as in or_loglik_counts.
+ * stats[0..2] = S_0..S_2, stats[3..5] = Z_0..Z_2. */
+OR_EXPORT int or_loglik_stats(const int8_t* traj, int n_traj, int n_lat, int L, int64_t stats[6])
+{
+    if (n_traj < 0 || n_lat < 1 || L < 2)
+        return -1;
+    memset(stats, 0, 6 * sizeof(int64_t));
+    size_t N = (size_t)L * (size_t)L;
+    for (int a = 0; a < n_traj; ++a) {
+        for (int m = 0; m + 1 < n_lat; ++m) {
+            const int8_t* X = traj + ((size_t)a * (size_t)n_lat + (size_t)m) * N;
+            const int8_t* Y = X + N;
+            for (int j = 0; j < L; ++j) {
+                for (int i = 0; i < L; ++i) {
+                    int n1, n2;
+                    if ((m & 1) == 0) {
+                        n1 = X[or_site(L, i, j - 1)];
+                        n2 = X[or_site(L, i - 1, j)];
+                    } else {
+                        n1 = X[or_site(L, i, j + 1)];
+                        n2 = X[or_site(L, i + 1, j)];
+                    }
+                    int idx = or_class_index(n1, n2, X[or_site(L, i, j)]);
+                    int s = Y[or_site(L, i, j)];
+                    int leader = idx < 3;
+                    int pair = leader ? idx : 5 - idx;
+                    stats[pair] += 1;
+                    stats[3 + pair] += leader ? (s > 0) : (s < 0);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* LL and its gradient from the paired statistics, in FP64: the leader class j
+ * has h_j = J (2k - 2) + q c, and the pair contributes
+ * h_j (2 Z_j - S_j) - S_j log 2cosh h_j, resp. (a_j, c_j) (2 Z_j - S_j - S_j tanh h_j). */
+static double or_log2cosh(double h);
+
+OR_EXPORT double or_loglik_from_stats(const int64_t stats[6], double J, double q, double grad[2])
+{
+    double ll = 0.0, gJ = 0.0, gq = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        int k = j >> 1, cplus = j & 1;
+        double a = (double)(2 * k - 2), c = (double)(2 * cplus - 1);
+        double h = J * a + q * c;
+        double S = (double)stats[j], D = 2.0 * (double)stats[3 + j] - (double)stats[j];
+        ll += h * D - S * or_log2cosh(h);
+        gJ += a * (D - S * tanh(h));
+        gq += c * (D - S * tanh(h));
+    }
+    if (grad) {
+        grad[0] = gJ;
+        grad[1] = gq;
+    }
+    return ll;
+}
+
 /* log(2 cosh h) without overflow: |h| + log1p(exp(-2|h|)). */
 static double or_log2cosh(double h)
 {

@@ -99,3 +99,46 @@ def test_mle_recovers_generating_parameters(oracle):
     assert np.linalg.norm(oracle.loglik_grad(c, *theta)) < 1e-6 * c.sum()
     assert abs(theta[0] - J0) < 3 * se[0], (theta, se)
     assert abs(theta[1] - q0) < 3 * se[1], (theta, se)
+
+
+def _pair_map(c):
+    """Linear map from the 12 transition counts (class 2k + [c = +1], drawn
+    spin) to the paired statistics: the pair is (j, 5 - j), j = 0, 1, 2."""
+    S = [c[2 * j] + c[2 * j + 1] + c[2 * (5 - j)] + c[2 * (5 - j) + 1] for j in range(3)]
+    Z = [c[2 * j + 1] + c[2 * (5 - j)] for j in range(3)]
+    return np.array(S + Z, dtype=np.int64)
+
+
+@pytest.mark.parametrize("L,k", [(3, 6), (8, 5), (10, 3)])
+def test_paired_stats_are_the_pair_map_of_the_counts(oracle, L, k):
+    traj = np.stack([oracle.trajectory(oracle.init(L, 2, 0.5, 1, a), 0.4, 0.6, SEED, a, 0, k) for a in range(3)])
+    s = oracle.loglik_stats(traj)
+    assert np.array_equal(s, _pair_map(oracle.loglik_counts(traj)))
+    assert s[:3].sum() == 3 * 2 * k * L * L
+    assert np.all(s[3:] <= s[:3]) and np.all(s[3:] >= 0)
+
+
+@pytest.mark.parametrize("J,q", [(0.4, 0.6), (1.1, -0.3), (0.0, 0.8)])
+def test_paired_loglik_equals_exact_transition_log_probabilities(oracle, J, q):
+    L, k = 3, 6
+    traj = oracle.trajectory(oracle.init(L, 2, 0.5, 4, 1), J, q, SEED, 1, 0, k)
+    s = oracle.loglik_stats(traj[None])
+    for Je, qe in [(J, q), (J - 0.2, q + 0.5)]:
+        ex = en.Enumeration(L, Je, qe)
+        exact = sum(math.log((ex.K_A if m % 2 == 0 else ex.K_B)[en.config_index(traj[m]), en.config_index(traj[m + 1])])
+                    for m in range(2 * k))
+        ll, _ = oracle.loglik_from_stats(s, Je, qe)
+        assert math.isclose(ll, exact, rel_tol=1e-12, abs_tol=1e-10)
+
+
+def test_paired_gradient_matches_central_differences(oracle):
+    traj = np.stack([oracle.trajectory(oracle.init(16, 2, 0.5, 1, a), 0.45, 0.7, SEED, a, 0, 10) for a in range(2)])
+    s = oracle.loglik_stats(traj)
+    scale = 2.0 * s[:3].sum()
+    for J, q in [(0.2, 0.2), (0.45, 0.7), (1.0, -1.5), (0.0, 0.0)]:
+        _, g = oracle.loglik_from_stats(s, J, q)
+        eps = 1e-5
+        fdJ = (oracle.loglik_from_stats(s, J + eps, q)[0] - oracle.loglik_from_stats(s, J - eps, q)[0]) / (2 * eps)
+        fdq = (oracle.loglik_from_stats(s, J, q + eps)[0] - oracle.loglik_from_stats(s, J, q - eps)[0]) / (2 * eps)
+        assert abs(g[0] - fdJ) <= 1e-7 * scale, (J, q, g[0], fdJ)
+        assert abs(g[1] - fdq) <= 1e-7 * scale, (J, q, g[1], fdq)
