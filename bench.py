@@ -302,29 +302,39 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     counts = torch.empty(12, dtype=torch.int64, device="cuda")
-    sd.sd_loglik_counts(traj, n_traj, n_lat, L, counts)   # warm-up
+    stats = torch.empty(6, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 3
-    e0.record(stream)
-    for _ in range(reps):
-        sd.sd_loglik_counts(traj, n_traj, n_lat, L, counts)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(fn, out, reps=3):
+        fn(traj, n_traj, n_lat, L, out)   # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn(traj, n_traj, n_lat, L, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(sd.sd_loglik_counts, counts)
+    ms_st = timed(sd.sd_loglik_stats, stats)
     gbs = traj.numel() * 8 / (ms * 1e-3) / 1e9
+    gbs_st = traj.numel() * 8 / (ms_st * 1e-3) / 1e9
+    ch = counts.cpu().numpy()
+    sh = stats.cpu().numpy()
+    pair_map = [ch[2 * j] + ch[2 * j + 1] + ch[2 * (5 - j)] + ch[2 * (5 - j) + 1] for j in range(3)]
+    pair_map += [ch[2 * j + 1] + ch[2 * (5 - j)] for j in range(3)]
+    stats_consistent = bool(np.array_equal(sh, np.array(pair_map)))
     # gradient at the ascent start, against FP64 from the same integer counts
     Jq = torch.tensor([0.2, 0.2], dtype=torch.float32, device="cuda", requires_grad=True)
-    ll = AG.loglik(Jq, counts)
+    ll = AG.loglik(Jq, stats)
     (g,) = torch.autograd.grad(ll, Jq)
-    ch = counts.cpu().numpy()
     g64 = _fp64_grad(ch, 0.2, 0.2)
     rel = float(np.max(np.abs(g.cpu().numpy().astype(np.float64) - g64) / np.abs(g64)))
-    # gradient ascent on LL / N from (0.2, 0.2)
+    # gradient ascent on LL / N from (0.2, 0.2), on the paired statistics
     N = float(ch.sum())
     x = torch.tensor([0.2, 0.2], dtype=torch.float32, device="cuda", requires_grad=True)
     for _ in range(300):
-        (gg,) = torch.autograd.grad(AG.loglik(x, counts) / N, x)
+        (gg,) = torch.autograd.grad(AG.loglik(x, stats) / N, x)
         with torch.no_grad():
             x += 0.5 * gg
     est = x.detach().cpu().numpy().tolist()
@@ -332,6 +342,8 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
     return {"workload": f"{n_traj} trajectories of {L}x{L}, {k} steps at (J,q)=({J},{q}), random starts",
             "transitions": int(N), "trajectory_GB": n_traj * n_lat * nb / 1e9, "generate_seconds": t_gen,
             "counts_ms": ms, "counts_GBps": gbs, "counts_hbm_frac": gbs / HBM_PEAK_GBS,
+            "stats_ms": ms_st, "stats_GBps": gbs_st, "stats_hbm_frac": gbs_st / HBM_PEAK_GBS,
+            "stats_equal_pair_map_of_counts": stats_consistent,
             "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est}
 
 
@@ -587,7 +599,7 @@ def main():
     if not args.no_loglik:
         log("[bench] log-likelihood")
         out["loglik"] = bench_loglik(sd, torch)
-        log(f"[bench] counts {out['loglik']['counts_GBps']:.0f} GB/s")
+        log(f"[bench] counts {out['loglik']['counts_GBps']:.0f} GB/s, paired stats {out['loglik']['stats_GBps']:.0f} GB/s")
     if not args.no_cpu:
         log(f"[bench] CPU oracle, {args.cpu_steps} step(s) at L={L}")
         out["cpu_baseline"] = bench_cpu(L, args.cpu_steps)

@@ -230,6 +230,37 @@ SD_API sd_status sd_loglik_fwd(const int64_t* counts12, const float* Jq, float* 
 SD_API sd_status sd_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
                                void* hip_stream);
 
+/*
+ * Paired sufficient statistics of the same log-likelihood (same trajectories,
+ * layout and L as sd_loglik_counts).  The classes idx and 5 - idx have
+ * opposite fields h, and log 2cosh is even and tanh odd, so LL and its
+ * gradient depend on each pair (j, 5 - j), j = 0, 1, 2, only through
+ *   stats6[j]     = S_j = sites of class j or 5 - j,
+ *   stats6[3 + j] = Z_j = sites of class j drawn +1 plus sites of class 5 - j
+ *                         drawn -1
+ * (device, 6 int64, over every transition of every trajectory).  In terms of
+ * the 12 counts: S_j = n[2j] + n[2j+1] + n[2(5-j)] + n[2(5-j)+1],
+ * Z_j = n[2j+1] + n[2(5-j)].  Exact integers; five popcounts per word and
+ * transition where the counts take twelve.
+ */
+SD_API sd_status sd_loglik_stats(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* stats6,
+                                 void* hip_stream);
+
+/*
+ * ll[0] (device float) = LL(J, q) = sum_j h_j (2 Z_j - S_j) - S_j log 2cosh h_j
+ * from the paired statistics, h_j the field of class j (h_j = J(2k-2) + q(2c-1)
+ * with j = 2k + [c = +1]).  Same arithmetic as sd_loglik_fwd.
+ */
+SD_API sd_status sd_loglik_fwd_stats(const int64_t* stats6, const float* Jq, float* ll, void* hip_stream);
+
+/*
+ * grad[0..1] (device floats) = g_out[0] * (dLL/dJ, dLL/dq) from the paired
+ * statistics: dLL/dJ = sum_j (2k-2)(2 Z_j - S_j - S_j tanh h_j), dLL/dq the
+ * same with (2c-1).  g_out may be NULL for 1.  Same arithmetic as sd_loglik_bwd.
+ */
+SD_API sd_status sd_loglik_bwd_stats(const int64_t* stats6, const float* Jq, const float* g_out, float* grad,
+                                     void* hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Batched scan: many independent chains in one persistent launch.            */
 /* ------------------------------------------------------------------------- */

@@ -55,6 +55,9 @@ SIGNATURES = {
     "sd_loglik_counts": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "sd_loglik_stats": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_loglik_fwd_stats": (_I32, [_VP, _VP, _VP, _VP]),
+    "sd_loglik_bwd_stats": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "sd_tune": (_I32, [_I32, _I32, ctypes.c_char_p, _VP]),
     "sd_tuned_choice": (_I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                ctypes.POINTER(_I32)]),
@@ -176,6 +179,18 @@ def sd_loglik_fwd(counts12, Jq, ll, hip_stream=None) -> None:
 
 def sd_loglik_bwd(counts12, Jq, g_out, grad, hip_stream=None) -> None:
     _check(lib().sd_loglik_bwd(_ptr(counts12), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
+
+
+def sd_loglik_stats(traj, n_traj, n_lat, L, stats6, hip_stream=None) -> None:
+    _check(lib().sd_loglik_stats(_ptr(traj), n_traj, n_lat, L, _ptr(stats6), _stream(hip_stream)))
+
+
+def sd_loglik_fwd_stats(stats6, Jq, ll, hip_stream=None) -> None:
+    _check(lib().sd_loglik_fwd_stats(_ptr(stats6), _ptr(Jq), _ptr(ll), _stream(hip_stream)))
+
+
+def sd_loglik_bwd_stats(stats6, Jq, g_out, grad, hip_stream=None) -> None:
+    _check(lib().sd_loglik_bwd_stats(_ptr(stats6), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
 
 
 class sd_batch_plan:

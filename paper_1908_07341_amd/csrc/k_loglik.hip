@@ -9,8 +9,18 @@
 // are sufficient statistics: LL = sum n (h s - log 2cosh h),
 // dLL/dJ = sum n (2k-2)(s - tanh h),  dLL/dq = sum n c (s - tanh h).
 //
+// The classes idx and 5 - idx have opposite fields, and log 2cosh is even and
+// tanh odd, so LL and its gradient need only the six paired statistics
+//   S_j = sites of the pair (j, 5 - j),
+//   Z_j = sites of class j drawn +1 plus sites of class 5 - j drawn -1,
+// j = 0, 1, 2 (class j is the pair's leader, with field h_j).  Pair 0 holds the
+// sites whose two neighbours agree with the spin, pair 1 those whose neighbours
+// agree with each other but not with the spin, pair 2 those whose neighbours
+// differ; in every pair the drawn spin counts towards Z_j when it differs from
+// the majority of (n1, n2, c).  Five popcounts per word instead of twelve.
+//
 // k_loglik_counts streams the packed trajectories once (HBM-bound) and
-// accumulates the counts exactly in 64-bit integers.  The forward and backward
+// accumulates the counts (or the paired statistics) exactly in integers.  The forward and backward
 // kernels combine them with binary32 arithmetic only; every value is carried
 // as an unevaluated sum of two floats (about 48 significant bits) because near
 // the maximum of the likelihood the per-class terms (size ~N) cancel down to a
@@ -51,7 +61,35 @@ __device__ __forceinline__ void count_transition32(uint64_t c, uint64_t n1, uint
     }
 }
 
-// Workgroup sums of the 12 counts: into partials[12 * block ...] when
+// The paired statistics of one word-transition: acc gets popc(Q0), popc(Q2),
+// and popc(mask_j & z) for j = 0, 1, 2, with Q0 = sites whose neighbours both
+// equal the spin, Q2 = sites whose neighbours differ, W1 = the rest and
+// z = y ^ majority(n1, n2, c).  S_1 follows from the number of sites.
+template <typename T>
+__device__ __forceinline__ void pair_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, T (&acc)[5]) {
+    const uint64_t q2 = n1 ^ n2;
+    const uint64_t q0 = ~((n1 ^ c) | q2);
+    const uint64_t w1 = ~(q0 | q2);
+    const uint64_t z = y ^ ((q2 & c) | (~q2 & n1));
+    const uint64_t v[5] = {q0, q2, q0 & z, w1 & z, q2 & z};
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        acc[i] += __popc((uint32_t)v[i]) + __popc((uint32_t)(v[i] >> 32));
+}
+
+// (S_0, S_1, S_2, Z_0, Z_1, Z_2) from pair_transition's five sums over
+// n_words word-transitions.
+template <typename T>
+__device__ __forceinline__ void pair_stats(const T (&acc)[5], int64_t n_words, int64_t (&out)[6]) {
+    out[0] = (int64_t)acc[0];
+    out[2] = (int64_t)acc[1];
+    out[1] = 64 * n_words - out[0] - out[2];
+    out[3] = (int64_t)acc[2];
+    out[4] = (int64_t)acc[3];
+    out[5] = (int64_t)acc[4];
+}
+
+// Workgroup sums of the 12 counts (or the 6 paired statistics): into partials[12 * block ...] when
 // partials is non-null (k_counts_finish adds them up), else into counts
 // through 64-bit atomics.
 template <int N>
@@ -72,21 +110,22 @@ __device__ __forceinline__ void flush_counts(int64_t (&acc)[N], int64_t* red, un
     }
 }
 
+template <int N>
 __global__ __launch_bounds__(1024) void k_counts_finish(const int64_t* __restrict__ partials, uint32_t n_blocks,
                                                         int64_t* __restrict__ counts) {
-    __shared__ int64_t red[12 * 16];
-    int64_t v[12];
+    __shared__ int64_t red[N * 16];
+    int64_t v[N];
 #pragma unroll
-    for (int i = 0; i < 12; ++i)
+    for (int i = 0; i < N; ++i)
         v[i] = 0;
     for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x)
 #pragma unroll
-        for (int i = 0; i < 12; ++i)
-            v[i] += partials[12u * b + i];
-    block_sum_i64<12>(v, red);
+        for (int i = 0; i < N; ++i)
+            v[i] += partials[(uint32_t)N * b + i];
+    block_sum_i64<N>(v, red);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int i = 0; i < 12; ++i)
+        for (int i = 0; i < N; ++i)
             counts[i] = v[i];
 }
 
@@ -99,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_counts_finish(const int64_t* __restric
 constexpr uint32_t kStageWords = 4096;   // L <= 512
 constexpr uint32_t kChunk = 256;
 
-template <uint32_t WPT, uint32_t DEPTH>
+template <uint32_t WPT, uint32_t DEPTH, bool PAIRED>
 __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __restrict__ traj, uint32_t n_lat,
                                                             uint32_t L, FastDiv divW,
                                                             unsigned long long* __restrict__ counts,
@@ -113,16 +152,21 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
     const uint32_t n_trans = n_lat - 1;
     const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     const uint64_t* X = traj + (size_t)a * n_lat * n_words;
-    uint32_t tot[6], plus[6];
+    uint32_t tot[6], plus[6], pst[5];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
         tot[i] = plus[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        pst[i] = 0;
+    uint32_t n_mine = 0;
     bool mine[WPT];
     uint32_t jj[WPT], ww[WPT];
 #pragma unroll
     for (uint32_t k = 0; k < WPT; ++k) {
         const uint32_t g = threadIdx.x + 256u * k;
         mine[k] = g < n_words;
+        n_mine += mine[k] ? 1u : 0u;
         jj[k] = fdiv(g, divW);
         ww[k] = g - jj[k] * W;
     }
@@ -162,7 +206,10 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
                             n1 = S[(j == L - 1 ? 0 : j + 1) * W + w];
                             n2 = (c >> 1) | (S[j * W + (w == W - 1 ? 0 : w + 1)] << 63);
                         }
-                        count_transition32(c, n1, n2, ring[d][k], tot, plus);
+                        if (PAIRED)
+                            pair_transition(c, n1, n2, ring[d][k], pst);
+                        else
+                            count_transition32(c, n1, n2, ring[d][k], tot, plus);
                         cur[k] = ring[d][k];
                         // refill the slot with lattice m + 1 + DEPTH (the chunk
                         // needs lattices up to m1)
@@ -173,17 +220,24 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
             }
         }
     }
-    int64_t acc[12];
+    if (PAIRED) {
+        int64_t acc[6];
+        pair_stats(pst, (int64_t)n_mine * (m1 - m0), acc);
+        flush_counts<6>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
+    } else {
+        int64_t acc[12];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        acc[2 * i + 1] = plus[i];
-        acc[2 * i] = (int64_t)tot[i] - (int64_t)plus[i];
+        for (int i = 0; i < 6; ++i) {
+            acc[2 * i + 1] = plus[i];
+            acc[2 * i] = (int64_t)tot[i] - (int64_t)plus[i];
+        }
+        flush_counts<12>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
     }
-    flush_counts<12>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Any L % 64 == 0: one lane per word of one trajectory, walking all its
 // transitions; neighbour words from the caches.
+template <bool PAIRED>
 __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restrict__ traj, uint32_t n_traj,
                                                         uint32_t n_lat, uint32_t L, FastDiv divW,
                                                         unsigned long long* __restrict__ counts,
@@ -194,11 +248,15 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
     const uint32_t blocks_per_traj = (n_words + blockDim.x - 1) / blockDim.x;
     const uint32_t a = blockIdx.x / blocks_per_traj;
     const uint32_t g = (blockIdx.x % blocks_per_traj) * blockDim.x + threadIdx.x;
-    int64_t acc[12];
+    int64_t acc[12], pst[5];
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0;
-    if (a < n_traj && g < n_words) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        pst[i] = 0;
+    const bool live = a < n_traj && g < n_words;
+    if (live) {
         const uint32_t j = fdiv(g, divW);
         const uint32_t w = g - j * W;
         const uint32_t down = (j == 0 ? L - 1 : j - 1) * W + w;
@@ -214,11 +272,20 @@ __global__ __launch_bounds__(256) void k_loglik_counts(const uint64_t* __restric
             const uint64_t n1 = Xm[even ? down : up];
             const uint64_t w2 = Xm[even ? prev : next];
             const uint64_t n2 = even ? ((c << 1) | (w2 >> 63)) : ((c >> 1) | (w2 << 63));
-            count_transition(c, n1, n2, y, acc);
+            if (PAIRED)
+                pair_transition(c, n1, n2, y, pst);
+            else
+                count_transition(c, n1, n2, y, acc);
             c = y;
         }
     }
-    flush_counts<12>(acc, red, counts, partials, blockIdx.x);
+    if (PAIRED) {
+        int64_t out[6];
+        pair_stats(pst, live ? (int64_t)(n_lat - 1) : 0, out);
+        flush_counts<6>(out, red, counts, partials, blockIdx.x);
+    } else {
+        flush_counts<12>(acc, red, counts, partials, blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,31 +407,49 @@ __device__ ClassTerms class_terms(int idx, float J, float q) {
     return t;
 }
 
+// Class idx's site count N and signed sum D = (drawn +1) - (drawn -1): from
+// the 12 counts, or (PAIRED, idx < 3) from the pair statistics, where the pair
+// acts as its leader class with N = S_j and D = 2 Z_j - S_j.
+template <bool PAIRED>
+__device__ __forceinline__ void class_sums(const int64_t* __restrict__ v, int idx, int64_t& D, int64_t& N) {
+    if (PAIRED) {
+        N = v[idx];
+        D = 2 * v[3 + idx] - v[idx];
+    } else {
+        N = v[2 * idx + 1] + v[2 * idx];
+        D = v[2 * idx + 1] - v[2 * idx];
+    }
+}
+
+template <bool PAIRED>
 __global__ void k_loglik_fwd(const int64_t* __restrict__ counts, const float* __restrict__ Jq,
                              float* __restrict__ ll) {
     if (blockIdx.x != 0 || threadIdx.x != 0)
         return;
     const float J = Jq[0], q = Jq[1];
     ff acc = {0.0f, 0.0f};
-    for (int idx = 0; idx < 6; ++idx) {
+    for (int idx = 0; idx < (PAIRED ? 3 : 6); ++idx) {
         const ClassTerms t = class_terms(idx, J, q);
-        const int64_t np = counts[2 * idx + 1], nm = counts[2 * idx];
-        const ff d = ff_from_i64(np - nm), N = ff_from_i64(np + nm);
+        int64_t Di, Ni;
+        class_sums<PAIRED>(counts, idx, Di, Ni);
+        const ff d = ff_from_i64(Di), N = ff_from_i64(Ni);
         acc = ff_add(acc, ff_sub(ff_mul(d, t.h), ff_mul(N, t.log2ch)));
     }
     ll[0] = acc.hi + acc.lo;
 }
 
+template <bool PAIRED>
 __global__ void k_loglik_bwd(const int64_t* __restrict__ counts, const float* __restrict__ Jq,
                              const float* __restrict__ g_out, float* __restrict__ grad) {
     if (blockIdx.x != 0 || threadIdx.x != 0)
         return;
     const float J = Jq[0], q = Jq[1];
     ff gJ = {0.0f, 0.0f}, gq = {0.0f, 0.0f};
-    for (int idx = 0; idx < 6; ++idx) {
+    for (int idx = 0; idx < (PAIRED ? 3 : 6); ++idx) {
         const ClassTerms t = class_terms(idx, J, q);
-        const int64_t np = counts[2 * idx + 1], nm = counts[2 * idx];
-        const ff resid = ff_sub(ff_from_i64(np - nm), ff_mul(ff_from_i64(np + nm), t.tanh_h));
+        int64_t Di, Ni;
+        class_sums<PAIRED>(counts, idx, Di, Ni);
+        const ff resid = ff_sub(ff_from_i64(Di), ff_mul(ff_from_i64(Ni), t.tanh_h));
         gJ = ff_add(gJ, ff_mul_f(resid, t.a));
         gq = ff_add(gq, ff_mul_f(resid, t.c));
     }
@@ -376,15 +461,16 @@ __global__ void k_loglik_bwd(const int64_t* __restrict__ counts, const float* __
 
 }  // namespace
 
-hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_lat, uint32_t L, int64_t* counts12,
-                                hipStream_t st, int64_t* partials, size_t partials_words) {
-    hipError_t e = launch_fill_i64(counts12, 12, 0, st);
+hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_lat, uint32_t L, int64_t* out,
+                                bool paired, hipStream_t st, int64_t* partials, size_t partials_words) {
+    const uint32_t n_out = paired ? 6u : 12u;
+    hipError_t e = launch_fill_i64(out, n_out, 0, st);
     if (e != hipSuccess)
         return e;
     const uint32_t n_words = L * (L / 64u);
     if (n_traj == 0 || n_lat < 2)
         return hipSuccess;
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(counts12);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(out);
     const uint32_t chunks = (n_lat - 1 + kChunk - 1) / kChunk;
     if (n_words <= kStageWords && chunks > 65535u)
         return hipErrorInvalidValue;
@@ -395,30 +481,54 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
         blocks = (uint64_t)((n_words + 255u) / 256u) * n_traj;
     if (blocks > 0x7FFFFFFFull)
         return hipErrorInvalidValue;
-    int64_t* part = (partials && 12u * blocks <= partials_words) ? partials : nullptr;
+    int64_t* part = (partials && n_out * blocks <= partials_words) ? partials : nullptr;
     const uint64_t* X = static_cast<const uint64_t*>(traj);
-    if (n_words <= 1024u)
-        hipLaunchKernelGGL((k_loglik_counts_lds<4, 8>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat, L,
-                           make_fastdiv(L / 64u), out, part);
-    else if (n_words <= kStageWords)
-        hipLaunchKernelGGL((k_loglik_counts_lds<16, 2>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat, L,
-                           make_fastdiv(L / 64u), out, part);
+    const FastDiv divW = make_fastdiv(L / 64u);
+    if (n_words <= 1024u) {
+        if (paired)
+            hipLaunchKernelGGL((k_loglik_counts_lds<4, 8, true>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
+                               L, divW, acc, part);
+        else
+            hipLaunchKernelGGL((k_loglik_counts_lds<4, 8, false>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
+                               L, divW, acc, part);
+    } else if (n_words <= kStageWords) {
+        if (paired)
+            hipLaunchKernelGGL((k_loglik_counts_lds<16, 2, true>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
+                               L, divW, acc, part);
+        else
+            hipLaunchKernelGGL((k_loglik_counts_lds<16, 2, false>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
+                               L, divW, acc, part);
+    } else {
+        if (paired)
+            hipLaunchKernelGGL(k_loglik_counts<true>, dim3((uint32_t)blocks), dim3(256), 0, st, X, n_traj, n_lat, L,
+                               divW, acc, part);
+        else
+            hipLaunchKernelGGL(k_loglik_counts<false>, dim3((uint32_t)blocks), dim3(256), 0, st, X, n_traj, n_lat, L,
+                               divW, acc, part);
+    }
+    if (part) {
+        if (paired)
+            hipLaunchKernelGGL(k_counts_finish<6>, dim3(1), dim3(1024), 0, st, part, (uint32_t)blocks, out);
+        else
+            hipLaunchKernelGGL(k_counts_finish<12>, dim3(1), dim3(1024), 0, st, part, (uint32_t)blocks, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik_fwd(const int64_t* stats, bool paired, const float* Jq, float* ll, hipStream_t st) {
+    if (paired)
+        hipLaunchKernelGGL(k_loglik_fwd<true>, dim3(1), dim3(64), 0, st, stats, Jq, ll);
     else
-        hipLaunchKernelGGL(k_loglik_counts, dim3((uint32_t)blocks), dim3(256), 0, st, X, n_traj, n_lat, L,
-                           make_fastdiv(L / 64u), out, part);
-    if (part)
-        hipLaunchKernelGGL(k_counts_finish, dim3(1), dim3(1024), 0, st, part, (uint32_t)blocks, counts12);
+        hipLaunchKernelGGL(k_loglik_fwd<false>, dim3(1), dim3(64), 0, st, stats, Jq, ll);
     return hipGetLastError();
 }
 
-hipError_t launch_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, hipStream_t st) {
-    hipLaunchKernelGGL(k_loglik_fwd, dim3(1), dim3(64), 0, st, counts12, Jq, ll);
-    return hipGetLastError();
-}
-
-hipError_t launch_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
+hipError_t launch_loglik_bwd(const int64_t* stats, bool paired, const float* Jq, const float* g_out, float* grad,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_loglik_bwd, dim3(1), dim3(64), 0, st, counts12, Jq, g_out, grad);
+    if (paired)
+        hipLaunchKernelGGL(k_loglik_bwd<true>, dim3(1), dim3(64), 0, st, stats, Jq, g_out, grad);
+    else
+        hipLaunchKernelGGL(k_loglik_bwd<false>, dim3(1), dim3(64), 0, st, stats, Jq, g_out, grad);
     return hipGetLastError();
 }
 

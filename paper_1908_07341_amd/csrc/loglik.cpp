@@ -92,33 +92,70 @@ sd_status sd_trajectories(const void* sigma0, void* traj, int32_t n_traj, int32_
     return SD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+sd_status loglik_sums(const char* name, const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* out,
+                      bool paired, void* hip_stream) {
+    if (!traj || !out)
+        return fail(SD_EINVAL, "%s: null pointer", name);
+    if (n_traj < 0 || n_lat < 1 || L < 64 || L > 65535 || L % 64 != 0)
+        return fail(SD_EINVAL, "%s: need n_traj >= 0, n_lat >= 1 and L a multiple of 64", name);
+    if (reinterpret_cast<uintptr_t>(traj) & 7u)
+        return fail(SD_EINVAL, "%s: trajectories must be 8-byte aligned", name);
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, out, paired, st,
+                                        partials_workspace(st), kPartialsWords);
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
+}
+
+sd_status loglik_fwd(const char* name, const int64_t* stats, bool paired, const float* Jq, float* ll,
+                     void* hip_stream) {
+    if (!stats || !Jq || !ll)
+        return fail(SD_EINVAL, "%s: null pointer", name);
+    hipError_t e = launch_loglik_fwd(stats, paired, Jq, ll, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
+}
+
+sd_status loglik_bwd(const char* name, const int64_t* stats, bool paired, const float* Jq, const float* g_out,
+                     float* grad, void* hip_stream) {
+    if (!stats || !Jq || !grad)
+        return fail(SD_EINVAL, "%s: null pointer", name);
+    hipError_t e = launch_loglik_bwd(stats, paired, Jq, g_out, grad, static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
+}
+
+}  // namespace
+
+extern "C" {
+
 sd_status sd_loglik_counts(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* counts12,
                            void* hip_stream) {
-    if (!traj || !counts12)
-        return fail(SD_EINVAL, "sd_loglik_counts: null pointer");
-    if (n_traj < 0 || n_lat < 1 || L < 64 || L > 65535 || L % 64 != 0)
-        return fail(SD_EINVAL, "sd_loglik_counts: need n_traj >= 0, n_lat >= 1 and L a multiple of 64");
-    if (reinterpret_cast<uintptr_t>(traj) & 7u)
-        return fail(SD_EINVAL, "sd_loglik_counts: trajectories must be 8-byte aligned");
-    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, counts12, st,
-                                        partials_workspace(st), kPartialsWords);
-    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_counts");
+    return loglik_sums("sd_loglik_counts", traj, n_traj, n_lat, L, counts12, false, hip_stream);
 }
 
 sd_status sd_loglik_fwd(const int64_t* counts12, const float* Jq, float* ll, void* hip_stream) {
-    if (!counts12 || !Jq || !ll)
-        return fail(SD_EINVAL, "sd_loglik_fwd: null pointer");
-    hipError_t e = launch_loglik_fwd(counts12, Jq, ll, static_cast<hipStream_t>(hip_stream));
-    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_fwd");
+    return loglik_fwd("sd_loglik_fwd", counts12, false, Jq, ll, hip_stream);
 }
 
 sd_status sd_loglik_bwd(const int64_t* counts12, const float* Jq, const float* g_out, float* grad,
                         void* hip_stream) {
-    if (!counts12 || !Jq || !grad)
-        return fail(SD_EINVAL, "sd_loglik_bwd: null pointer");
-    hipError_t e = launch_loglik_bwd(counts12, Jq, g_out, grad, static_cast<hipStream_t>(hip_stream));
-    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_loglik_bwd");
+    return loglik_bwd("sd_loglik_bwd", counts12, false, Jq, g_out, grad, hip_stream);
+}
+
+sd_status sd_loglik_stats(const void* traj, int32_t n_traj, int32_t n_lat, int32_t L, int64_t* stats6,
+                          void* hip_stream) {
+    return loglik_sums("sd_loglik_stats", traj, n_traj, n_lat, L, stats6, true, hip_stream);
+}
+
+sd_status sd_loglik_fwd_stats(const int64_t* stats6, const float* Jq, float* ll, void* hip_stream) {
+    return loglik_fwd("sd_loglik_fwd_stats", stats6, true, Jq, ll, hip_stream);
+}
+
+sd_status sd_loglik_bwd_stats(const int64_t* stats6, const float* Jq, const float* g_out, float* grad,
+                              void* hip_stream) {
+    return loglik_bwd("sd_loglik_bwd_stats", stats6, true, Jq, g_out, grad, hip_stream);
 }
 
 }  // extern "C"

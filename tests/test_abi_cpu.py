@@ -95,6 +95,13 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_corr_diag(fake, 64, sd.SD_I8, 3, None, st) == sd.SD_EINVAL
     assert lib.sd_trajectories(fake, fake2, -1, 64, sd.SD_P64, 0.4, 0.6, 1, 0, 0, 2, st) == sd.SD_EINVAL
     assert lib.sd_trajectories(fake, fake2, 2, 64, sd.SD_I8, 0.4, 0.6, 1, 0, 0, 2, st) == sd.SD_EUNSUPPORTED
+    assert lib.sd_loglik_stats(fake, 1, 3, 96, fake2, st) == sd.SD_EINVAL
+    assert b"sd_loglik_stats" in lib.sd_last_error()
+    assert lib.sd_loglik_stats(ctypes.c_void_p(0x10004), 1, 3, 64, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_loglik_stats(fake, 1, 0, 64, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_loglik_stats(fake, 1, 3, 64, None, st) == sd.SD_EINVAL
+    assert lib.sd_loglik_fwd_stats(None, fake, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_loglik_bwd_stats(fake, fake, None, None, st) == sd.SD_EINVAL
     out = (ctypes.c_uint32 * 6)()
     assert lib.sd_threshold_table(float("inf"), 0.1, out) == sd.SD_EINVAL
     assert lib.sd_threshold_table(0.1, 0.1, None) == sd.SD_EINVAL

@@ -51,8 +51,12 @@ def test_trajectory_and_counts_match_oracle(oracle, L, n_traj, k):
         ref.append(X)
     counts = AG.loglik_counts(traj, n_traj, 2 * k + 1, L)
     assert np.array_equal(counts.cpu().numpy(), oracle.loglik_counts(np.stack(ref)))
+    stats = AG.loglik_stats(traj, n_traj, 2 * k + 1, L)
+    assert np.array_equal(stats.cpu().numpy(), oracle.loglik_stats(np.stack(ref)))
     # a single lattice has no transitions
     one = AG.loglik_counts(traj[:1, :1].contiguous(), 1, 1, L)
+    assert not one.any()
+    one = AG.loglik_stats(traj[:1, :1].contiguous(), 1, 1, L)
     assert not one.any()
 
 
@@ -101,11 +105,20 @@ def c5_small():
     L, J, q, n_traj, k = 128, 0.45, 0.7, 16, 300
     traj = _traj_gpu(L, J, q, n_traj, k, stream0=100)
     counts = AG.loglik_counts(traj, n_traj, 2 * k + 1, L)
+    stats = AG.loglik_stats(traj, n_traj, 2 * k + 1, L)
     del traj
-    return counts
+    return counts, stats
+
+
+def test_paired_stats_are_the_pair_map_of_the_counts(c5_small):
+    c, s = (t.cpu().numpy() for t in c5_small)
+    S = [c[2 * j] + c[2 * j + 1] + c[2 * (5 - j)] + c[2 * (5 - j) + 1] for j in range(3)]
+    Z = [c[2 * j + 1] + c[2 * (5 - j)] for j in range(3)]
+    assert np.array_equal(s, np.array(S + Z))
 
 
 def test_forward_and_backward_against_fp64(oracle, c5_small):
+    c5_small, _ = c5_small
     ch = c5_small.cpu().numpy()
     N = int(ch.sum())
     for J, q in [(0.2, 0.2), (0.45, 0.7), (1.0, 1.5), (0.0, 0.0), (0.6, 0.3)]:
@@ -130,7 +143,33 @@ def test_forward_and_backward_against_fp64(oracle, c5_small):
             assert abs(got_g[i] - fd[i]) <= 1e-5 * abs(fd[i]) + 1e-7 * scale, (i, got_g[i], fd[i])
 
 
+def test_paired_forward_and_backward_against_fp64(oracle, c5_small):
+    _, st = c5_small
+    sh = st.cpu().numpy()
+    scale = 2.0 * float(sh[:3].sum())
+    for J, q in [(0.2, 0.2), (0.45, 0.7), (1.0, 1.5), (0.0, 0.0), (0.6, -0.3)]:
+        J32, q32 = float(np.float32(J)), float(np.float32(q))
+        Jq = torch.tensor([J32, q32], dtype=torch.float32, device="cuda")
+        ll = torch.empty(1, dtype=torch.float32, device="cuda")
+        grad = torch.empty(2, dtype=torch.float32, device="cuda")
+        g_out = torch.tensor([-2.0], dtype=torch.float32, device="cuda")
+        sd.sd_loglik_fwd_stats(st, Jq, ll)
+        sd.sd_loglik_bwd_stats(st, Jq, g_out, grad)
+        ll64, g64 = oracle.loglik_from_stats(sh, J32, q32)
+        got_ll = float(ll.cpu()[0])
+        got_g = grad.cpu().numpy().astype(np.float64) / -2.0
+        print(f"paired J={J} q={q} ll={got_ll} ll64={ll64} g={got_g} g64={g64}", flush=True)
+        assert abs(got_ll - ll64) <= 1e-6 * abs(ll64)
+        for i in range(2):
+            assert abs(got_g[i] - g64[i]) <= 1e-5 * abs(g64[i]) + 1e-9 * scale, (i, got_g[i], g64[i])
+
+
 def test_autograd_function(oracle, c5_small):
+    c5_small, st = c5_small
+    Jq2 = torch.tensor([0.3, 0.5], dtype=torch.float32, device="cuda", requires_grad=True)
+    (g2,) = torch.autograd.grad(3.0 * AG.loglik(Jq2, st), Jq2)
+    _, g64s = oracle.loglik_from_stats(st.cpu().numpy(), float(np.float32(0.3)), float(np.float32(0.5)))
+    assert np.allclose(g2.cpu().numpy(), 3.0 * g64s, rtol=1e-5)
     Jq = torch.tensor([0.3, 0.5], dtype=torch.float32, device="cuda", requires_grad=True)
     ll = AG.loglik(Jq, c5_small)
     (g,) = torch.autograd.grad(3.0 * ll, Jq)
@@ -140,6 +179,7 @@ def test_autograd_function(oracle, c5_small):
 
 
 def test_gradient_ascent_recovers_parameters(oracle, c5_small):
+    c5_small, _ = c5_small
     ch = c5_small.cpu().numpy()
     N = float(ch.sum())
     # plain gradient ascent on LL / N (a concave objective with curvature of
