@@ -50,9 +50,9 @@ __device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64
 // thread adds at most 64 per word and transition, so 2^26 word-transitions
 // per thread stay exact.
 __device__ __forceinline__ void count_transition32(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, uint32_t (&tot)[6],
-                                                   uint32_t (&plus)[6]) {
-    const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2);
-    const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c, k1 & c, k2 & ~c, k2 & c};
+                                                   uint32_t (&plus)[6], uint64_t live = ~0ull) {
+    const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2) & live;
+    const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c & live, k1 & c & live, k2 & ~c & live, k2 & c & live};
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         const uint64_t a = cls[i], b = cls[i] & y;
@@ -64,12 +64,14 @@ __device__ __forceinline__ void count_transition32(uint64_t c, uint64_t n1, uint
 // The paired statistics of one word-transition: acc gets popc(Q0), popc(Q2),
 // and popc(mask_j & z) for j = 0, 1, 2, with Q0 = sites whose neighbours both
 // equal the spin, Q2 = sites whose neighbours differ, W1 = the rest and
-// z = y ^ majority(n1, n2, c).  S_1 follows from the number of sites.
+// z = y ^ majority(n1, n2, c).  S_1 follows from the number of sites.  Only
+// the sites of `live` count.
 template <typename T>
-__device__ __forceinline__ void pair_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, T (&acc)[5]) {
-    const uint64_t q2 = n1 ^ n2;
-    const uint64_t q0 = ~((n1 ^ c) | q2);
-    const uint64_t w1 = ~(q0 | q2);
+__device__ __forceinline__ void pair_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, T (&acc)[5],
+                                                uint64_t live = ~0ull) {
+    const uint64_t q2 = (n1 ^ n2) & live;
+    const uint64_t q0 = ~((n1 ^ c) | (n1 ^ n2)) & live;
+    const uint64_t w1 = ~(q0 | q2) & live;
     const uint64_t z = y ^ ((q2 & c) | (~q2 & n1));
     const uint64_t v[5] = {q0, q2, q0 & z, w1 & z, q2 & z};
 #pragma unroll
@@ -131,20 +133,27 @@ __global__ __launch_bounds__(1024) void k_counts_finish(const int64_t* __restric
 
 // Lattices of at most kStageWords words: one workgroup walks a chunk of
 // kChunk consecutive transitions of one trajectory.  Every lattice is read
-// from HBM exactly once (coalesced, each thread owning the words tid,
-// tid + 256, ...), DEPTH lattices ahead of use; the source lattice of each
+// from HBM exactly once (coalesced, each of the THREADS threads owning the
+// words tid, tid + THREADS, ...), DEPTH lattices ahead of use; the source lattice of each
 // transition is staged in LDS (double-buffered) so that the neighbour words
-// come from LDS.  One barrier per transition.
+// come from LDS.  One barrier per transition.  The loads are unconditional
+// (lanes without a word read word 0, lattices past the chunk are clamped to
+// its last one) so that the code between barriers has no divergent branch
+// and each load is waited for only when its lattice is used; FULL = every
+// lane owns WPT words.  Chunks start at even transitions and DEPTH is even,
+// so the parity of a transition (half-step A or B) is that of its slot in
+// the unrolled ring.
 constexpr uint32_t kStageWords = 4096;   // L <= 512
 constexpr uint32_t kChunk = 256;
 
-template <uint32_t WPT, uint32_t DEPTH, bool PAIRED>
-__global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __restrict__ traj, uint32_t n_lat,
+template <uint32_t THREADS, uint32_t WPT, uint32_t DEPTH, bool PAIRED, bool FULL>
+__global__ __launch_bounds__(THREADS) void k_loglik_counts_lds(const uint64_t* __restrict__ traj, uint32_t n_lat,
                                                             uint32_t L, FastDiv divW,
                                                             unsigned long long* __restrict__ counts,
                                                             int64_t* __restrict__ partials) {
-    __shared__ uint64_t buf[2][256 * WPT];
-    __shared__ int64_t red[12 * 4];
+    static_assert(DEPTH % 2 == 0 && kChunk % DEPTH == 0, "transition parity must follow the ring slot");
+    __shared__ uint64_t buf[2][THREADS * WPT];
+    __shared__ int64_t red[12 * (THREADS / 64)];
     const uint32_t W = L / 64u;
     const uint32_t n_words = L * W;
     const uint32_t a = blockIdx.x;
@@ -160,66 +169,78 @@ __global__ __launch_bounds__(256) void k_loglik_counts_lds(const uint64_t* __res
     for (int i = 0; i < 5; ++i)
         pst[i] = 0;
     uint32_t n_mine = 0;
-    bool mine[WPT];
-    uint32_t jj[WPT], ww[WPT];
+    uint32_t gi[WPT], i_down[WPT], i_up[WPT], i_prev[WPT], i_next[WPT];
+    uint64_t live[WPT];
 #pragma unroll
     for (uint32_t k = 0; k < WPT; ++k) {
-        const uint32_t g = threadIdx.x + 256u * k;
-        mine[k] = g < n_words;
-        n_mine += mine[k] ? 1u : 0u;
-        jj[k] = fdiv(g, divW);
-        ww[k] = g - jj[k] * W;
+        const uint32_t g = threadIdx.x + THREADS * k;
+        const bool mine = FULL || g < n_words;
+        n_mine += mine ? 1u : 0u;
+        live[k] = mine ? ~0ull : 0ull;
+        const uint32_t gg = mine ? g : 0u;
+        const uint32_t j = fdiv(gg, divW);
+        const uint32_t w = gg - j * W;
+        gi[k] = gg;
+        i_down[k] = (j == 0 ? L - 1 : j - 1) * W + w;
+        i_up[k] = (j == L - 1 ? 0 : j + 1) * W + w;
+        i_prev[k] = j * W + (w == 0 ? W - 1 : w - 1);
+        i_next[k] = j * W + (w == W - 1 ? 0 : w + 1);
     }
     // ring[d] holds lattice m + 1 + d while transition m is processed
     uint64_t cur[WPT], ring[DEPTH][WPT];
-#pragma unroll
-    for (uint32_t k = 0; k < WPT; ++k)
-        cur[k] = mine[k] ? X[(size_t)m0 * n_words + threadIdx.x + 256u * k] : 0;
-#pragma unroll
-    for (uint32_t d = 0; d < DEPTH; ++d)
+    {
+        const uint64_t* X0 = X + (size_t)m0 * n_words;
 #pragma unroll
         for (uint32_t k = 0; k < WPT; ++k)
-            ring[d][k] = (mine[k] && m0 + 1 + d <= m1)
-                             ? X[(size_t)(m0 + 1 + d) * n_words + threadIdx.x + 256u * k] : 0;
-    for (uint32_t mb = m0; mb < m1; mb += DEPTH) {
-#pragma unroll
-        for (uint32_t d = 0; d < DEPTH; ++d) {
-            const uint32_t m = mb + d;
-            if (m < m1) {
-                uint64_t* S = buf[m & 1u];
-#pragma unroll
-                for (uint32_t k = 0; k < WPT; ++k)
-                    if (mine[k])
-                        S[threadIdx.x + 256u * k] = cur[k];
-                __syncthreads();
-                const bool even = (m & 1u) == 0;
-#pragma unroll
-                for (uint32_t k = 0; k < WPT; ++k) {
-                    if (mine[k]) {
-                        const uint32_t j = jj[k], w = ww[k];
-                        const uint64_t c = cur[k];
-                        uint64_t n1, n2;
-                        if (even) {
-                            n1 = S[(j == 0 ? L - 1 : j - 1) * W + w];
-                            n2 = (c << 1) | (S[j * W + (w == 0 ? W - 1 : w - 1)] >> 63);
-                        } else {
-                            n1 = S[(j == L - 1 ? 0 : j + 1) * W + w];
-                            n2 = (c >> 1) | (S[j * W + (w == W - 1 ? 0 : w + 1)] << 63);
-                        }
-                        if (PAIRED)
-                            pair_transition(c, n1, n2, ring[d][k], pst);
-                        else
-                            count_transition32(c, n1, n2, ring[d][k], tot, plus);
-                        cur[k] = ring[d][k];
-                        // refill the slot with lattice m + 1 + DEPTH (the chunk
-                        // needs lattices up to m1)
-                        const uint32_t mf = m + 1 + DEPTH;
-                        ring[d][k] = mf <= m1 ? X[(size_t)mf * n_words + threadIdx.x + 256u * k] : 0;
-                    }
-                }
-            }
-        }
+            cur[k] = X0[gi[k]];
     }
+#pragma unroll
+    for (uint32_t d = 0; d < DEPTH; ++d) {
+        const uint32_t mf = m0 + 1 + d <= m1 ? m0 + 1 + d : m1;
+        const uint64_t* Xf = X + (size_t)mf * n_words;
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k)
+            ring[d][k] = Xf[gi[k]];
+    }
+    auto transition = [&](uint32_t m, uint32_t d) __attribute__((always_inline)) {
+        uint64_t* S = buf[d & 1u];
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k)
+            S[threadIdx.x + THREADS * k] = cur[k];
+        __syncthreads();
+        const uint32_t mf = m + 1 + DEPTH <= m1 ? m + 1 + DEPTH : m1;
+        const uint64_t* Xf = X + (size_t)mf * n_words;
+        // all neighbour words first: the LDS reads overlap instead of each
+        // waiting for the previous one
+        uint64_t nv[WPT], nh[WPT];
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k) {
+            nv[k] = S[(d & 1u) == 0 ? i_down[k] : i_up[k]];
+            nh[k] = S[(d & 1u) == 0 ? i_prev[k] : i_next[k]];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k) {
+            const uint64_t c = cur[k];
+            const uint64_t n1 = nv[k];
+            const uint64_t n2 = (d & 1u) == 0 ? ((c << 1) | (nh[k] >> 63)) : ((c >> 1) | (nh[k] << 63));
+            if (PAIRED)
+                pair_transition(c, n1, n2, ring[d][k], pst, FULL ? ~0ull : live[k]);
+            else
+                count_transition32(c, n1, n2, ring[d][k], tot, plus, FULL ? ~0ull : live[k]);
+            cur[k] = ring[d][k];
+            ring[d][k] = Xf[gi[k]];
+        }
+    };
+    uint32_t mb = m0;
+    for (; mb + DEPTH <= m1; mb += DEPTH) {
+#pragma unroll
+        for (uint32_t d = 0; d < DEPTH; ++d)
+            transition(mb + d, d);
+    }
+#pragma unroll
+    for (uint32_t d = 0; d < DEPTH; ++d)
+        if (mb + d < m1)
+            transition(mb + d, d);
     if (PAIRED) {
         int64_t acc[6];
         pair_stats(pst, (int64_t)n_mine * (m1 - m0), acc);
@@ -484,20 +505,33 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     int64_t* part = (partials && n_out * blocks <= partials_words) ? partials : nullptr;
     const uint64_t* X = static_cast<const uint64_t*>(traj);
     const FastDiv divW = make_fastdiv(L / 64u);
-    if (n_words <= 1024u) {
-        if (paired)
-            hipLaunchKernelGGL((k_loglik_counts_lds<4, 8, true>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
-                               L, divW, acc, part);
-        else
-            hipLaunchKernelGGL((k_loglik_counts_lds<4, 8, false>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
-                               L, divW, acc, part);
+    const dim3 grid(n_traj, chunks);
+#define SD_LL_LDS(THREADS, WPT, DEPTH)                                                                                 \
+    do {                                                                                                               \
+        const bool full = n_words == (THREADS) * (WPT);                                                                \
+        if (paired && full)                                                                                            \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, true, true>), grid, dim3(THREADS), 0, st, X,  \
+                               n_lat, L, divW, acc, part);                                                             \
+        else if (paired)                                                                                               \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, true, false>), grid, dim3(THREADS), 0, st, X, \
+                               n_lat, L, divW, acc, part);                                                             \
+        else if (full)                                                                                                 \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, false, true>), grid, dim3(THREADS), 0, st, X, \
+                               n_lat, L, divW, acc, part);                                                             \
+        else                                                                                                           \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, false, false>), grid, dim3(THREADS), 0, st,   \
+                               X, n_lat, L, divW, acc, part);                                                          \
+    } while (0)
+    // a lattice of n_words words is spread over THREADS x WPT slots
+    if (n_words <= 64u) {
+        SD_LL_LDS(64, 1, 16);
+    } else if (n_words <= 256u) {
+        SD_LL_LDS(256, 1, 16);
+    } else if (n_words <= 1024u) {
+        SD_LL_LDS(256, 4, 4);
     } else if (n_words <= kStageWords) {
-        if (paired)
-            hipLaunchKernelGGL((k_loglik_counts_lds<16, 2, true>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
-                               L, divW, acc, part);
-        else
-            hipLaunchKernelGGL((k_loglik_counts_lds<16, 2, false>), dim3(n_traj, chunks), dim3(256), 0, st, X, n_lat,
-                               L, divW, acc, part);
+        SD_LL_LDS(1024, 4, 4);
+#undef SD_LL_LDS
     } else {
         if (paired)
             hipLaunchKernelGGL(k_loglik_counts<true>, dim3((uint32_t)blocks), dim3(256), 0, st, X, n_traj, n_lat, L,
