@@ -76,6 +76,9 @@ def lib():
         L.or_run.restype = c.c_int
         L.or_loglik_counts.argtypes = [i8p, c.c_int, c.c_int, c.c_int, i64p]
         L.or_loglik_counts.restype = c.c_int
+        L.or_propp_wilson.argtypes = [i8p, c.c_int, c.c_double, c.c_double, c.c_uint64, c.c_uint32, c.c_uint64,
+                                      c.c_uint32, c.c_uint32]
+        L.or_propp_wilson.restype = c.c_int64
         L.or_loglik_stats.argtypes = [i8p, c.c_int, c.c_int, c.c_int, i64p]
         L.or_loglik_stats.restype = c.c_int
         L.or_loglik_from_stats.argtypes = [i64p, c.c_double, c.c_double, ctypes.POINTER(c.c_double)]
@@ -221,6 +224,15 @@ def trajectory(sigma0: np.ndarray, J: float, q: float, seed: int, stream: int, s
         X.append(half_step(X[-1], J, q, 0, seed, stream, 2 * n))
         X.append(half_step(X[-1], J, q, 1, seed, stream, 2 * n + 1))
     return np.stack(X)
+
+
+def propp_wilson(L: int, J: float, q: float, seed: int, stream: int, step_end: int, T0: int, T_max: int):
+    """Coupling from the past: (sample [L, L] int8, T that coalesced or 0)."""
+    out = np.zeros((L, L), dtype=np.int8)
+    T = int(lib().or_propp_wilson(_p(out, ctypes.c_int8), L, float(J), float(q), seed, stream, step_end, T0, T_max))
+    if T < 0:
+        raise ValueError("oracle Propp-Wilson rejected its arguments")
+    return out, T
 
 
 def loglik_counts(traj: np.ndarray) -> np.ndarray:

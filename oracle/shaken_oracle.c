@@ -372,6 +372,52 @@ OR_EXPORT int or_run(int8_t* sigma, int8_t* tau, int L, double J, double q, uint
 }
 
 /* ------------------------------------------------------------------------- */
+/* Coupling from the past (Propp and Wilson), the exact sampler that section   */
+/* 3.2 builds on the coupling.  For J, q >= 0 one full step is monotone: with   */
+/* the same uniforms, sigma <= sigma' site by site stays so after the step.     */
+/* The uniforms of time -t (t = 1, 2, ...) are those of step index             */
+/* step_end - t.  T runs through T0, 2 T0, 4 T0, ... while T <= T_max; the      */
+/* chains started from all +1 and all -1 at time -T are run to time 0, and at   */
+/* the first T where they agree their common lattice is the sample (every      */
+/* chain started at -T lies between them).  Returns that T; 0 if no T up to    */
+/* T_max coalesced (sample: the top chain at time 0 from the largest T tried); */
+/* -1 on bad arguments.                                                         */
+/* ------------------------------------------------------------------------- */
+OR_EXPORT int64_t or_propp_wilson(int8_t* sample, int L, double J, double q, uint64_t seed, uint32_t stream,
+                                  uint64_t step_end, uint32_t T0, uint32_t T_max)
+{
+    if (L < 2 || T0 < 1 || T_max < T0 || !(J >= 0.0) || !(q >= 0.0) || step_end < T_max ||
+        step_end > (1ull << 29))
+        return -1;
+    size_t N = (size_t)L * (size_t)L;
+    int8_t* top = (int8_t*)malloc(N);
+    int8_t* bot = (int8_t*)malloc(N);
+    int8_t* tau = (int8_t*)malloc(N);
+    if (!top || !bot || !tau) {
+        free(top);
+        free(bot);
+        free(tau);
+        return -1;
+    }
+    int64_t found = 0;
+    for (uint64_t T = T0; T <= T_max; T *= 2) {
+        or_init(top, L, OR_INIT_UP, 0.5, seed, stream);
+        or_init(bot, L, OR_INIT_DOWN, 0.5, seed, stream);
+        or_run(top, tau, L, J, q, seed, stream, step_end - T, (uint32_t)T, NULL, 0);
+        or_run(bot, tau, L, J, q, seed, stream, step_end - T, (uint32_t)T, NULL, 0);
+        memcpy(sample, top, N);
+        if (memcmp(top, bot, N) == 0) {
+            found = (int64_t)T;
+            break;
+        }
+    }
+    free(top);
+    free(bot);
+    free(tau);
+    return found;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Trajectory log-likelihood.  A trajectory is X_0 = sigma_0, X_1 = tau_1,      */
 /* X_2 = sigma_1, ...; the transition X_m -> X_(m+1) is a half-step A draw for  */
 /* even m and a half-step B draw for odd m.  By the product form of eqs.        */
