@@ -261,6 +261,34 @@ SD_API sd_status sd_loglik_fwd_stats(const int64_t* stats6, const float* Jq, flo
 SD_API sd_status sd_loglik_bwd_stats(const int64_t* stats6, const float* Jq, const float* g_out, float* grad,
                                      void* hip_stream);
 
+/*
+ * Exact samples from the stationary law of the shaken dynamics by coupling
+ * from the past (Propp-Wilson), the sampler that section 3.2 builds on the
+ * coupling of two copies driven by the same randomness.  For J, q >= 0 a full
+ * step is monotone (sigma <= sigma' site by site stays so under shared
+ * uniforms), so the chains from all +1 and all -1 bound every other chain.
+ * Sample p (0 <= p < n_samples) uses stream stream0 + p; time -t (t >= 1)
+ * draws the uniforms of step index step_end - t.  T runs through T0, 2 T0,
+ * 4 T0, ... while T <= T_max; the two chains are started at time -T and run
+ * to time 0, and the sample is their common lattice at the first T at which
+ * they agree.
+ *   samples: device, n_samples lattices of sd_lattice_bytes(L, SD_P64) bytes
+ *            (SD_P64 layout), written.
+ *   work:    device scratch of 4 * n_samples * sd_lattice_bytes(L, SD_P64)
+ *            bytes, owned by the caller, contents overwritten; must not
+ *            overlap samples.
+ *   T_used:  host, n_samples int64: the T that coalesced, or 0 if none up to
+ *            T_max (that sample is then the top chain's lattice at time 0 from
+ *            the largest T tried).
+ * Needs finite J, q >= 0, L a multiple of 8 whose lattice pair fits one
+ * workgroup's LDS, 1 <= T0 <= T_max <= step_end <= 2^29, 8-byte aligned
+ * buffers.  Synchronises hip_stream once per T (to read the pairs' flags) and
+ * allocates a few bytes of device scratch per sample for the call.
+ */
+SD_API sd_status sd_propp_wilson(void* samples, void* work, int32_t n_samples, int32_t L, double J, double q,
+                                 uint64_t seed, uint32_t stream0, uint64_t step_end, uint32_t T0, uint32_t T_max,
+                                 int64_t* T_used, void* hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Batched scan: many independent chains in one persistent launch.            */
 /* ------------------------------------------------------------------------- */

@@ -56,6 +56,7 @@ SIGNATURES = {
     "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "sd_loglik_stats": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_propp_wilson": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _U32, _VP, _VP]),
     "sd_loglik_fwd_stats": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd_stats": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "sd_tune": (_I32, [_I32, _I32, ctypes.c_char_p, _VP]),
@@ -191,6 +192,15 @@ def sd_loglik_fwd_stats(stats6, Jq, ll, hip_stream=None) -> None:
 
 def sd_loglik_bwd_stats(stats6, Jq, g_out, grad, hip_stream=None) -> None:
     _check(lib().sd_loglik_bwd_stats(_ptr(stats6), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
+
+
+def sd_propp_wilson(samples, work, n_samples, L, J, q, seed, stream0, step_end, T0, T_max,
+                    hip_stream=None) -> list:
+    """Coupling-from-the-past samples into `samples`; returns T_used (n_samples ints)."""
+    T_used = (ctypes.c_int64 * max(n_samples, 1))()
+    _check(lib().sd_propp_wilson(_ptr(samples), _ptr(work), n_samples, L, J, q, seed, stream0, step_end, T0, T_max,
+                                 ctypes.cast(T_used, ctypes.c_void_p), _stream(hip_stream)))
+    return list(T_used[:n_samples])
 
 
 class sd_batch_plan:

@@ -48,19 +48,17 @@ struct sd_batch_plan {
 };
 
 namespace sd {
-namespace {
 
-constexpr size_t kAlign = 256;
-
-// 64-site words of an L x L lattice (L % 8 == 0).
 uint32_t lattice_words(uint32_t L) { return (uint32_t)(((uint64_t)L * L) / 64u); }
 
-// Division constants of a chain: by the words per row (rows of whole words
-// only; 1 otherwise) and by L.
 void set_divisors(ChainDesc& d, uint32_t L) {
     d.divW = make_fastdiv(L >= 64u ? L / 64u : 1u);
     d.divL = make_fastdiv(L);
 }
+
+namespace {
+
+constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

@@ -51,11 +51,26 @@ struct BatchArgs {
 // words per wavefront of a threads-sized workgroup.
 constexpr uint32_t kMomentWords = 5;
 
+// 64-site words of an L x L lattice (L % 8 == 0).
+uint32_t lattice_words(uint32_t L);
+// Division constants of a chain: by the words per row (rows of whole words
+// only; 1 otherwise) and by L.
+void set_divisors(ChainDesc& d, uint32_t L);
+
 size_t batch_lds_bytes(uint32_t max_words, uint32_t threads);
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds);
 hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, bool bits, int* blocks_per_cu);
+
+// Coupling from the past: pair p of `pairs` owns four lattices of `words`
+// words at work + 4 p words*8 bytes (top sigma, top tau, bottom sigma, bottom
+// tau).  reset: top sigma all +1, bottom sigma all -1.  finish: equal[i] =
+// (top sigma == bottom sigma) of pair pairs[i], and its top sigma is copied
+// to samples + pairs[i] * words * 8 bytes.
+hipError_t launch_pw_reset(uint8_t* work, const uint32_t* pairs, uint32_t n, uint32_t words, hipStream_t st);
+hipError_t launch_pw_finish(const uint8_t* work, const uint32_t* pairs, uint32_t n, uint32_t words, uint8_t* samples,
+                            uint32_t* equal, hipStream_t st);
 
 // Lattices with at most this many 64-site words run in one workgroup with
 // LDS-resident lattices when sd_run is called without SD_FLAG_GLOBAL_KERNELS.

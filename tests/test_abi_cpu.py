@@ -102,6 +102,17 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_loglik_stats(fake, 1, 3, 64, None, st) == sd.SD_EINVAL
     assert lib.sd_loglik_fwd_stats(None, fake, fake2, st) == sd.SD_EINVAL
     assert lib.sd_loglik_bwd_stats(fake, fake, None, None, st) == sd.SD_EINVAL
+    tu = (ctypes.c_int64 * 4)()
+    far = ctypes.c_void_p(0x100000)
+    assert lib.sd_propp_wilson(fake, far, 4, 12, 0.4, 0.5, 1, 0, 100, 1, 10, tu, st) == sd.SD_EINVAL
+    assert lib.sd_propp_wilson(fake, far, 4, 16, -0.4, 0.5, 1, 0, 100, 1, 10, tu, st) == sd.SD_EINVAL
+    assert b"monotone" in lib.sd_last_error()
+    assert lib.sd_propp_wilson(fake, far, 4, 16, 0.4, 0.5, 1, 0, 100, 1, 200, tu, st) == sd.SD_EINVAL
+    assert lib.sd_propp_wilson(fake, far, 4, 16, 0.4, 0.5, 1, 0, 2 ** 30, 1, 200, tu, st) == sd.SD_EINVAL
+    assert lib.sd_propp_wilson(fake, far, 4, 16, 0.4, 0.5, 1, 0, 100, 0, 10, tu, st) == sd.SD_EINVAL
+    assert lib.sd_propp_wilson(fake, ctypes.c_void_p(0x10010), 4, 16, 0.4, 0.5, 1, 0, 100, 1, 10, tu, st) == sd.SD_EINVAL
+    assert b"overlap" in lib.sd_last_error()
+    assert lib.sd_propp_wilson(fake, far, 4, 16, 0.4, 0.5, 1, 0, 100, 1, 10, None, st) == sd.SD_EINVAL
     out = (ctypes.c_uint32 * 6)()
     assert lib.sd_threshold_table(float("inf"), 0.1, out) == sd.SD_EINVAL
     assert lib.sd_threshold_table(0.1, 0.1, None) == sd.SD_EINVAL
