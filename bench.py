@@ -154,6 +154,8 @@ def parse():
     p.add_argument("--scan-rec", type=int, default=300000)
     p.add_argument("--coalescence", action="store_true",
                    help="only the coalescence times of section 3.2 (32x32, monotone coupling)")
+    p.add_argument("--propp-wilson", action="store_true",
+                   help="only the coupling-from-the-past samples (32x32, J near the square-lattice critical value)")
     p.add_argument("--table1", action="store_true",
                    help="only the diagonal-correlation comparison with Table 1 (32x32, all (q, J) rows)")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -472,6 +474,40 @@ def bench_coalescence(sd, torch, L=32, n_pairs=256):
                         f"cap 200000 steps", "rows": rows, "seconds": time.perf_counter() - t0}
 
 
+def bench_propp_wilson(sd, torch, L=32, n=512):
+    """Exact samples of the stationary law by coupling from the past (the
+    Propp-Wilson sampler on the monotone coupling of section 3.2), at the kind
+    of points where the paper compares pi_s with the square-lattice Gibbs
+    measure: J below the square-lattice critical value, q growing.  Per point:
+    wall time, coalescence times, and the sample means of m, |m| and the
+    square-lattice bond sum per site -(1/L^2) sum_x s_x (s_right + s_up)."""
+    from paper_1908_07341_amd import inputs
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    samples = torch.empty((n, nb), dtype=torch.uint8, device="cuda")
+    work = torch.empty(4 * n * nb, dtype=torch.uint8, device="cuda")
+    rows = []
+    t_all = time.perf_counter()
+    for idx, (q, J) in enumerate([(1.0, 0.30), (1.0, 0.38), (2.5, 0.30), (2.5, 0.38), (2.5, 0.42), (4.0, 0.38)]):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = np.array(sd.sd_propp_wilson(samples, work, n, L, J, q, 1, 10000 * idx, 1 << 28, 16, 1 << 24))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        host = samples.cpu().numpy()
+        lat = np.stack([inputs.unpack_bits(host[p], L) for p in range(n)]).astype(np.int64)
+        m = lat.mean(axis=(1, 2))
+        bonds = -(lat * (np.roll(lat, -1, axis=2) + np.roll(lat, -1, axis=1))).sum(axis=(1, 2)) / (L * L)
+        ok = T > 0
+        rows.append({"q": q, "J": J, "samples": n, "coalesced": int(ok.sum()), "seconds": dt,
+                     "samples_per_s": n / dt, "mean_T": float(T[ok].mean()) if ok.any() else None,
+                     "max_T": int(T.max()), "mean_m": float(m[ok].mean()), "mean_abs_m": float(np.abs(m[ok]).mean()),
+                     "sd_m": float(m[ok].std()), "mean_bond_sum_per_site": float(bonds[ok].mean()),
+                     "sd_bond_sum_per_site": float(bonds[ok].std())})
+        log(f"[bench] propp-wilson q={q} J={J}: {n} samples in {dt:.2f} s, mean T {rows[-1]['mean_T']}")
+    return {"workload": f"{L}x{L} torus, {n} samples per point, T from 16 doubling to at most 2^24, "
+                        f"time 0 at step index 2^28, seed 1", "rows": rows, "seconds": time.perf_counter() - t_all}
+
+
 def bench_table1(sd, torch, burn=2000, n_meas=4000, every=5, L=32):
     """Time-averaged diagonal correlations C(l) = D(l) / L^2 on a 32x32 torus at
     every (q, J) row of Table 1 (section 3.3), next to the printed values
@@ -552,6 +588,9 @@ def main():
         return
     if args.coalescence:
         print(json.dumps({"coalescence": bench_coalescence(sd, torch)}), flush=True)
+        return
+    if args.propp_wilson:
+        print(json.dumps({"propp_wilson": bench_propp_wilson(sd, torch)}), flush=True)
         return
     if args.critical_scan:
         out = bench_critical_scan(sd, torch, args.scan_grid, args.scan_L, args.scan_warm, args.scan_rec,
