@@ -45,50 +45,89 @@ __device__ __forceinline__ void count_transition(uint64_t c, uint64_t n1, uint64
     }
 }
 
-// The same counts in 32-bit accumulators: tot[i] = sites of class i,
-// plus[i] = those drawn +1 (each popcount folds into its accumulator).  A
-// thread adds at most 64 per word and transition, so 2^26 word-transitions
-// per thread stay exact.
-__device__ __forceinline__ void count_transition32(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, uint32_t (&tot)[6],
-                                                   uint32_t (&plus)[6], uint64_t live = ~0ull) {
-    const uint64_t k2 = n1 & n2, k1 = n1 ^ n2, k0 = ~(n1 | n2) & live;
-    const uint64_t cls[6] = {k0 & ~c, k0 & c, k1 & ~c & live, k1 & c & live, k2 & ~c & live, k2 & c & live};
+// Immediates of the three-input logic instruction (V_BITOP3): the function
+// applied bitwise to the operand patterns 0xF0, 0xCC, 0xAA.
+constexpr uint32_t kTA = 0xF0u, kTB = 0xCCu, kTC = 0xAAu;
+constexpr uint32_t tt(uint32_t f) { return f & 0xFFu; }
+constexpr uint32_t kAllEqual = tt(~((kTA ^ kTB) | (kTA ^ kTC)));      // a = b = c
+constexpr uint32_t kMajority = tt((kTA & kTB) | (kTA & kTC) | (kTB & kTC));
+constexpr uint32_t kXorAnd = tt((kTA ^ kTB) & kTC);                   // (a ^ b) & c
+// class idx = 2k + [c = +1] of a site with neighbours (a, b) and spin c
+constexpr uint32_t kClass0 = tt(~kTA & ~kTB & ~kTC), kClass1 = tt(~kTA & ~kTB & kTC);
+constexpr uint32_t kClass2 = tt((kTA ^ kTB) & ~kTC), kClass3 = tt((kTA ^ kTB) & kTC);
+constexpr uint32_t kClass4 = tt(kTA & kTB & ~kTC), kClass5 = tt(kTA & kTB & kTC);
+
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+
+// acc + popcount(x) as one accumulating v_bcnt.  Written as an instruction so
+// that the compiler does not regroup a chain of them into three-way adds of
+// separate popcounts (one more instruction per pair).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+// The 12 counts over one 32-site half of a word-transition, only the sites of
+// `live`: tot[i] = sites of class i (i < 5; class 5 takes the rest of the
+// sites), plus[i] = those drawn +1.  Each half has accumulators of its own,
+// so every popcount is one accumulating v_bcnt.  A thread adds at most 32 per
+// half-word and transition, so 2^27 word-transitions per thread stay exact.
+__device__ __forceinline__ void count_half(uint32_t c, uint32_t n1, uint32_t n2, uint32_t y, uint32_t live,
+                                           uint32_t (&tot)[5], uint32_t (&plus)[6]) {
+    const uint32_t cls[6] = {lop3<kClass0>(n1, n2, c) & live, lop3<kClass1>(n1, n2, c) & live,
+                             lop3<kClass2>(n1, n2, c) & live, lop3<kClass3>(n1, n2, c) & live,
+                             lop3<kClass4>(n1, n2, c) & live, lop3<kClass5>(n1, n2, c) & live};
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        const uint64_t a = cls[i], b = cls[i] & y;
-        tot[i] += __popc((uint32_t)a) + __popc((uint32_t)(a >> 32));
-        plus[i] += __popc((uint32_t)b) + __popc((uint32_t)(b >> 32));
+        if (i < 5)
+            tot[i] = bcnt_acc(cls[i], tot[i]);
+        plus[i] = bcnt_acc(cls[i] & y, plus[i]);
     }
 }
 
-// The paired statistics of one word-transition: acc gets popc(Q0), popc(Q2),
-// and popc(mask_j & z) for j = 0, 1, 2, with Q0 = sites whose neighbours both
-// equal the spin, Q2 = sites whose neighbours differ, W1 = the rest and
-// z = y ^ majority(n1, n2, c).  S_1 follows from the number of sites.  Only
-// the sites of `live` count.
-template <typename T>
-__device__ __forceinline__ void pair_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, T (&acc)[5],
-                                                uint64_t live = ~0ull) {
-    const uint64_t q2 = (n1 ^ n2) & live;
-    const uint64_t q0 = ~((n1 ^ c) | (n1 ^ n2)) & live;
-    const uint64_t w1 = ~(q0 | q2) & live;
-    const uint64_t z = y ^ ((q2 & c) | (~q2 & n1));
-    const uint64_t v[5] = {q0, q2, q0 & z, w1 & z, q2 & z};
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-        acc[i] += __popc((uint32_t)v[i]) + __popc((uint32_t)(v[i] >> 32));
+// The paired sums of one word-transition: acc gets popc(Q0), popc(Q2),
+// popc(Q0 & z), popc(Q2 & z) and popc(z), with Q0 = sites whose neighbours
+// both equal the spin, Q2 = sites whose neighbours differ (W1 = the rest) and
+// z = y ^ majority(n1, n2, c), the sites that drew the opposite of the
+// majority; Z_1 = popc(z) - Z_0 - Z_2 and S_1 follows from the number of
+// sites.  Only the sites of `live` count.
+__device__ __forceinline__ void pair_half(uint32_t c, uint32_t n1, uint32_t n2, uint32_t y, uint32_t live,
+                                          uint32_t (&acc)[5]) {
+    const uint32_t q2 = lop3<kXorAnd>(n1, n2, live);
+    const uint32_t q0 = lop3<kAllEqual>(n1, n2, c) & live;
+    const uint32_t z = lop3<kXorAnd>(y, lop3<kMajority>(n1, n2, c), live);
+    acc[0] += __popc(q0);
+    acc[1] += __popc(q2);
+    acc[2] += __popc(q0 & z);
+    acc[3] += __popc(q2 & z);
+    acc[4] += __popc(z);
 }
 
-// (S_0, S_1, S_2, Z_0, Z_1, Z_2) from pair_transition's five sums over
-// n_words word-transitions.
+template <typename T>
+__device__ __forceinline__ void pair_transition(uint64_t c, uint64_t n1, uint64_t n2, uint64_t y, T (&acc)[5]) {
+    const uint64_t q2 = n1 ^ n2;
+    const uint64_t q0 = ~((n1 ^ c) | q2);
+    const uint64_t z = y ^ ((q2 & c) | (~q2 & n1));
+    const uint64_t v[5] = {q0, q2, q0 & z, q2 & z, z};
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        acc[i] += __popcll(v[i]);
+}
+
+// (S_0, S_1, S_2, Z_0, Z_1, Z_2) from the five paired sums over n_words
+// word-transitions.
 template <typename T>
 __device__ __forceinline__ void pair_stats(const T (&acc)[5], int64_t n_words, int64_t (&out)[6]) {
     out[0] = (int64_t)acc[0];
     out[2] = (int64_t)acc[1];
     out[1] = 64 * n_words - out[0] - out[2];
     out[3] = (int64_t)acc[2];
-    out[4] = (int64_t)acc[3];
-    out[5] = (int64_t)acc[4];
+    out[5] = (int64_t)acc[3];
+    out[4] = (int64_t)acc[4] - out[3] - out[5];
 }
 
 // Workgroup sums of the 12 counts (or the 6 paired statistics): into partials[12 * block ...] when
@@ -161,22 +200,26 @@ __global__ __launch_bounds__(THREADS) void k_loglik_counts_lds(const uint64_t* _
     const uint32_t n_trans = n_lat - 1;
     const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     const uint64_t* X = traj + (size_t)a * n_lat * n_words;
-    uint32_t tot[6], plus[6], pst[5];
+    // per 32-site half: [0] low, [1] high
+    uint32_t tot[2][5], plus[2][6], pst[2][5];
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
-        tot[i] = plus[i] = 0;
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
-        pst[i] = 0;
+        for (int i = 0; i < 6; ++i)
+            plus[h][i] = 0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            tot[h][i] = pst[h][i] = 0;
+    }
     uint32_t n_mine = 0;
     uint32_t gi[WPT], i_down[WPT], i_up[WPT], i_prev[WPT], i_next[WPT];
-    uint64_t live[WPT];
+    uint32_t live[WPT];
 #pragma unroll
     for (uint32_t k = 0; k < WPT; ++k) {
         const uint32_t g = threadIdx.x + THREADS * k;
         const bool mine = FULL || g < n_words;
         n_mine += mine ? 1u : 0u;
-        live[k] = mine ? ~0ull : 0ull;
+        live[k] = mine ? ~0u : 0u;
         const uint32_t gg = mine ? g : 0u;
         const uint32_t j = fdiv(gg, divW);
         const uint32_t w = gg - j * W;
@@ -220,14 +263,27 @@ __global__ __launch_bounds__(THREADS) void k_loglik_counts_lds(const uint64_t* _
         }
 #pragma unroll
         for (uint32_t k = 0; k < WPT; ++k) {
-            const uint64_t c = cur[k];
-            const uint64_t n1 = nv[k];
-            const uint64_t n2 = (d & 1u) == 0 ? ((c << 1) | (nh[k] >> 63)) : ((c >> 1) | (nh[k] << 63));
-            if (PAIRED)
-                pair_transition(c, n1, n2, ring[d][k], pst, FULL ? ~0ull : live[k]);
-            else
-                count_transition32(c, n1, n2, ring[d][k], tot, plus, FULL ? ~0ull : live[k]);
-            cur[k] = ring[d][k];
+            const uint32_t c0 = lo32(cur[k]), c1 = hi32(cur[k]);
+            // the second neighbour: the word shifted by one site, the missing
+            // bit from the adjacent word (funnel shifts of the halves)
+            uint32_t m0, m1;
+            if ((d & 1u) == 0) {
+                m0 = __builtin_amdgcn_alignbit(c0, hi32(nh[k]), 31);
+                m1 = __builtin_amdgcn_alignbit(c1, c0, 31);
+            } else {
+                m0 = __builtin_amdgcn_alignbit(c1, c0, 1);
+                m1 = __builtin_amdgcn_alignbit(lo32(nh[k]), c1, 1);
+            }
+            const uint32_t lv = FULL ? ~0u : live[k];
+            const uint64_t y = ring[d][k];
+            if (PAIRED) {
+                pair_half(c0, lo32(nv[k]), m0, lo32(y), lv, pst[0]);
+                pair_half(c1, hi32(nv[k]), m1, hi32(y), lv, pst[1]);
+            } else {
+                count_half(c0, lo32(nv[k]), m0, lo32(y), lv, tot[0], plus[0]);
+                count_half(c1, hi32(nv[k]), m1, hi32(y), lv, tot[1], plus[1]);
+            }
+            cur[k] = y;
             ring[d][k] = Xf[gi[k]];
         }
     };
@@ -242,15 +298,22 @@ __global__ __launch_bounds__(THREADS) void k_loglik_counts_lds(const uint64_t* _
         if (mb + d < m1)
             transition(mb + d, d);
     if (PAIRED) {
-        int64_t acc[6];
-        pair_stats(pst, (int64_t)n_mine * (m1 - m0), acc);
+        int64_t sums[5], acc[6];
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            sums[i] = (int64_t)pst[0][i] + (int64_t)pst[1][i];
+        pair_stats(sums, (int64_t)n_mine * (m1 - m0), acc);
         flush_counts<6>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
     } else {
         int64_t acc[12];
+        int64_t rest = 64 * (int64_t)n_mine * (m1 - m0);   // sites seen by this thread
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            acc[2 * i + 1] = plus[i];
-            acc[2 * i] = (int64_t)tot[i] - (int64_t)plus[i];
+            const int64_t p = (int64_t)plus[0][i] + (int64_t)plus[1][i];
+            const int64_t t = i < 5 ? (int64_t)tot[0][i < 5 ? i : 0] + (int64_t)tot[1][i < 5 ? i : 0] : rest;
+            rest -= i < 5 ? t : 0;
+            acc[2 * i + 1] = p;
+            acc[2 * i] = t - p;
         }
         flush_counts<12>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
     }
@@ -506,31 +569,32 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     const uint64_t* X = static_cast<const uint64_t*>(traj);
     const FastDiv divW = make_fastdiv(L / 64u);
     const dim3 grid(n_traj, chunks);
-#define SD_LL_LDS(THREADS, WPT, DEPTH)                                                                                 \
+#define SD_LL_LDS(THREADS, WPT, DEPTH_PAIRED, DEPTH_COUNTS)                                                          \
     do {                                                                                                               \
         const bool full = n_words == (THREADS) * (WPT);                                                                \
         if (paired && full)                                                                                            \
-            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, true, true>), grid, dim3(THREADS), 0, st, X,  \
-                               n_lat, L, divW, acc, part);                                                             \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH_PAIRED, true, true>), grid, dim3(THREADS), 0, \
+                               st, X, n_lat, L, divW, acc, part);                                                      \
         else if (paired)                                                                                               \
-            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, true, false>), grid, dim3(THREADS), 0, st, X, \
-                               n_lat, L, divW, acc, part);                                                             \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH_PAIRED, true, false>), grid, dim3(THREADS),   \
+                               0, st, X, n_lat, L, divW, acc, part);                                                   \
         else if (full)                                                                                                 \
-            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, false, true>), grid, dim3(THREADS), 0, st, X, \
-                               n_lat, L, divW, acc, part);                                                             \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH_COUNTS, false, true>), grid, dim3(THREADS),   \
+                               0, st, X, n_lat, L, divW, acc, part);                                                   \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH, false, false>), grid, dim3(THREADS), 0, st,   \
-                               X, n_lat, L, divW, acc, part);                                                          \
+            hipLaunchKernelGGL((k_loglik_counts_lds<THREADS, WPT, DEPTH_COUNTS, false, false>), grid, dim3(THREADS),  \
+                               0, st, X, n_lat, L, divW, acc, part);                                                   \
     } while (0)
-    // a lattice of n_words words is spread over THREADS x WPT slots
+    // a lattice of n_words words is spread over THREADS x WPT slots; the ring
+    // depth keeps each variant within the registers of its occupancy
     if (n_words <= 64u) {
-        SD_LL_LDS(64, 1, 16);
+        SD_LL_LDS(64, 1, 16, 16);
     } else if (n_words <= 256u) {
-        SD_LL_LDS(256, 1, 16);
+        SD_LL_LDS(256, 1, 16, 16);
     } else if (n_words <= 1024u) {
-        SD_LL_LDS(256, 4, 4);
+        SD_LL_LDS(256, 4, 4, 4);
     } else if (n_words <= kStageWords) {
-        SD_LL_LDS(1024, 4, 4);
+        SD_LL_LDS(1024, 4, 2, 2);
 #undef SD_LL_LDS
     } else {
         if (paired)
