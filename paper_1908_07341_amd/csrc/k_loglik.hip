@@ -592,7 +592,7 @@ hipError_t launch_loglik_counts(const void* traj, uint32_t n_traj, uint32_t n_la
     } else if (n_words <= 256u) {
         SD_LL_LDS(256, 1, 16, 16);
     } else if (n_words <= 1024u) {
-        SD_LL_LDS(256, 4, 4, 4);
+        SD_LL_LDS(256, 4, 2, 2);
     } else if (n_words <= kStageWords) {
         SD_LL_LDS(1024, 4, 2, 2);
 #undef SD_LL_LDS
