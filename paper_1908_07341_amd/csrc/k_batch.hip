@@ -81,7 +81,7 @@ struct WaveWordList {
 
 // The chain's per-launch constants in LDS.
 struct ChainShared {
-    uint32_t T24[6];   // low 24 bits of the thresholds
+    uint32_t T24[6];   // tail thresholds of the classes (paired_tail in the paired form)
 };
 
 struct ObsSums {
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int i = 0; i < 6; ++i)
-                s_ch.T24[i] = cd.T[i] & 0xFFFFFFu;
+                s_ch.T24[i] = PAIRED ? paired_tail(cd.T, i) : cd.T[i] & 0xFFFFFFu;
         }
         __syncthreads();
 

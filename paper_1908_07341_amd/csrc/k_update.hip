@@ -238,7 +238,7 @@ struct WaveList {
 
 struct HalfStepScratch {
     WaveList list[kWavesPerBlock];
-    uint32_t T24[6];               // low 24 bits of the class thresholds
+    uint32_t T24[6];               // tail thresholds of the classes (paired_tail in the paired form)
 };
 
 struct ObsAcc {
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < 6; ++i)
-            sh.T24[i] = dp.T[i] & 0xFFFFFFu;
+            sh.T24[i] = PAIRED ? paired_tail(dp.T, i) : dp.T[i] & 0xFFFFFFu;
     }
     __syncthreads();
     const uint32_t n_tiles = (G.n_groups + kWaveTile - 1) / kWaveTile;

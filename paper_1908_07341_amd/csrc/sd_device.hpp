@@ -186,13 +186,30 @@ __device__ __forceinline__ PlaneMasks make_plane_masks(const DrawParams& dp) {
     return pm;
 }
 
-// True when every class pair (idx, 5 - idx) has complementary top bytes, i.e.
-// no threshold has its low 24 bits all zero (host-side check).
+// True when every class pair satisfies T[idx] + T[5 - idx] = 2^32, the
+// condition of the paired compare.  The threshold table always meets it
+// (the classes of a pair have opposite fields and T(h) + T(-h) = 2^32), so
+// the general form remains only as a checked fallback.
 inline bool thresholds_paired(const uint32_t T[6]) {
-    for (int i = 0; i < 6; ++i)
-        if ((T[i] & 0xFFFFFFu) == 0u)
+    for (int i = 0; i < 3; ++i)
+        if ((uint32_t)(T[i] + T[5 - i]) != 0u)
             return false;
     return true;
+}
+
+// The tail threshold of class idx in the paired compare.  The scan compares
+// the top byte of r with the top byte of T[idx] for idx < 3 and with the
+// complement of the top byte of T[5 - idx] for idx >= 3; a site left
+// undecided has r's top byte equal to that scan byte B, so r < T[idx] iff its
+// low 24 bits are below T[idx] - B * 2^24.  That is T[idx] mod 2^24 when B is
+// T[idx]'s own top byte, and 2^24 (every tail) when the pair's thresholds are
+// multiples of 2^24 (T[5 - idx] = B' 2^24 makes T[idx] = (256 - B') 2^24 while
+// the scan byte is 255 - B').
+__host__ __device__ inline uint32_t paired_tail(const uint32_t T[6], int idx) {
+    if (idx < 3)
+        return T[idx] & 0xFFFFFFu;
+    const uint32_t scan_byte = 255u - (T[5 - idx] >> 24);
+    return T[idx] - (scan_byte << 24);
 }
 
 // Bit-sliced comparison of the top 8 bits of every r_s in a 32-site half word
