@@ -69,6 +69,9 @@ typedef enum { SD_INIT_UP = 0, SD_INIT_DOWN = 1, SD_INIT_RANDOM = 2 } sd_init_ki
 #define SD_FLAG_MOMENTS 4u        /* batch plans: keep per-chain sums of the records instead of traces */
 #define SD_FLAG_GLOBAL_KERNELS 2u /* sd_run: always use one grid-wide launch per half-step, never the
                                      single-workgroup LDS-resident kernel used for small lattices */
+#define SD_FLAG_GENERAL_COMPARE 8u /* sd_half_step, sd_run, batch plans: decide the sites with the
+                                      six-class bit-sliced compare instead of the paired one (same
+                                      results, slower; a cross-check of the two forms) */
 
 #define SD_ABI_VERSION 1
 
@@ -105,7 +108,8 @@ SD_API sd_status sd_init(void* lattice, int32_t L, int32_t layout, int32_t kind,
  * One half-step: which = 0 draws tau (dst) from sigma (src) with the
  * down/left field (eq. (15)); which = 1 draws sigma' (dst) from tau (src) with
  * the up/right field (eq. (16)).  t is the half-step index (< 2^30).  src and
- * dst are device lattices of the same layout and must not overlap.
+ * dst are device lattices of the same layout and must not overlap.  flags:
+ * SD_FLAG_COMPLEMENT_RNG, SD_FLAG_GENERAL_COMPARE.
  */
 SD_API sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, int32_t which, double J, double q,
                        uint64_t seed, uint32_t stream, uint32_t t, uint32_t flags, void* hip_stream);
@@ -122,6 +126,7 @@ SD_API sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t lay
  * of the pair (sigma_n, tau_n) — the new sigma and the tau it was drawn from —
  * so that m = M / L^2 and H(sigma, tau) = -(J A + q B) (section 3.1, eq. (5)):
  * obs[3 * r + {0, 1, 2}] for record r = 0 .. k_steps/obs_every - 1.
+ * flags: SD_FLAG_COMPLEMENT_RNG, SD_FLAG_GLOBAL_KERNELS, SD_FLAG_GENERAL_COMPARE.
  * EINVAL: bad sizes, obs without obs_every, step0 + k_steps >= 2^29.
  */
 SD_API sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
@@ -315,7 +320,7 @@ typedef struct sd_batch_plan sd_batch_plan;
  * picks each group's workgroup size: measured and cached in the JSON file
  * tune_cache_path if that is not NULL (measuring allocates scratch device
  * memory for the duration of the call), 256 otherwise.  layout is SD_P64 or
- * SD_I8.  flags: SD_FLAG_COMPLEMENT_RNG, and SD_FLAG_MOMENTS (needs
+ * SD_I8.  flags: SD_FLAG_COMPLEMENT_RNG, SD_FLAG_GENERAL_COMPARE, and SD_FLAG_MOMENTS (needs
  * obs_every > 0), under which the trace buffer holds instead, per chain, the
  * 5 int64 sums over the run's recorded steps of M, M^2, |M|, A and B (the
  * mean and variance of the magnetisation that section 3.1 scans; each

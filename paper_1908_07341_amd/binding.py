@@ -20,6 +20,7 @@ SD_INIT_UP, SD_INIT_DOWN, SD_INIT_RANDOM = 0, 1, 2
 SD_FLAG_COMPLEMENT_RNG = 1
 SD_FLAG_GLOBAL_KERNELS = 2
 SD_FLAG_MOMENTS = 4
+SD_FLAG_GENERAL_COMPARE = 8
 
 
 class sd_chain_desc(ctypes.Structure):

@@ -267,7 +267,7 @@ sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, in
         return fail(SD_EINVAL, "sd_half_step: J and q must be finite");
     if (t >= (1u << 30))
         return fail(SD_EINVAL, "sd_half_step: half-step index must be < 2^30");
-    if (flags & ~SD_FLAG_COMPLEMENT_RNG)
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GENERAL_COMPARE))
         return fail(SD_EINVAL, "sd_half_step: unknown flags");
     if (overlap(src, dst, lattice_bytes(L, layout)))
         return fail(SD_EINVAL, "sd_half_step: src and dst overlap");
@@ -278,7 +278,8 @@ sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, in
                                        : kernel_layout(L, layout, src);
     const Geom G = make_geom(L, klay);
     const DrawParams dp = dynamics_params(J, q, seed, stream, t, flags);
-    hipError_t e = launch_half_step(klay, which, src, dst, G, dp, nullptr, static_cast<hipStream_t>(hip_stream));
+    hipError_t e = launch_half_step(klay, which, src, dst, G, dp, nullptr, static_cast<hipStream_t>(hip_stream), 0,
+                                    nullptr, (flags & SD_FLAG_GENERAL_COMPARE) != 0);
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_half_step");
 }
 
@@ -296,7 +297,7 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
         return fail(SD_EINVAL, "sd_run: step indices must stay below 2^29");
     if (obs && obs_every == 0)
         return fail(SD_EINVAL, "sd_run: obs given without obs_every");
-    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GLOBAL_KERNELS))
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GLOBAL_KERNELS | SD_FLAG_GENERAL_COMPARE))
         return fail(SD_EINVAL, "sd_run: unknown flags");
     if (overlap(sigma, tau, lattice_bytes(L, layout)))
         return fail(SD_EINVAL, "sd_run: sigma and tau overlap");
@@ -330,14 +331,15 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
         DrawParams dp = dynamics_params(J, q, seed, stream, (uint32_t)(2 * n), flags & SD_FLAG_COMPLEMENT_RNG);
-        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks);
+        const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
+        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks, nullptr, general);
         if (e != hipSuccess)
             break;
         dp.t = (uint32_t)(2 * n + 1);
         int64_t* rec = nullptr;
         if (n_rec && (m + 1) % obs_every == 0)
             rec = obs + 3u * (size_t)((m + 1) / obs_every - 1);
-        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks, partials);
+        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks, partials, general);
     }
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
 }

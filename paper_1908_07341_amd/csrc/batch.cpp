@@ -263,7 +263,7 @@ hipError_t launch_single_chain_lds(void* sigma, void* tau, int32_t L, bool int8_
     std::memset(&a, 0, sizeof a);
     a.counter = nullptr;
     threshold_table(J, q, a.single.T);
-    a.single.paired = thresholds_paired(a.single.T) ? 1u : 0u;
+    a.single.paired = thresholds_paired(a.single.T) && !(flags & SD_FLAG_GENERAL_COMPARE) ? 1u : 0u;
     a.single.L = (uint32_t)L;
     a.single.stream = stream;
     set_divisors(a.single, (uint32_t)L);
@@ -302,7 +302,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         return fail(SD_EUNSUPPORTED, "sd_batch_plan_create: layout must be SD_P64 or SD_I8");
     if (k_steps >= (1u << 29))
         return fail(SD_EINVAL, "sd_batch_plan_create: k_steps must be below 2^29");
-    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_MOMENTS))
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_MOMENTS | SD_FLAG_GENERAL_COMPARE))
         return fail(SD_EINVAL, "sd_batch_plan_create: unknown flags");
     if ((flags & SD_FLAG_MOMENTS) && !obs_every)
         return fail(SD_EINVAL, "sd_batch_plan_create: SD_FLAG_MOMENTS needs obs_every > 0");
@@ -347,7 +347,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         }
         ChainDesc& d = p->descs[(size_t)c];
         threshold_table(in.J, in.q, d.T);
-        d.paired = thresholds_paired(d.T) ? 1u : 0u;
+        d.paired = thresholds_paired(d.T) && !(flags & SD_FLAG_GENERAL_COMPARE) ? 1u : 0u;
         d.L = (uint32_t)in.L;
         d.stream = in.stream;
         set_divisors(d, (uint32_t)in.L);

@@ -510,8 +510,8 @@ void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, 
 }
 
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st, uint32_t max_blocks, int64_t* partials) {
-    const bool paired = thresholds_paired(dp.T);
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks, int64_t* partials, bool general) {
+    const bool paired = !general && thresholds_paired(dp.T);
     uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
     if (max_blocks && blocks > max_blocks)
         blocks = max_blocks;

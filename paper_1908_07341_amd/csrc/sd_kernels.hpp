@@ -55,8 +55,10 @@ inline uint32_t fdiv_host(uint32_t n, const FastDiv& f) {
 // 4 * kMaxBlocks int64), the workgroups' partial sums go to partials and a
 // one-workgroup kernel adds M, A, B into obs; without partials every
 // workgroup adds into obs with atomics.
+// general: use the six-class compare even when the table is paired.
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st, uint32_t max_blocks = 0, int64_t* partials = nullptr);
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks = 0, int64_t* partials = nullptr,
+                            bool general = false);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
                        hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);

@@ -84,7 +84,7 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_half_step(fake, fake2, 64, sd.SD_I8, 0, 0.4, 0.6, 1, 0, 2 ** 30, 0, st) == sd.SD_EINVAL
     assert lib.sd_half_step(fake, ctypes.c_void_p(0x10100), 64, sd.SD_I8, 0, 0.4, 0.6, 1, 0, 0, 0, st) == sd.SD_EINVAL
     assert b"overlap" in lib.sd_last_error()
-    assert lib.sd_half_step(fake, fake2, 64, sd.SD_I8, 0, 0.4, 0.6, 1, 0, 0, 8, st) == sd.SD_EINVAL
+    assert lib.sd_half_step(fake, fake2, 64, sd.SD_I8, 0, 0.4, 0.6, 1, 0, 0, 16, st) == sd.SD_EINVAL
     assert lib.sd_half_step(ctypes.c_void_p(0x10004), fake2, 64, sd.SD_P64, 0, 0.4, 0.6, 1, 0, 0, 0, st) == sd.SD_EINVAL
     assert lib.sd_run(fake, fake2, 64, sd.SD_I8, 0.4, 0.6, 1, 0, 0, 10, fake, 0, 0, st) == sd.SD_EINVAL
     assert lib.sd_run(fake, fake2, 64, sd.SD_I8, 0.4, 0.6, 1, 0, 2 ** 29, 1, None, 0, 0, st) == sd.SD_EINVAL

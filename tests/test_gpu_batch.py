@@ -66,6 +66,27 @@ def test_batch_matches_oracle(oracle, layout, sizes):
     plan.close()
 
 
+def test_batch_general_compare_flag_identical():
+    # scan-like (J, q) including rows with h = 0 classes (J = 0, q = 0, q = 2J)
+    J = np.array([0.0, 0.3, 0.5, 0.7, 0.0, 0.45, 1.2, 0.25])
+    q = np.array([0.0, 0.0, 1.0, 0.4, 0.9, 0.9, 0.3, 0.5])
+    L = np.array([64, 128, 40, 200, 72, 64, 8, 128])
+    st = np.arange(8) + 70
+    res = []
+    for flags in (0, sd.SD_FLAG_GENERAL_COMPARE):
+        plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=20, obs_every=2, flags=flags)
+        lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+        tr = torch.zeros(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+        sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+        sd.sd_batch_run(plan, lat, tr, 0)
+        torch.cuda.synchronize()
+        res.append(([_unpack(lat, sd.sd_batch_chain_offset(plan, c, w), int(L[c]), sd.SD_P64)
+                     for c in range(len(J)) for w in (0, 1)], tr.cpu().numpy()))
+        plan.close()
+    assert all(np.array_equal(a, b) for a, b in zip(res[0][0], res[1][0]))
+    assert np.array_equal(res[0][1], res[1][1])
+
+
 def test_batch_equals_plain_runs_and_graph_reuse():
     J, q, L, st = _chains(40, [128, 256, 512], seed=9)
     k = 25

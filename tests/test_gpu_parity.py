@@ -345,3 +345,25 @@ def test_run_captured_in_a_graph_replays_like_eager(L, layout):
         torch.cuda.synchronize()
         assert torch.equal(sig_g, sig_e) and torch.equal(tau_g, tau_e), (L, r)
         assert torch.equal(obs_g, obs_e), (L, r)
+
+
+@pytest.mark.parametrize("J,q", [(0.4, 0.6), (0.0, 0.0), (0.5, 1.0), (0.0, 0.7), (0.8, 0.0), (-0.3, 0.5)])
+def test_general_compare_flag_gives_identical_chains(oracle, J, q):
+    # the paired compare (default) and the six-class compare must draw the same
+    # spins; (0, 0), (0.5, 1) (q = 2J), (0, q) and (J, 0) have classes with
+    # h = 0, whose pair of thresholds are multiples of 2^24
+    print(f"general compare J={J} q={q}", flush=True)
+    for L, layout, flags in [(40, sd.SD_P64, 0), (64, sd.SD_I8, 0), (128, sd.SD_P64, 0),
+                             (192, sd.SD_P64, sd.SD_FLAG_GLOBAL_KERNELS), (96, sd.SD_P32, 0)]:
+        s0 = inputs.random_lattice(L, 31)
+        out = []
+        for extra in (0, sd.SD_FLAG_GENERAL_COMPARE):
+            sigma, tau = to_device(s0, layout), sd.new_lattice(L, layout)
+            obs = torch.zeros((12, 3), dtype=torch.int64, device="cuda")
+            sd.sd_run(sigma, tau, L, layout, J, q, SEED, 11, 3, 12, obs, 1, flags | extra)
+            out.append((to_host(sigma, L, layout), to_host(tau, L, layout), obs.cpu().numpy()))
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a, b), (L, layout)
+        if L == 40:
+            rs, rt, ro = oracle.run(s0, J, q, SEED, 11, 3, 12, obs_every=1)
+            assert np.array_equal(out[0][0], rs) and np.array_equal(out[0][1], rt) and np.array_equal(out[0][2], ro)
