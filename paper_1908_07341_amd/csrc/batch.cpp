@@ -330,7 +330,8 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     p->flags = flags;
     p->descs.resize((size_t)n_chains);
 
-    // buckets by (L, paired form): largest L first, paired before unpaired
+    // buckets by (L, compare form): largest L first, paired before the
+    // six-class form (only under SD_FLAG_GENERAL_COMPARE)
     std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>, std::greater<std::pair<uint32_t, uint32_t>>> by_L;
     size_t off = 0;
     for (int32_t c = 0; c < n_chains; ++c) {

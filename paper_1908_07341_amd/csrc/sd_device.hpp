@@ -154,9 +154,10 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 // Threshold bits of the eight planes as all-ones / all-zeros masks, one per
 // (plane m, class idx): S[m][idx] = ~0 iff bit (31 - m) of T[idx] is set.
 // Classes idx and 5 - idx have opposite fields (k -> 2 - k, c -> -c), so
-// T[5 - idx] = 2^32 - T[idx]; when no T[idx] has its low 24 bits all zero the
-// top bytes of the pair are bitwise complements and only the three "leader"
-// classes 0, 1, 2 are needed (paired form, see compare_planes_paired).
+// T[5 - idx] = 2^32 - T[idx]: the top bytes of a pair are bitwise complements
+// unless both thresholds are multiples of 2^24, and the scan needs only the
+// three "leader" classes 0, 1, 2 (paired form, see compare_planes_paired and
+// paired_tail for the exception).
 struct PlaneMasks {
     uint32_t S[8][6];   // general form: all ones where bit (31 - m) of T[i] is set
     uint32_t code;      // paired form: bits 3m..3m+2 = bit (31 - m) of T[0], T[1], T[2]

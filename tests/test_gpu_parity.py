@@ -61,8 +61,9 @@ def test_init_matches_oracle(oracle, L):
             assert np.array_equal(to_host(lat, L, layout), oracle.init(L, kind, p, SEED, 7)), (L, layout, kind, p)
 
 
-# (0, 0) and (0.25, 0.5) give classes with h = 0 (threshold 2^31 exactly), which
-# exercises the kernels' general (unpaired) threshold form.
+# (0, 0), (0, 0.9) and (0.25, 0.5) give classes with h = 0 (threshold 2^31
+# exactly), whose pair of thresholds the paired compare resolves with the
+# 2^24 tail threshold (paired_tail).
 PARAMS = [(0.4, 0.6), (0.0, 0.0), (0.0, 0.9), (1.1, 0.2), (-0.5, 0.8), (0.6585, 0.6585), (3.0, 2.5), (0.25, 0.5)]
 
 
