@@ -1,0 +1,132 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times, on outputs the oracle can compute one by one:
+
+* the 4096-chain (q, J) scan (L from {128, 256, 512}, 5000 steps, records
+  every step): two 128^2 chains in full against the oracle, one chain of
+  every size against its own sd_run, and for every chain the last record
+  against a recount of the returned lattice pair;
+* the differentiation workload (256 trajectories of 256^2, 2000 steps):
+  trajectory 0 lattice by lattice and its counts and paired statistics
+  against the oracle; for the whole set, the site total, the pair map of
+  the counts and the FP32 LL and gradient against FP64 from the counts."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1908_07341_amd as sd
+from paper_1908_07341_amd import autograd as AG
+from paper_1908_07341_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.lib()
+
+
+def _unpack_many(raw: np.ndarray, L: int) -> np.ndarray:
+    bits = np.unpackbits(np.ascontiguousarray(raw).view(np.uint8).reshape(raw.shape[0], -1), axis=1,
+                         bitorder="little")[:, : L * L]
+    return (2 * bits.astype(np.int8) - 1).reshape(-1, L, L)
+
+
+def test_C4_full_scan_sampled(oracle, tmp_path):
+    qv, Jv, Lv = inputs.scan_table()
+    n, K = len(qv), 5000
+    streams = np.arange(n, dtype=np.uint32)
+    print("C4 plan", flush=True)
+    plan = sd.sd_batch_plan_create(Jv, qv, Lv, streams, layout=sd.SD_P64, seed=1, k_steps=K, obs_every=1,
+                                   tune_cache_path=str(tmp_path / "tune.json"))
+    lat = torch.empty(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    traces = torch.empty(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+    start = lat.clone()
+    print("C4 run", flush=True)
+    sd.sd_batch_run(plan, lat, traces, 0)
+    torch.cuda.synchronize()
+    tr = traces.view(n, K, 3)
+
+    def pair(c):
+        Lc = int(Lv[c])
+        nb = sd.sd_lattice_bytes(Lc, sd.SD_P64)
+        so, to = sd.sd_batch_chain_offset(plan, c, 0), sd.sd_batch_chain_offset(plan, c, 1)
+        return Lc, nb, so, to
+
+    # every chain: the last record is (M, A, B) of the returned pair
+    out = torch.empty((n, 3), dtype=torch.int64, device="cuda")
+    for c in range(n):
+        Lc, nb, so, to = pair(c)
+        sd.sd_observe(lat[so:so + nb], lat[to:to + nb], Lc, sd.SD_P64, out[c])
+    torch.cuda.synchronize()
+    assert torch.equal(out, tr[:, K - 1, :])
+
+    rng = np.random.default_rng(11)
+    # one chain of every size against its own sd_run from the same start
+    for size in (128, 256, 512):
+        c = int(rng.choice(np.flatnonzero(Lv == size)))
+        Lc, nb, so, to = pair(c)
+        sig = start[so:so + nb].clone()
+        tau = torch.empty_like(sig)
+        obs = torch.empty((K, 3), dtype=torch.int64, device="cuda")
+        print(f"C4 chain {c} L={Lc} against sd_run", flush=True)
+        sd.sd_run(sig, tau, Lc, sd.SD_P64, float(Jv[c]), float(qv[c]), 1, c, 0, K, obs, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(sig, lat[so:so + nb]) and torch.equal(tau, lat[to:to + nb]), c
+        assert torch.equal(obs, tr[c]), c
+    # two 128^2 chains in full against the oracle
+    for c in rng.choice(np.flatnonzero(Lv == 128), size=2, replace=False):
+        c = int(c)
+        Lc, nb, so, to = pair(c)
+        print(f"C4 chain {c} L={Lc} against the oracle", flush=True)
+        s0 = oracle.init(Lc, oracle.INIT_RANDOM, 0.5, 1, c)
+        assert np.array_equal(inputs.unpack_bits(start[so:so + nb].cpu().numpy(), Lc), s0)
+        rs, rt, ro = oracle.run(s0, float(Jv[c]), float(qv[c]), 1, c, 0, K, obs_every=1)
+        assert np.array_equal(inputs.unpack_bits(lat[so:so + nb].cpu().numpy(), Lc), rs), c
+        assert np.array_equal(inputs.unpack_bits(lat[to:to + nb].cpu().numpy(), Lc), rt), c
+        assert np.array_equal(tr[c].cpu().numpy(), ro), c
+    plan.close()
+
+
+def test_C5_full_loglik_sampled(oracle):
+    n_traj, L, k, J, q = 256, 256, 2000, 0.45, 0.7
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    n_lat = 2 * k + 1
+    print("C5 trajectories", flush=True)
+    starts = torch.empty((n_traj, nb // 8), dtype=torch.int64, device="cuda")
+    for a in range(n_traj):
+        sd.sd_init(starts[a], L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, a)
+    traj = torch.empty((n_traj, n_lat, nb // 8), dtype=torch.int64, device="cuda")
+    sd.sd_trajectories(starts, traj, n_traj, L, sd.SD_P64, J, q, 1, 0, 0, k)
+    counts = AG.loglik_counts(traj, n_traj, n_lat, L)
+    stats = AG.loglik_stats(traj, n_traj, n_lat, L)
+    c0 = AG.loglik_counts(traj[:1], 1, n_lat, L)
+    s0_ = AG.loglik_stats(traj[:1], 1, n_lat, L)
+    torch.cuda.synchronize()
+    # trajectory 0 lattice by lattice
+    print("C5 trajectory 0 against the oracle", flush=True)
+    X = oracle.trajectory(oracle.init(L, oracle.INIT_RANDOM, 0.5, 1, 0), J, q, 1, 0, 0, k)
+    assert np.array_equal(_unpack_many(traj[0].cpu().numpy(), L), X)
+    assert np.array_equal(c0.cpu().numpy(), oracle.loglik_counts(X[None]))
+    assert np.array_equal(s0_.cpu().numpy(), oracle.loglik_stats(X[None]))
+    del X
+    # the whole set
+    ch, sh = counts.cpu().numpy(), stats.cpu().numpy()
+    assert ch.sum() == n_traj * 2 * k * L * L
+    S = [ch[2 * j] + ch[2 * j + 1] + ch[2 * (5 - j)] + ch[2 * (5 - j) + 1] for j in range(3)]
+    Z = [ch[2 * j + 1] + ch[2 * (5 - j)] for j in range(3)]
+    assert np.array_equal(sh, np.array(S + Z))
+    for Jp, qp in ((0.2, 0.2), (0.45, 0.7)):
+        Jt = torch.tensor([Jp, qp], dtype=torch.float32, device="cuda", requires_grad=True)
+        J32, q32 = (float(x) for x in Jt.detach().cpu().numpy())
+        for vec in (counts, stats):
+            ll = AG.loglik(Jt, vec)
+            (g,) = torch.autograd.grad(ll, Jt)
+            ll64, g64 = oracle.loglik(ch, J32, q32), oracle.loglik_grad(ch, J32, q32)
+            assert abs(float(ll.detach()) - ll64) <= 1e-6 * abs(ll64)
+            scale = 2.0 * float(ch.sum())
+            gg = g.cpu().numpy().astype(np.float64)
+            for i in range(2):
+                assert abs(gg[i] - g64[i]) <= 1e-5 * abs(g64[i]) + 1e-9 * scale, (Jp, qp, i, gg[i], g64[i])
