@@ -5,6 +5,8 @@ benchmark times, on outputs the oracle can compute one by one:
   every step): two 128^2 chains in full against the oracle, one chain of
   every size against its own sd_run, and for every chain the last record
   against a recount of the returned lattice pair;
+* one point of the 1024^2 int8 sweep for its full 10^4 steps: records,
+  D(r) and sampled sites of a further step against the oracle;
 * the differentiation workload (256 trajectories of 256^2, 2000 steps):
   trajectory 0 lattice by lattice and its counts and paired statistics
   against the oracle; for the whole set, the site total, the pair map of
@@ -130,3 +132,44 @@ def test_C5_full_loglik_sampled(oracle):
             gg = g.cpu().numpy().astype(np.float64)
             for i in range(2):
                 assert abs(gg[i] - g64[i]) <= 1e-5 * abs(g64[i]) + 1e-9 * scale, (Jp, qp, i, gg[i], g64[i])
+
+
+def test_C2_full_length_point(oracle):
+    # 1024^2 int8 from a random start at J = q = 0.6 (the middle of the sweep,
+    # stream 2), 10^4 steps with (M, A, B) every step and D(r <= 512) every 100
+    # steps: D(0) = L^2 at every measurement, the final D(r) against the
+    # oracle's sum over the returned lattice, the last record against a recount
+    # of the returned pair, and one more step's sampled sites against the
+    # oracle's thresholds and uniforms
+    L, J, q, stream = 1024, 0.6, 0.6, 2
+    sigma = sd.new_lattice(L, sd.SD_I8)
+    tau = sd.new_lattice(L, sd.SD_I8)
+    sd.sd_init(sigma, L, sd.SD_I8, sd.SD_INIT_RANDOM, 0.5, 1, stream)
+    obs = torch.empty((10000, 3), dtype=torch.int64, device="cuda")
+    D = torch.empty((100, 513), dtype=torch.int64, device="cuda")
+    print("C2 full-length run", flush=True)
+    for blk in range(100):
+        sd.sd_run(sigma, tau, L, sd.SD_I8, J, q, 1, stream, 100 * blk, 100, obs[100 * blk:100 * (blk + 1)], 1)
+        sd.sd_corr_row(sigma, L, sd.SD_I8, 512, D[blk])
+    torch.cuda.synchronize()
+    assert bool((D[:, 0] == L * L).all())
+    s_fin = to_host_i8(sigma, L)
+    assert np.array_equal(D[-1].cpu().numpy(), oracle.corr_row(s_fin, 512))
+    out3 = torch.empty(3, dtype=torch.int64, device="cuda")
+    sd.sd_observe(sigma, tau, L, sd.SD_I8, out3)
+    assert torch.equal(out3, obs[-1])
+    sd.sd_run(sigma, tau, L, sd.SD_I8, J, q, 1, stream, 10000, 1, None, 0)
+    t_new, s_new = to_host_i8(tau, L), to_host_i8(sigma, L)
+    rng = np.random.default_rng(2)
+    for j in [0, L - 1] + [int(x) for x in rng.integers(0, L, 6)]:
+        rowA = oracle.row_thresholds_of(s_fin, J, q, 0, j)
+        rowB = oracle.row_thresholds_of(t_new, J, q, 1, j)
+        for i in [0, L - 1] + [int(x) for x in rng.integers(0, L, 40)]:
+            s = j * L + i
+            assert t_new[j, i] == (1 if oracle.site_uniform(1, stream, 20000, 0, s) < rowA[i] else -1), (j, i)
+            assert s_new[j, i] == (1 if oracle.site_uniform(1, stream, 20001, 0, s) < rowB[i] else -1), (j, i)
+
+
+def to_host_i8(t: torch.Tensor, L: int) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.int8).reshape(L, L)
