@@ -295,6 +295,40 @@ SD_API sd_status sd_propp_wilson(void* samples, void* work, int32_t n_samples, i
                                  int64_t* T_used, void* hip_stream);
 
 /* ------------------------------------------------------------------------- */
+/* Replica-coded chains: 64 chains that share one stream, one bit each.        */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Bytes of a replica lattice: L * L 64-bit words, word s = j L + i holding
+ * site (i, j) of 64 replicas, bit r for replica r (1 = spin +1).  0 unless L
+ * is a multiple of 8 in [8, 32768].
+ */
+SD_API size_t sd_replica_lattice_bytes(int32_t L);
+
+/*
+ * k_steps full steps (steps step0 .. step0+k_steps-1) of 64 chains at once,
+ * chain r at (J[r], q[r]) (host arrays of 64), all with the same seed and
+ * stream: every site's uniform (eqs. (15)-(16) draw each spin independently,
+ * so one uniform per site and half-step) is drawn once and compared with the
+ * 64 chains' own thresholds.  Replica r's lattices equal, bit for bit, those
+ * of sd_run at (J[r], q[r], seed, stream) from the same start; the chains are
+ * not independent of each other (they share their randomness, which is what
+ * makes them a monotone coupling when their (J, q) agree), but each is an
+ * exact chain of its own (J, q).  sigma (device) is updated in place; tau
+ * (device, same size) receives the last half-step-A lattice.  Layout as
+ * sd_replica_lattice_bytes; 8-byte aligned, non-overlapping.  EINVAL: bad L,
+ * null or non-finite parameters, step0 + k_steps > 2^29.
+ */
+SD_API sd_status sd_replica_run(void* sigma, void* tau, int32_t L, const double* J, const double* q, uint64_t seed,
+                                uint32_t stream, uint64_t step0, uint32_t k_steps, void* hip_stream);
+
+/*
+ * out (device, 192 int64): out[3 r + {0, 1, 2}] = (M, A, B) of replica r's
+ * pair (sigma, tau), as sd_observe computes them for one chain.
+ */
+SD_API sd_status sd_replica_observe(const void* sigma, const void* tau, int32_t L, int64_t* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
 /* Batched scan: many independent chains in one persistent launch.            */
 /* ------------------------------------------------------------------------- */
 

@@ -57,6 +57,9 @@ SIGNATURES = {
     "sd_loglik_fwd": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "sd_loglik_stats": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_replica_lattice_bytes": (ctypes.c_size_t, [_I32]),
+    "sd_replica_run": (_I32, [_VP, _VP, _I32, _VP, _VP, _U64, _U32, _U64, _U32, _VP]),
+    "sd_replica_observe": (_I32, [_VP, _VP, _I32, _VP, _VP]),
     "sd_propp_wilson": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _U32, _VP, _VP]),
     "sd_loglik_fwd_stats": (_I32, [_VP, _VP, _VP, _VP]),
     "sd_loglik_bwd_stats": (_I32, [_VP, _VP, _VP, _VP, _VP]),
@@ -202,6 +205,24 @@ def sd_propp_wilson(samples, work, n_samples, L, J, q, seed, stream0, step_end, 
     _check(lib().sd_propp_wilson(_ptr(samples), _ptr(work), n_samples, L, J, q, seed, stream0, step_end, T0, T_max,
                                  ctypes.cast(T_used, ctypes.c_void_p), _stream(hip_stream)))
     return list(T_used[:n_samples])
+
+
+def sd_replica_lattice_bytes(L: int) -> int:
+    return int(lib().sd_replica_lattice_bytes(L))
+
+
+def sd_replica_run(sigma, tau, L, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:
+    """64 chains sharing one stream; J and q: 64 floats each (host)."""
+    Ja = (ctypes.c_double * 64)(*[float(x) for x in J])
+    qa = (ctypes.c_double * 64)(*[float(x) for x in q])
+    if len(J) != 64 or len(q) != 64:
+        raise ValueError("sd_replica_run needs 64 values of J and of q")
+    _check(lib().sd_replica_run(_ptr(sigma), _ptr(tau), L, ctypes.cast(Ja, ctypes.c_void_p),
+                                ctypes.cast(qa, ctypes.c_void_p), seed, stream, step0, k_steps, _stream(hip_stream)))
+
+
+def sd_replica_observe(sigma, tau, L, out, hip_stream=None) -> None:
+    _check(lib().sd_replica_observe(_ptr(sigma), _ptr(tau), L, _ptr(out), _stream(hip_stream)))
 
 
 class sd_batch_plan:

@@ -1,0 +1,194 @@
+// Replica-coded shaken dynamics: multi-spin coding across chains.  Word s of a
+// replica lattice holds site s (row-major, s = j L + i) of 64 replicas, bit r
+// for replica r (1 = spin +1).  The replicas share the seed and the stream, so
+// each site's uniform r_s -- the eight bit-planes of its 64-site group and its
+// 24-bit tail, exactly as a single chain draws them -- serves all 64, and
+// replica r compares it with its own thresholds T_r (its own J_r, q_r).
+// Replica r therefore follows, bit for bit, the single chain at (J_r, q_r) with
+// that seed and stream, while the uniforms are drawn once per site instead of
+// once per site and chain.
+//
+// A wavefront takes batches of 16 groups (1024 sites).  Its 64 lanes first
+// evaluate the batch's 64 plane calls (lane 4 g + p: call p of group g) and its
+// 256 tail calls (four evaluations, tails kept in LDS), then walk the groups
+// one lane per site: the plane words of the group are read from the lane that
+// drew them (v_readlane), each lane takes its site's bit as an all-ones or
+// all-zeros mask, and the 64 replicas of the site are compared bit-sliced in
+// the paired form (per-replica threshold bits S[m][k] as uniform words).
+// Replicas left undecided after the eight planes (top byte of r_s equal to
+// their scan byte) compare the site's tail with their tail threshold.
+#include "sd_replica.hpp"
+
+namespace sd {
+
+namespace {
+
+constexpr uint32_t kBatch = 16;   // groups per batch: 16 groups x 4 plane calls = one call per lane
+
+// Immediates of V_BITOP3: the function applied bitwise to the operand patterns
+// 0xF0, 0xCC, 0xAA.
+constexpr uint32_t kTA = 0xF0u, kTB = 0xCCu, kTC = 0xAAu;
+constexpr uint32_t tt3(uint32_t f) { return f & 0xFFu; }
+constexpr uint32_t kAllEqual = tt3(~((kTA ^ kTB) | (kTA ^ kTC)));
+constexpr uint32_t kMajority = tt3((kTA & kTB) | (kTA & kTC) | (kTB & kTC));
+constexpr uint32_t kNor = tt3(~(kTA | kTB));
+constexpr uint32_t kSelect = tt3((kTA & kTB) | (~kTA & kTC));       // a ? b : c
+constexpr uint32_t kSelectNot = tt3((kTA & ~kTB) | (~kTA & kTC));   // a ? ~b : c
+constexpr uint32_t kAndNotXor = tt3(kTA & ~(kTB ^ kTC));            // a & ~(b ^ c)
+
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t op3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr uint32_t kWaves = 4;   // wavefronts per workgroup
+
+template <int WHICH>
+__global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __restrict__ src,
+                                                             uint64_t* __restrict__ dst, uint32_t L, FastDiv divL,
+                                                             uint32_t n_groups, DrawParams dp, ReplicaParams rp) {
+    __shared__ uint32_t tail_thr[6][kReplicas];
+    __shared__ uint32_t tails[kWaves][kBatch * 64];
+    for (uint32_t e = threadIdx.x; e < 6 * kReplicas; e += blockDim.x)
+        tail_thr[e / kReplicas][e % kReplicas] = rp.T24[e / kReplicas][e % kReplicas];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t waves_total = gridDim.x * kWaves;
+    uint32_t* my_tails = tails[wave];
+    for (uint32_t b0 = (blockIdx.x * kWaves + wave) * kBatch; b0 < n_groups; b0 += waves_total * kBatch) {
+        // plane call (lane & 3) of group b0 + (lane >> 2)
+        const U4 pl = philox10_uuuv(dp.stream, dp.t | ((lane & 3u) << 30), dp.tag2, b0 + (lane >> 2), dp.key0,
+                                    dp.key1);
+        // tails of the batch's 1024 sites: quad 16 b0 + 64 e + lane holds sites 4 quad .. 4 quad + 3
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e) {
+            const U4 y = philox10_uuuv(dp.stream, dp.t, dp.tag2 + 1u, 16u * b0 + 64u * e + lane, dp.key0, dp.key1);
+            uint32_t* t4 = my_tails + 4u * (64u * e + lane);
+            t4[0] = y.x0 >> 8;
+            t4[1] = y.x1 >> 8;
+            t4[2] = y.x2 >> 8;
+            t4[3] = y.x3 >> 8;
+        }
+        lds_wave_sync();
+        const uint32_t nb = n_groups - b0 < kBatch ? n_groups - b0 : kBatch;
+        for (uint32_t gi = 0; gi < nb; ++gi) {
+            const uint32_t s = 64u * (b0 + gi) + lane;
+            const uint32_t j = fdiv(s, divL);
+            const uint32_t i = s - j * L;
+            const uint64_t c = src[s];
+            uint64_t n1, n2;
+            if (WHICH == 0) {
+                n1 = src[(j == 0 ? L - 1 : j - 1) * L + i];
+                n2 = src[j * L + (i == 0 ? L - 1 : i - 1)];
+            } else {
+                n1 = src[(j == L - 1 ? 0 : j + 1) * L + i];
+                n2 = src[j * L + (i == L - 1 ? 0 : i + 1)];
+            }
+            uint32_t q0[2], w1[2], q2[2], nl[2], und[2], v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t a = (uint32_t)(n1 >> (32 * h)), b = (uint32_t)(n2 >> (32 * h)),
+                               cc = (uint32_t)(c >> (32 * h));
+                q0[h] = op3<kAllEqual>(a, b, cc);
+                q2[h] = a ^ b;
+                w1[h] = op3<kNor>(q0[h], q2[h], 0u);
+                nl[h] = op3<kMajority>(a, b, cc);
+                und[h] = ~0u;
+                v[h] = 0u;
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const uint32_t from = 4u * gi + (uint32_t)(m >> 1);
+                const uint32_t lo = __builtin_amdgcn_readlane((m & 1) ? pl.x2 : pl.x0, from);
+                const uint32_t hi = __builtin_amdgcn_readlane((m & 1) ? pl.x3 : pl.x1, from);
+                const uint64_t plane = ((uint64_t)hi << 32) | lo;
+                const uint32_t rm = (uint32_t)__builtin_amdgcn_sbfe((uint32_t)(plane >> lane), 0u, 1u);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t S0 = (uint32_t)(rp.S[m][0] >> (32 * h));
+                    const uint32_t S1 = (uint32_t)(rp.S[m][1] >> (32 * h));
+                    const uint32_t S2 = (uint32_t)(rp.S[m][2] >> (32 * h));
+                    const uint32_t tb = op3<kSelect>(q0[h], S0, op3<kSelect>(w1[h], S1, S2));
+                    v[h] = op3<kSelectNot>(und[h], rm, v[h]);
+                    und[h] = op3<kAndNotXor>(und[h], rm ^ nl[h], tb);
+                }
+            }
+            uint64_t lt = ((uint64_t)(v[0] & ~und[0])) | ((uint64_t)(v[1] & ~und[1]) << 32);
+            uint64_t u = (uint64_t)und[0] | ((uint64_t)und[1] << 32);
+            if (u) {
+                const uint32_t t24 = my_tails[64u * gi + lane];
+                while (u) {
+                    const int r = __ffsll((unsigned long long)u) - 1;
+                    u &= u - 1;
+                    const uint32_t idx = 2u * ((uint32_t)((n1 >> r) & 1u) + (uint32_t)((n2 >> r) & 1u)) +
+                                         (uint32_t)((c >> r) & 1u);
+                    if (t24 < tail_thr[idx][r])
+                        lt |= 1ull << r;
+                }
+            }
+            dst[s] = lt;
+        }
+        lds_wave_sync();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_replica_observe(const uint64_t* __restrict__ sig,
+                                                         const uint64_t* __restrict__ tau, uint32_t L, FastDiv divL,
+                                                         int64_t* __restrict__ out) {
+    __shared__ int64_t red[4 * 4];
+    const uint32_t r = blockIdx.x;
+    const uint32_t n = L * L;
+    int64_t v[4] = {0, 0, 0, 0};   // +1 spins, sigma != tau_up, sigma != tau_right, sigma != tau
+    for (uint32_t s = threadIdx.x; s < n; s += blockDim.x) {
+        const uint32_t j = fdiv(s, divL);
+        const uint32_t i = s - j * L;
+        const uint64_t x = sig[s];
+        const uint64_t tu = tau[(j == L - 1 ? 0 : j + 1) * L + i];
+        const uint64_t tr = tau[j * L + (i == L - 1 ? 0 : i + 1)];
+        const uint64_t ts = tau[s];
+        v[0] += (int64_t)((x >> r) & 1u);
+        v[1] += (int64_t)(((x ^ tu) >> r) & 1u);
+        v[2] += (int64_t)(((x ^ tr) >> r) & 1u);
+        v[3] += (int64_t)(((x ^ ts) >> r) & 1u);
+    }
+    block_sum_i64<4>(v, red);
+    if (threadIdx.x == 0) {
+        const int64_t N = (int64_t)n;
+        out[3 * r] = 2 * v[0] - N;
+        out[3 * r + 1] = 2 * N - 2 * (v[1] + v[2]);
+        out[3 * r + 2] = N - 2 * v[3];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_replica_half(int which, const uint64_t* src, uint64_t* dst, uint32_t L, const DrawParams& dp,
+                               const ReplicaParams& rp, hipStream_t st) {
+    const uint32_t n_groups = (uint32_t)(((uint64_t)L * L) / 64u);
+    const uint32_t batches = (n_groups + kBatch - 1) / kBatch;
+    uint32_t blocks = (batches + kWaves - 1) / kWaves;
+    if (blocks > 8192u)
+        blocks = 8192u;
+    const FastDiv divL = make_fastdiv(L);
+    if (which == 0)
+        hipLaunchKernelGGL(k_replica_half<0>, dim3(blocks), dim3(64 * kWaves), 0, st, src, dst, L, divL, n_groups, dp,
+                           rp);
+    else
+        hipLaunchKernelGGL(k_replica_half<1>, dim3(blocks), dim3(64 * kWaves), 0, st, src, dst, L, divL, n_groups, dp,
+                           rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_replica_observe(const uint64_t* sigma, const uint64_t* tau, uint32_t L, int64_t* out,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_replica_observe, dim3(kReplicas), dim3(256), 0, st, sigma, tau, L, make_fastdiv(L), out);
+    return hipGetLastError();
+}
+
+}  // namespace sd

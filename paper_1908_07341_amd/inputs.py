@@ -38,3 +38,19 @@ def scan_table(n_q: int = 64, n_J: int = 64, q_max: float = 2.0, J_max: float = 
     rng = np.random.default_rng(seed)
     L = rng.choice(np.asarray(sizes), size=q.size)
     return q.astype(np.float64), J.astype(np.float64), L.astype(np.int32)
+
+
+def pack_replicas(lattices: np.ndarray) -> np.ndarray:
+    """int8 +-1 lattices [64, L, L] -> replica words [L * L] uint64, bit r of
+    word s = site s of replica r (1 = +1)."""
+    lat = np.asarray(lattices)
+    bits = (lat.reshape(lat.shape[0], -1) > 0).astype(np.uint64)
+    shifts = np.arange(lat.shape[0], dtype=np.uint64)[:, None]
+    return np.bitwise_or.reduce(bits << shifts, axis=0)
+
+
+def unpack_replicas(words: np.ndarray, L: int, n: int = 64) -> np.ndarray:
+    """Replica words [L * L] (any 8-byte dtype view) -> int8 +-1 lattices [n, L, L]."""
+    w = np.ascontiguousarray(words).view(np.uint64).reshape(-1)
+    bits = (w[None, :] >> np.arange(n, dtype=np.uint64)[:, None]) & np.uint64(1)
+    return (2 * bits.astype(np.int8) - 1).reshape(n, L, L)

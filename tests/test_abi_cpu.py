@@ -102,8 +102,17 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_loglik_stats(fake, 1, 3, 64, None, st) == sd.SD_EINVAL
     assert lib.sd_loglik_fwd_stats(None, fake, fake2, st) == sd.SD_EINVAL
     assert lib.sd_loglik_bwd_stats(fake, fake, None, None, st) == sd.SD_EINVAL
-    tu = (ctypes.c_int64 * 4)()
+    Jr = (ctypes.c_double * 64)(*([0.4] * 64))
     far = ctypes.c_void_p(0x100000)
+    assert lib.sd_replica_run(fake, far, 12, Jr, Jr, 1, 0, 0, 2, st) == sd.SD_EINVAL
+    assert lib.sd_replica_run(fake, ctypes.c_void_p(0x10040), 16, Jr, Jr, 1, 0, 0, 2, st) == sd.SD_EINVAL
+    assert b"overlap" in lib.sd_last_error()
+    assert lib.sd_replica_run(fake, far, 16, None, Jr, 1, 0, 0, 2, st) == sd.SD_EINVAL
+    Jr[63] = float("inf")
+    assert lib.sd_replica_run(fake, far, 16, Jr, Jr, 1, 0, 0, 2, st) == sd.SD_EINVAL
+    assert lib.sd_replica_observe(fake, far, 16, None, st) == sd.SD_EINVAL
+    assert sd.sd_replica_lattice_bytes(16) == 16 * 16 * 8 and sd.sd_replica_lattice_bytes(12) == 0
+    tu = (ctypes.c_int64 * 4)()
     assert lib.sd_propp_wilson(fake, far, 4, 12, 0.4, 0.5, 1, 0, 100, 1, 10, tu, st) == sd.SD_EINVAL
     assert lib.sd_propp_wilson(fake, far, 4, 16, -0.4, 0.5, 1, 0, 100, 1, 10, tu, st) == sd.SD_EINVAL
     assert b"monotone" in lib.sd_last_error()

@@ -1,0 +1,78 @@
+"""GPU parity of the replica-coded chains (sd_replica_run): each of the 64
+replicas, sharing seed and stream, equals bit for bit the single chain of its
+own (J, q) run by sd_run from the same start, and replica 0 the oracle; the
+per-replica observables equal sd_observe on the unpacked lattices."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1908_07341_amd as sd
+from paper_1908_07341_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0xABCDEF12345
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.lib()
+
+
+def _params(rng):
+    # a scan-like spread with the degenerate tables (h = 0 classes) included
+    J = rng.uniform(0.0, 1.5, 64)
+    q = rng.uniform(0.0, 2.0, 64)
+    J[:6] = [0.0, 0.0, 0.5, 0.3, -0.4, 2.5]
+    q[:6] = [0.0, 0.8, 1.0, 0.0, 0.6, 3.0]
+    return J, q
+
+
+@pytest.mark.parametrize("L,k", [(8, 5), (16, 7), (40, 3), (64, 4), (128, 2)])
+def test_replicas_equal_single_chains(oracle, L, k):
+    rng = np.random.default_rng(L)
+    J, q = _params(rng)
+    starts = np.stack([inputs.random_lattice(L, 1000 + r) for r in range(64)])
+    words = inputs.pack_replicas(starts)
+    assert np.array_equal(inputs.unpack_replicas(words, L), starts)
+    sig = torch.from_numpy(words.view(np.int64)).cuda()
+    tau = torch.zeros_like(sig)
+    stream, step0 = 5, 3
+    print(f"replicas L={L} k={k}", flush=True)
+    sd.sd_replica_run(sig, tau, L, J, q, SEED, stream, step0, k)
+    torch.cuda.synchronize()
+    got_s = inputs.unpack_replicas(sig.cpu().numpy(), L)
+    got_t = inputs.unpack_replicas(tau.cpu().numpy(), L)
+    obs = torch.empty(192, dtype=torch.int64, device="cuda")
+    sd.sd_replica_observe(sig, tau, L, obs)
+    obs = obs.cpu().numpy().reshape(64, 3)
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    for r in range(64):
+        s1 = sd.new_lattice(L, sd.SD_P64)
+        s1.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(starts[r])))
+        t1 = sd.new_lattice(L, sd.SD_P64)
+        sd.sd_run(s1, t1, L, sd.SD_P64, float(J[r]), float(q[r]), SEED, stream, step0, k, None, 0)
+        o1 = torch.empty(3, dtype=torch.int64, device="cuda")
+        sd.sd_observe(s1, t1, L, sd.SD_P64, o1)
+        torch.cuda.synchronize()
+        assert np.array_equal(inputs.unpack_bits(s1.cpu().numpy(), L), got_s[r]), r
+        assert np.array_equal(inputs.unpack_bits(t1.cpu().numpy(), L), got_t[r]), r
+        assert np.array_equal(o1.cpu().numpy(), obs[r]), r
+    rs, rt, _ = oracle.run(starts[0], J[0], q[0], SEED, stream, step0, k)
+    assert np.array_equal(got_s[0], rs) and np.array_equal(got_t[0], rt)
+
+
+def test_replicas_with_equal_parameters_are_a_monotone_coupling():
+    # 64 copies of one (J, q) from all +1 (even replicas) and all -1 (odd):
+    # shared uniforms keep every top copy above its bottom copy
+    L, J0, q0 = 32, 0.5, 0.6
+    starts = np.stack([np.full((L, L), 1 if r % 2 == 0 else -1, np.int8) for r in range(64)])
+    sig = torch.from_numpy(inputs.pack_replicas(starts).view(np.int64)).cuda()
+    tau = torch.zeros_like(sig)
+    for n in range(0, 40, 8):
+        sd.sd_replica_run(sig, tau, L, [J0] * 64, [q0] * 64, 7, 1, n, 8)
+        got = inputs.unpack_replicas(sig.cpu().numpy(), L)
+        assert np.all(got[0::2] >= got[1::2])
+        assert all(np.array_equal(got[0], got[2 * i]) for i in range(32))
