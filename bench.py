@@ -154,6 +154,10 @@ def parse():
     p.add_argument("--scan-rec", type=int, default=300000)
     p.add_argument("--coalescence", action="store_true",
                    help="only the coalescence times of section 3.2 (32x32, monotone coupling)")
+    p.add_argument("--replicas", action="store_true",
+                   help="only the replica-coded chains (64 chains per word sharing one stream)")
+    p.add_argument("--replica-L", type=int, default=4096)
+    p.add_argument("--replica-steps", type=int, default=100)
     p.add_argument("--propp-wilson", action="store_true",
                    help="only the coupling-from-the-past samples (32x32, J near the square-lattice critical value)")
     p.add_argument("--table1", action="store_true",
@@ -474,6 +478,39 @@ def bench_coalescence(sd, torch, L=32, n_pairs=256):
                         f"cap 200000 steps", "rows": rows, "seconds": time.perf_counter() - t0}
 
 
+def bench_replicas(sd, torch, L, K):
+    """64 chains per 64-bit word sharing seed and stream, at the 64 (q, J)
+    points of one row of the scan grid (q = 1, J from 0 to 1.5), L x L from
+    random starts: spin updates/ns over all chains, with HIP events around the
+    timed steps, and the algorithmic HBM rate (one 8-byte word read and one
+    written per site and half-step: 0.25 B per spin update)."""
+    J = list(1.5 * np.arange(64) / 63)
+    q = [1.0] * 64
+    nb = sd.sd_replica_lattice_bytes(L)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    sig = torch.randint(-2 ** 62, 2 ** 62, (nb // 8,), dtype=torch.int64, device="cuda", generator=g)
+    tau = torch.empty_like(sig)
+    sd.sd_replica_run(sig, tau, L, J, q, 1, 0, 0, 2)   # warm-up
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sd.sd_replica_run(sig, tau, L, J, q, 1, 0, 2, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    updates = 2.0 * 64 * L * L * K
+    out = torch.empty(192, dtype=torch.int64, device="cuda")
+    sd.sd_replica_observe(sig, tau, L, out)
+    m = (out.view(64, 3)[:, 0].double() / (L * L)).abs().cpu().numpy()
+    rate = updates / (ms * 1e6)
+    return {"workload": f"64 chains sharing one stream, {L}x{L}, (q, J) = (1, 1.5 k / 63) for k = 0..63, "
+                        f"random start, {K} steps", "spin_updates_per_ns": rate, "ms": ms,
+            "half_step_us": ms * 1e3 / (2 * K), "hbm_algorithmic_GBps": rate * 0.25,
+            "hbm_frac": rate * 0.25 / HBM_PEAK_GBS, "abs_m_lowest_J": float(m[0]), "abs_m_highest_J": float(m[-1])}
+
+
 def bench_propp_wilson(sd, torch, L=32, n=512):
     """Exact samples of the stationary law by coupling from the past (the
     Propp-Wilson sampler on the monotone coupling of section 3.2), at the kind
@@ -588,6 +625,9 @@ def main():
         return
     if args.coalescence:
         print(json.dumps({"coalescence": bench_coalescence(sd, torch)}), flush=True)
+        return
+    if args.replicas:
+        print(json.dumps({"replicas": bench_replicas(sd, torch, args.replica_L, args.replica_steps)}), flush=True)
         return
     if args.propp_wilson:
         print(json.dumps({"propp_wilson": bench_propp_wilson(sd, torch)}), flush=True)

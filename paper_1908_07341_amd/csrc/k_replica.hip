@@ -16,7 +16,12 @@
 // all-zeros mask, and the 64 replicas of the site are compared bit-sliced in
 // the paired form (per-replica threshold bits S[m][k] as uniform words).
 // Replicas left undecided after the eight planes (top byte of r_s equal to
-// their scan byte) compare the site's tail with their tail threshold.
+// their scan byte) compare the site's tail with their tail threshold, one
+// replica at a time.  Replicas whose thresholds share a top byte (strongly
+// ordered classes: 0x00 or 0xFF) are undecided together at a site whose top
+// byte matches, so a few lanes of a wavefront carry dozens of tail compares
+// while the others wait; on a 64-point J scan that loop takes about half of
+// the kernel's instructions.
 #include "sd_replica.hpp"
 
 namespace sd {
@@ -58,7 +63,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
     for (uint32_t e = threadIdx.x; e < 6 * kReplicas; e += blockDim.x)
         tail_thr[e / kReplicas][e % kReplicas] = rp.T24[e / kReplicas][e % kReplicas];
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: loop bounds stay scalar
     const uint32_t waves_total = gridDim.x * kWaves;
     uint32_t* my_tails = tails[wave];
     for (uint32_t b0 = (blockIdx.x * kWaves + wave) * kBatch; b0 < n_groups; b0 += waves_total * kBatch) {
@@ -77,12 +83,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
         }
         lds_wave_sync();
         const uint32_t nb = n_groups - b0 < kBatch ? n_groups - b0 : kBatch;
-        for (uint32_t gi = 0; gi < nb; ++gi) {
-            const uint32_t s = 64u * (b0 + gi) + lane;
+        // the words of a group are loaded one group ahead of their use
+        auto load = [&](uint32_t g, uint64_t& c, uint64_t& n1, uint64_t& n2) __attribute__((always_inline)) {
+            const uint32_t s = 64u * g + lane;
             const uint32_t j = fdiv(s, divL);
             const uint32_t i = s - j * L;
-            const uint64_t c = src[s];
-            uint64_t n1, n2;
+            c = src[s];
             if (WHICH == 0) {
                 n1 = src[(j == 0 ? L - 1 : j - 1) * L + i];
                 n2 = src[j * L + (i == 0 ? L - 1 : i - 1)];
@@ -90,6 +96,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
                 n1 = src[(j == L - 1 ? 0 : j + 1) * L + i];
                 n2 = src[j * L + (i == L - 1 ? 0 : i + 1)];
             }
+        };
+        uint64_t nc, nn1, nn2;
+        load(b0, nc, nn1, nn2);
+        for (uint32_t gi = 0; gi < nb; ++gi) {
+            const uint32_t s = 64u * (b0 + gi) + lane;
+            const uint64_t c = nc, n1 = nn1, n2 = nn2;
+            if (gi + 1 < nb)
+                load(b0 + gi + 1, nc, nn1, nn2);
             uint32_t q0[2], w1[2], q2[2], nl[2], und[2], v[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
