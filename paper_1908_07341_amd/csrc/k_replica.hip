@@ -152,14 +152,18 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
     }
 }
 
+// Block (r, y) sums replica r's (M, A, B) over sites y * chunk .. and adds
+// them to out[3 r ...] (zeroed before the launch).
 __global__ __launch_bounds__(256) void k_replica_observe(const uint64_t* __restrict__ sig,
                                                          const uint64_t* __restrict__ tau, uint32_t L, FastDiv divL,
-                                                         int64_t* __restrict__ out) {
+                                                         uint32_t chunk, int64_t* __restrict__ out) {
     __shared__ int64_t red[4 * 4];
     const uint32_t r = blockIdx.x;
     const uint32_t n = L * L;
+    const uint32_t s0 = blockIdx.y * chunk;
+    const uint32_t s1 = s0 + chunk < n ? s0 + chunk : n;
     int64_t v[4] = {0, 0, 0, 0};   // +1 spins, sigma != tau_up, sigma != tau_right, sigma != tau
-    for (uint32_t s = threadIdx.x; s < n; s += blockDim.x) {
+    for (uint32_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
         const uint32_t j = fdiv(s, divL);
         const uint32_t i = s - j * L;
         const uint64_t x = sig[s];
@@ -172,11 +176,12 @@ __global__ __launch_bounds__(256) void k_replica_observe(const uint64_t* __restr
         v[3] += (int64_t)(((x ^ ts) >> r) & 1u);
     }
     block_sum_i64<4>(v, red);
-    if (threadIdx.x == 0) {
-        const int64_t N = (int64_t)n;
-        out[3 * r] = 2 * v[0] - N;
-        out[3 * r + 1] = 2 * N - 2 * (v[1] + v[2]);
-        out[3 * r + 2] = N - 2 * v[3];
+    if (threadIdx.x == 0 && s1 > s0) {
+        const int64_t N = (int64_t)(s1 - s0);
+        unsigned long long* o = reinterpret_cast<unsigned long long*>(out + 3 * r);
+        atomicAdd(o, (unsigned long long)(2 * v[0] - N));
+        atomicAdd(o + 1, (unsigned long long)(2 * N - 2 * (v[1] + v[2])));
+        atomicAdd(o + 2, (unsigned long long)(N - 2 * v[3]));
     }
 }
 
@@ -201,7 +206,14 @@ hipError_t launch_replica_half(int which, const uint64_t* src, uint64_t* dst, ui
 
 hipError_t launch_replica_observe(const uint64_t* sigma, const uint64_t* tau, uint32_t L, int64_t* out,
                                   hipStream_t st) {
-    hipLaunchKernelGGL(k_replica_observe, dim3(kReplicas), dim3(256), 0, st, sigma, tau, L, make_fastdiv(L), out);
+    hipError_t e = launch_fill_i64(out, 3 * kReplicas, 0, st);
+    if (e != hipSuccess)
+        return e;
+    const uint32_t n = L * L;
+    const uint32_t chunk = 65536u;
+    const uint32_t slices = (n + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_replica_observe, dim3(kReplicas, slices), dim3(256), 0, st, sigma, tau, L, make_fastdiv(L),
+                       chunk, out);
     return hipGetLastError();
 }
 
