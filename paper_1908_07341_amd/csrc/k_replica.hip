@@ -16,12 +16,11 @@
 // all-zeros mask, and the 64 replicas of the site are compared bit-sliced in
 // the paired form (per-replica threshold bits S[m][k] as uniform words).
 // Replicas left undecided after the eight planes (top byte of r_s equal to
-// their scan byte) compare the site's tail with their tail threshold, one
-// replica at a time.  Replicas whose thresholds share a top byte (strongly
-// ordered classes: 0x00 or 0xFF) are undecided together at a site whose top
-// byte matches, so a few lanes of a wavefront carry dozens of tail compares
-// while the others wait; on a 64-point J scan that loop takes about half of
-// the kernel's instructions.
+// their scan byte) compare the site's tail with their tail threshold.
+// Replicas whose thresholds share a top byte (strongly ordered classes: 0x00
+// or 0xFF) are undecided together at a site whose top byte matches; such a
+// site is resolved by the whole wavefront, one replica per lane, the others
+// (at most two undecided replicas) in their own lane.
 #include "sd_replica.hpp"
 
 namespace sd {
@@ -53,6 +52,14 @@ __device__ __forceinline__ void lds_wave_sync() {
 }
 
 constexpr uint32_t kWaves = 4;   // wavefronts per workgroup
+
+// Lane h's 64-bit value (h wavefront-uniform).  The builtin returns a signed
+// 32-bit value: each half is taken as unsigned before widening.
+__device__ __forceinline__ uint64_t lane_word(uint64_t x, uint32_t h) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)x, h);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(x >> 32), h);
+    return ((uint64_t)hi << 32) | lo;
+}
 
 template <int WHICH>
 __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __restrict__ src,
@@ -119,8 +126,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const uint32_t from = 4u * gi + (uint32_t)(m >> 1);
-                const uint32_t lo = __builtin_amdgcn_readlane((m & 1) ? pl.x2 : pl.x0, from);
-                const uint32_t hi = __builtin_amdgcn_readlane((m & 1) ? pl.x3 : pl.x1, from);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((m & 1) ? pl.x2 : pl.x0, from);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((m & 1) ? pl.x3 : pl.x1, from);
                 const uint64_t plane = ((uint64_t)hi << 32) | lo;
                 const uint32_t rm = (uint32_t)__builtin_amdgcn_sbfe((uint32_t)(plane >> lane), 0u, 1u);
 #pragma unroll
@@ -135,9 +142,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
             }
             uint64_t lt = ((uint64_t)(v[0] & ~und[0])) | ((uint64_t)(v[1] & ~und[1]) << 32);
             uint64_t u = (uint64_t)und[0] | ((uint64_t)und[1] << 32);
-            if (u) {
-                const uint32_t t24 = my_tails[64u * gi + lane];
-                while (u) {
+            const uint32_t t24 = my_tails[64u * gi + lane];
+            // Sites with at most kFewTails undecided chains resolve them in
+            // their own lane; a site with more (chains whose thresholds share
+            // the site's top byte) is resolved by the whole wavefront, one
+            // chain per lane, so that one lane's many compares do not hold up
+            // the others.
+            constexpr int kFewTails = 3;
+            const bool many = __popcll(u) > kFewTails;
+#pragma unroll
+            for (int it = 0; it < kFewTails; ++it) {
+                if (!many && u) {
                     const int r = __ffsll((unsigned long long)u) - 1;
                     u &= u - 1;
                     const uint32_t idx = 2u * ((uint32_t)((n1 >> r) & 1u) + (uint32_t)((n2 >> r) & 1u)) +
@@ -145,6 +160,21 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
                     if (t24 < tail_thr[idx][r])
                         lt |= 1ull << r;
                 }
+            }
+            uint64_t heavy = __ballot(many);
+            while (heavy) {   // wavefront-uniform
+                const uint32_t h = (uint32_t)__ffsll((unsigned long long)heavy) - 1u;
+                heavy &= heavy - 1;
+                const uint64_t uh = lane_word(u, h), ch = lane_word(c, h), ah = lane_word(n1, h),
+                               bh = lane_word(n2, h);
+                const uint32_t th = (uint32_t)__builtin_amdgcn_readlane(t24, h);
+                // lane l decides chain l of site h
+                const uint32_t idx = 2u * ((uint32_t)((ah >> lane) & 1u) + (uint32_t)((bh >> lane) & 1u)) +
+                                     (uint32_t)((ch >> lane) & 1u);
+                const bool plus = ((uh >> lane) & 1u) && th < tail_thr[idx][lane];
+                const uint64_t res = __ballot(plus);
+                if (lane == h)
+                    lt |= res;
             }
             dst[s] = lt;
         }
