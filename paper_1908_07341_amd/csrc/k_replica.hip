@@ -11,9 +11,9 @@
 // A wavefront takes batches of 16 groups (1024 sites).  Its 64 lanes first
 // evaluate the batch's 64 plane calls (lane 4 g + p: call p of group g) and its
 // 256 tail calls (four evaluations, tails kept in LDS), then walk the groups
-// one lane per site: the plane words of the group are read from the lane that
-// drew them (v_readlane), each lane takes its site's bit as an all-ones or
-// all-zeros mask, and the 64 replicas of the site are compared bit-sliced in
+// one lane per site: the plane words of the group are read from LDS, where
+// the lanes that drew them left them, each lane takes its site's bit as an
+// all-ones or all-zeros mask, and the 64 replicas of the site are compared bit-sliced in
 // the paired form (per-replica threshold bits S[m][k] as uniform words).
 // Replicas left undecided after the eight planes (top byte of r_s equal to
 // their scan byte) compare the site's tail with their tail threshold.
@@ -67,6 +67,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
                                                              uint32_t n_groups, DrawParams dp, ReplicaParams rp) {
     __shared__ uint32_t tail_thr[6][kReplicas];
     __shared__ uint32_t tails[kWaves][kBatch * 64];
+    __shared__ uint32_t planes[kWaves][64][4];   // lane 4 g + p: the four words of plane call p of group g
     for (uint32_t e = threadIdx.x; e < 6 * kReplicas; e += blockDim.x)
         tail_thr[e / kReplicas][e % kReplicas] = rp.T24[e / kReplicas][e % kReplicas];
     __syncthreads();
@@ -76,8 +77,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
     uint32_t* my_tails = tails[wave];
     for (uint32_t b0 = (blockIdx.x * kWaves + wave) * kBatch; b0 < n_groups; b0 += waves_total * kBatch) {
         // plane call (lane & 3) of group b0 + (lane >> 2)
-        const U4 pl = philox10_uuuv(dp.stream, dp.t | ((lane & 3u) << 30), dp.tag2, b0 + (lane >> 2), dp.key0,
-                                    dp.key1);
+        {
+            const U4 pl = philox10_uuuv(dp.stream, dp.t | ((lane & 3u) << 30), dp.tag2, b0 + (lane >> 2), dp.key0,
+                                        dp.key1);
+            planes[wave][lane][0] = pl.x0;
+            planes[wave][lane][1] = pl.x1;
+            planes[wave][lane][2] = pl.x2;
+            planes[wave][lane][3] = pl.x3;
+        }
         // tails of the batch's 1024 sites: quad 16 b0 + 64 e + lane holds sites 4 quad .. 4 quad + 3
 #pragma unroll
         for (uint32_t e = 0; e < 4; ++e) {
@@ -123,13 +130,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
                 und[h] = ~0u;
                 v[h] = 0u;
             }
+            // plane m of this group: word (m & 1) * 2 + (lane >= 32) of call m / 2;
+            // this lane's site is its bit lane % 32
+            const uint32_t* pg = &planes[wave][4u * gi][lane >> 5];
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
-                const uint32_t from = 4u * gi + (uint32_t)(m >> 1);
-                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((m & 1) ? pl.x2 : pl.x0, from);
-                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((m & 1) ? pl.x3 : pl.x1, from);
-                const uint64_t plane = ((uint64_t)hi << 32) | lo;
-                const uint32_t rm = (uint32_t)__builtin_amdgcn_sbfe((uint32_t)(plane >> lane), 0u, 1u);
+                const uint32_t word = pg[4 * (m >> 1) + 2 * (m & 1)];
+                const uint32_t rm = (uint32_t)__builtin_amdgcn_sbfe(word, lane & 31u, 1u);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const uint32_t S0 = (uint32_t)(rp.S[m][0] >> (32 * h));
