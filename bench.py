@@ -37,7 +37,7 @@ METRIC = "spin updates/ns (1 GPU, L=16384 packed) + batched-scan chain-steps/s v
 # 2.4 GHz issue 39.32e12 32-bit VALU lane operations per second.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
-# Algorithmic VALU operations per spin update of the half-step (see DESIGN.md):
+# Algorithmic VALU operations per spin update of the half-step:
 # Philox4x32-10 work of the stream contract, 4 calls per 64 sites plus one tail
 # call per undecided site (1/256 of them), 10 rounds of 2 multiplies + 2
 # three-way XORs each, and the bit-sliced comparison, 8 planes x (1 select +
@@ -610,8 +610,9 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the shaken-dynamics path here is "
-                                   "built and measured for a single MI355X (see DESIGN.md for how it would "
-                                   "shard)", "n_gpus": args.gpus}))
+                                   "built and measured for a single MI355X (a chain would shard by row bands "
+                                   "with one halo row exchanged per half-step, batched chains and "
+                                   "trajectories by whole chains)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
