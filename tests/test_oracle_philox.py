@@ -1,8 +1,8 @@
 """Pins of the oracle's random stream.
 
-* The Philox4x32-10 bijection against the published known-answer vectors and
-  against rocRAND's independently written engine (a second implementation of
-  the SC'11 generator, called through its public header).
+* The Philox4x32-10 bijection against rocRAND's independently written engine
+  (a second implementation of the SC'11 generator, called through its public
+  header), on random and on extreme counters and keys.
 * The per-site uniform against the stream contract, rebuilt here from raw
   Philox outputs, and a coarse uniformity check.
 """
@@ -14,24 +14,6 @@ import numpy as np
 import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def _kat_rows():
-    rows = []
-    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            v = [int(x, 16) for x in line.split()]
-            rows.append((v[0:4], v[4:6], v[6:10]))
-    return rows
-
-
-def test_philox_known_answers(oracle):
-    rows = _kat_rows()
-    assert len(rows) == 3
-    for ctr, key, expected in rows:
-        assert list(oracle.philox4x32_10(ctr, key)) == expected
 
 
 @pytest.fixture(scope="module")
@@ -58,6 +40,9 @@ def test_philox_matches_rocrand(oracle, rocrand_bijection):
     # include counters shaped like the stream contract's (small words, top bits set)
     rows[:8, 0] = np.arange(8)
     rows[:8, 1] = (np.arange(8) % 4) << 30
+    rows[8] = 0                    # all-zero counter and key
+    rows[9] = 0xFFFFFFFF           # all-one counter and key
+    rows[10, 4:6] = 0              # zero key, random counter
     ref = rocrand_bijection(rows.tolist())
     for r, expected in zip(rows, ref):
         got = oracle.philox4x32_10(r[:4], r[4:6])
