@@ -13,8 +13,14 @@ Also reported on the same JSON line:
                   5000 steps, (M, A, B) every step: one hipGraph launch vs the
                   same chains run one sd_run each (timed on a sample)
   loglik        - 256 trajectories of 256^2 lattices, 2000 steps at
-                  (J, q) = (0.45, 0.7): count kernel bandwidth and FP32
-                  gradient error against FP64
+                  (J, q) = (0.45, 0.7): bandwidth of the 12-count and the
+                  paired-statistics kernels, FP32 gradient error against FP64
+                  and the gradient ascent from (0.2, 0.2)
+  replicas      - 64 chains sharing one stream, one bit each, on 4096^2 at
+                  (q, J) = (1, 1.5 k / 63): spin updates/ns over the chains
+
+Other modes (one JSON object each): --critical-scan, --coalescence,
+--propp-wilson, --table1, --replicas, --traffic-from.
 """
 from __future__ import annotations
 
@@ -140,6 +146,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-scan leg")
     p.add_argument("--no-loglik", action="store_true", help="skip the log-likelihood leg")
+    p.add_argument("--no-replicas", action="store_true", help="skip the replica-coded chains leg")
     p.add_argument("--batch-steps", type=int, default=5000)
     p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
     p.add_argument("--cpu-steps", type=int, default=2)
@@ -680,6 +687,10 @@ def main():
         log("[bench] log-likelihood")
         out["loglik"] = bench_loglik(sd, torch)
         log(f"[bench] counts {out['loglik']['counts_GBps']:.0f} GB/s, paired stats {out['loglik']['stats_GBps']:.0f} GB/s")
+    if not args.no_replicas:
+        log("[bench] replica-coded chains")
+        out["replicas"] = bench_replicas(sd, torch, args.replica_L, args.replica_steps)
+        log(f"[bench] replicas {out['replicas']['spin_updates_per_ns']:.0f} spin updates/ns over 64 chains")
     if not args.no_cpu:
         log(f"[bench] CPU oracle, {args.cpu_steps} step(s) at L={L}")
         out["cpu_baseline"] = bench_cpu(L, args.cpu_steps)
