@@ -52,10 +52,19 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 struct U4 { uint32_t x0, x1, x2, x3; };
 
+// The full 64-bit product a * m in one v_mad_u64_u32.  Left to itself the
+// compiler splits some of the last round's products into v_mul_hi_u32 and
+// v_mul_lo_u32, two instructions for one product.
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t m) {
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "s"(m));
+    return r;
+}
+
 // One Philox round whose counter words are all lane-varying.
 __device__ __forceinline__ U4 philox_round(U4 c, uint32_t k0, uint32_t k1) {
-    uint64_t p0 = (uint64_t)kPhiloxM0 * c.x0;
-    uint64_t p1 = (uint64_t)kPhiloxM1 * c.x2;
+    uint64_t p0 = mul_wide(c.x0, kPhiloxM0);
+    uint64_t p1 = mul_wide(c.x2, kPhiloxM1);
     U4 n;
     n.x0 = xor3(hi32(p1), c.x1, k0);
     n.x1 = lo32(p1);
