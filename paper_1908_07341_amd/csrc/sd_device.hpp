@@ -235,7 +235,8 @@ __host__ __device__ inline uint32_t paired_tail(const uint32_t T[6], int idx) {
 // that word is one of eight per-site candidates, picked by the 3-bit plane code.
 // The scan keeps und (top bits equal so far) and v, the complement of r at the
 // last plane where the site was still undecided: for a decided site that is
-// the first differing plane, where r < T iff r's bit is 0.
+// the first differing plane, where r < T iff r's bit is 0.  Each plane costs
+// the pick and two three-input ops.
 // General form: the union of the class masks whose threshold bit is set.
 struct HalfWord {
     uint32_t lt, und;
@@ -270,6 +271,16 @@ struct WordDraw {
 
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
+// Truth tables of V_BITOP3_B32 from the operand patterns a = 0xF0, b = 0xCC,
+// c = 0xAA.  kScanV(und, r, v): ~r where und, else v; kScanUnd(r, tb, und):
+// und where r equals tb.  The C forms compare the complemented stream ~r.
+constexpr uint32_t kBopA = 0xF0u, kBopB = 0xCCu, kBopC = 0xAAu;
+constexpr uint32_t kScanV = ((kBopA & ~kBopB) | (~kBopA & kBopC)) & 0xFFu;
+constexpr uint32_t kScanVC = ((kBopA & kBopB) | (~kBopA & kBopC)) & 0xFFu;
+constexpr uint32_t kScanUnd = (~(kBopA ^ kBopB) & kBopC) & 0xFFu;
+constexpr uint32_t kScanUndC = ((kBopA ^ kBopB) & kBopC) & 0xFFu;
+static_assert(kScanV == 0x3Au && kScanVC == 0xCAu && kScanUnd == 0x82u && kScanUndC == 0x28u, "scan tables");
+
 // Paired form on a 64-site word.  The candidates of both 32-bit halves sit in
 // one 16-entry vector so that the uniform pick is an indexed VGPR move.
 template <bool COMPLEMENT>
@@ -301,9 +312,9 @@ __device__ __forceinline__ WordDraw compare_planes_paired(const uint64_t P[8], u
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t tb = cand[idx + 8u * h];
-            const uint32_t r = (uint32_t)((COMPLEMENT ? ~P[m] : P[m]) >> (32 * h));
-            v[h] = (und[h] & ~r) | (~und[h] & v[h]);
-            und[h] &= ~(r ^ tb);
+            const uint32_t r = (uint32_t)(P[m] >> (32 * h));
+            v[h] = __builtin_amdgcn_bitop3_b32(und[h], r, v[h], COMPLEMENT ? kScanVC : kScanV);
+            und[h] = __builtin_amdgcn_bitop3_b32(r, tb, und[h], COMPLEMENT ? kScanUndC : kScanUnd);
         }
     }
     const uint64_t u = (uint64_t)und[0] | ((uint64_t)und[1] << 32);
