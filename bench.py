@@ -7,8 +7,8 @@ W untimed warm-up steps are followed by exactly K timed steps.
 
 Also reported on the same JSON line:
   roofline      - the half-step kernel against the VALU peak it is bound by
-  cpu_baseline  - the CPU oracle (single thread) on a bounded sample of the
-                  same workload
+  cpu_baseline  - the CPU oracle on a bounded sample of the same workload: one
+                  thread, and (all_cores) one chain per host core at once
   batched_scan  - 4096 chains, (q, J) on a 64 x 64 grid, L in {128, 256, 512},
                   5000 steps, (M, A, B) every step: one hipGraph launch vs the
                   same chains run one sd_run each (timed on a sample)
@@ -218,7 +218,26 @@ def bench_cpu(L, n_steps):
     ups = 2.0 * L * L * n_steps / dt
     return {"value": ups / 1e9, "unit": "spin updates/ns", "cores": 1, "kind": "oracle",
             "sample": f"{n_steps} full step(s) of the {L}x{L} chain (J=q=0.5, random start) on one host core "
-                      f"in {dt:.1f} s", "seconds": dt}
+                      f"in {dt:.1f} s", "seconds": dt, "all_cores": bench_cpu_all_cores(L, n_steps)}
+
+
+def bench_cpu_all_cores(L, n_steps, max_cores=16):
+    """The same oracle step on every host core at once: independent chains
+    (streams 0..n-1), one per thread; the oracle's C loop runs without the
+    interpreter lock, so the threads run in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as orc
+    n = max(1, min(len(os.sched_getaffinity(0)), max_cores))
+    starts = [orc.init(L, orc.INIT_RANDOM, 0.5, 1, a) for a in range(n)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        list(ex.map(lambda a: orc.run(starts[a], 0.5, 0.5, 1, a, 0, n_steps)[2], range(n)))
+    dt = time.perf_counter() - t0
+    del starts
+    ups = 2.0 * L * L * n_steps * n / dt
+    return {"value": ups / 1e9, "unit": "spin updates/ns", "cores": n,
+            "sample": f"{n} independent {L}x{L} chains (streams 0..{n - 1}), {n_steps} full step(s) each, "
+                      f"one thread per core, in {dt:.1f} s"}
 
 
 def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
