@@ -9,6 +9,8 @@ Also reported on the same JSON line:
   roofline      - the half-step kernel against the VALU peak it is bound by
   cpu_baseline  - the CPU oracle on a bounded sample of the same workload: one
                   thread, and (all_cores) one chain per host core at once
+  int8_sweep    - 1024^2 int8 lattices at q = J in {0.2, ..., 1.0}, 10^4 steps
+                  each, (M, A, B) every step, D(r <= 512) every 100 steps
   batched_scan  - 4096 chains, (q, J) on a 64 x 64 grid, L in {128, 256, 512},
                   5000 steps, (M, A, B) every step: one hipGraph launch vs the
                   same chains run one sd_run each (timed on a sample)
@@ -147,6 +149,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the batched-scan leg")
     p.add_argument("--no-loglik", action="store_true", help="skip the log-likelihood leg")
     p.add_argument("--no-replicas", action="store_true", help="skip the replica-coded chains leg")
+    p.add_argument("--no-c2", action="store_true", help="skip the 1024^2 int8 sweep leg")
     p.add_argument("--batch-steps", type=int, default=5000)
     p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
     p.add_argument("--cpu-steps", type=int, default=2)
@@ -172,6 +175,56 @@ def parse():
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="write the half-step traffic record from two rocprofv3 counter CSVs and exit")
     return p.parse_args()
+
+
+def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=512):
+    """The five-point q = J sweep on 1024^2 int8 lattices: random start, 10^4
+    steps per point with (M, A, B) every step and D(r <= 512) every 100 steps,
+    stream = point index.  A 1024^2 half-step is a few microseconds of kernel
+    time, so one chain is bound by launches; the points are independent and
+    run on a stream each, and also one after another on a single stream."""
+    sd.sd_tune(L, sd.SD_I8, tune_cache)
+    points = [0.2, 0.4, 0.6, 0.8, 1.0]
+    n_blk = n_steps // corr_every
+    lat = [(sd.new_lattice(L, sd.SD_I8), sd.new_lattice(L, sd.SD_I8)) for _ in points]
+    obs = torch.empty((len(points), n_steps, 3), dtype=torch.int64, device="cuda")
+    D = torch.empty((len(points), n_blk, rmax + 1), dtype=torch.int64, device="cuda")
+    cur = torch.cuda.current_stream()
+    side = [torch.cuda.Stream() for _ in points]
+
+    def sweep(streams):
+        for a, (sigma, _) in enumerate(lat):
+            sd.sd_init(sigma, L, sd.SD_I8, sd.SD_INIT_RANDOM, 0.5, 1, a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for st in set(streams):
+            st.wait_stream(cur)
+        for blk in range(n_blk):
+            for a, (qj, (sigma, tau)) in enumerate(zip(points, lat)):
+                sd.sd_run(sigma, tau, L, sd.SD_I8, qj, qj, 1, a, corr_every * blk, corr_every,
+                          obs[a, corr_every * blk:corr_every * (blk + 1)], 1, hip_stream=streams[a])
+                sd.sd_corr_row(sigma, L, sd.SD_I8, rmax, D[a, blk], hip_stream=streams[a])
+        for st in set(streams):
+            cur.wait_stream(st)
+        e1.record(cur)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    sweep([cur] * len(points))   # warm-up: first launches of every kernel and stream
+    ms_one = sweep([cur] * len(points))
+    ms = sweep(side)
+    updates = 2.0 * L * L * n_steps * len(points)
+    m_last = (obs[:, -1000:, 0].double().abs().mean(dim=1) / (L * L)).cpu().numpy()
+    c1 = (D[:, -20:, 1].double().mean(dim=1) / (L * L)).cpu().numpy()
+    return {"workload": f"{L}x{L} int8, q = J in {points}, random start, {n_steps} steps per point, "
+                        f"(M, A, B) every step, D(r <= {rmax}) every {corr_every} steps",
+            "spin_updates_per_ns": updates / (ms * 1e6), "seconds": ms / 1e3, "streams": len(points),
+            "spin_updates_per_ns_one_stream": updates / (ms_one * 1e6),
+            "D0_equals_L2": bool((D[:, :, 0] == L * L).all().item()),
+            "abs_m_last_1000": [round(float(x), 4) for x in m_last],
+            "C1_row_last_20": [round(float(x), 4) for x in c1],
+            "run_choice": list(sd.sd_tuned_choice(L, sd.SD_I8))}
 
 
 def bench_single(sd, torch, L, K, W):
@@ -697,9 +750,15 @@ def main():
                      "hbm_frac": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "m_final": r["m_final"],
     }
+    if not args.no_c2:
+        log("[bench] 1024^2 int8 sweep")
+        out["int8_sweep"] = bench_c2(sd, torch, args.tune_cache)
+        log(f"[bench] sweep {out['int8_sweep']['spin_updates_per_ns']:.0f} spin updates/ns")
     if not args.no_batch:
         log(f"[bench] batched scan, {args.batch_steps} steps")
         out["batched_scan"] = bench_batched(sd, torch, inputs, args.batch_steps, args.plain_sample, args.tune_cache)
+        # how close the three concurrent buckets come to the single large chain, per spin update
+        out["batched_scan"]["rate_vs_single_chain"] = out["batched_scan"]["spin_updates_per_ns"] / value
         log(f"[bench] batched {out['batched_scan']['chain_steps_per_s']:.3g} chain-steps/s, "
             f"x{out['batched_scan']['speedup_vs_plain']:.1f} vs plain")
     if not args.no_loglik:

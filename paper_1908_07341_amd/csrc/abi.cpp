@@ -328,10 +328,13 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     int64_t* partials = n_rec ? partials_workspace(st) : nullptr;
     if (n_rec)
         e = launch_fill_i64(obs, (size_t)n_rec * 3u, 0, st);
+    // the table and keys once; only the time index changes from step to step
+    const DrawParams base = dynamics_params(J, q, seed, stream, 0u, flags & SD_FLAG_COMPLEMENT_RNG);
+    const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
-        DrawParams dp = dynamics_params(J, q, seed, stream, (uint32_t)(2 * n), flags & SD_FLAG_COMPLEMENT_RNG);
-        const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
+        DrawParams dp = base;
+        dp.t = (uint32_t)(2 * n);
         e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks, nullptr, general);
         if (e != hipSuccess)
             break;
