@@ -331,6 +331,13 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
     // the table and keys once; only the time index changes from step to step
     const DrawParams base = dynamics_params(J, q, seed, stream, 0u, flags & SD_FLAG_COMPLEMENT_RNG);
     const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
+    // Each record's workgroup sums go to a slot of their own in the partials
+    // workspace; one finishing launch adds a whole chunk of records, so that
+    // frequent records cost no third launch per step.
+    const uint32_t blocks = half_step_blocks(klay, G, !general && thresholds_paired(base.T), ch.blocks);
+    const uint32_t stride = 4u * blocks;
+    const uint32_t chunk = (uint32_t)(kPartialsWords / stride);
+    uint32_t pending = 0;   // records whose sums wait in the workspace
     for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
         DrawParams dp = base;
@@ -339,10 +346,22 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
         if (e != hipSuccess)
             break;
         dp.t = (uint32_t)(2 * n + 1);
-        int64_t* rec = nullptr;
-        if (n_rec && (m + 1) % obs_every == 0)
-            rec = obs + 3u * (size_t)((m + 1) / obs_every - 1);
-        e = launch_half_step(klay, 1, tau, sigma, G, dp, rec, st, ch.blocks, partials, general);
+        if (n_rec && (m + 1) % obs_every == 0 && !partials) {
+            // no workspace (first use under stream capture): atomics into the record
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)((m + 1) / obs_every - 1), st,
+                                 ch.blocks, nullptr, general);
+        } else if (n_rec && (m + 1) % obs_every == 0) {
+            const uint32_t r = (m + 1) / obs_every - 1;
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)r, st, ch.blocks,
+                                 partials + (size_t)pending * stride, general, false);
+            ++pending;
+            if (e == hipSuccess && (pending == chunk || r + 1 == n_rec)) {
+                e = launch_obs_finish(partials, blocks, pending, stride, obs + 3u * (size_t)(r + 1 - pending), st);
+                pending = 0;
+            }
+        } else {
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, nullptr, st, ch.blocks, nullptr, general);
+        }
     }
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
 }

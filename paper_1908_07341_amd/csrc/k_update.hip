@@ -456,21 +456,25 @@ __global__ __launch_bounds__(256) void k_init_const(void* __restrict__ dst, Geom
     }
 }
 
-// Sums the per-workgroup partials of an observables launch into obs (M, A, B).
+// Sums the per-workgroup partials of observables launches into records of
+// obs (M, A, B): workgroup r adds the n_blocks partials at partials + r * stride
+// into record r.
 __global__ __launch_bounds__(1024) void k_obs_finish(const int64_t* __restrict__ partials, uint32_t n_blocks,
-                                                     int64_t* __restrict__ obs) {
+                                                     uint32_t stride, int64_t* __restrict__ obs) {
     __shared__ int64_t red[4 * 16];
+    const int64_t* p = partials + (size_t)blockIdx.x * stride;
+    int64_t* o = obs + 3u * blockIdx.x;
     int64_t v[4] = {0, 0, 0, 0};
     for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            v[i] += partials[4u * b + i];
+            v[i] += p[4u * b + i];
     block_sum_i64<4>(v, red);
     if (threadIdx.x == 0) {
         const int64_t n = v[3];
-        obs[0] += 2 * v[0] - n;
-        obs[1] += 2 * n - 2 * v[1];
-        obs[2] += n - 2 * v[2];
+        o[0] += 2 * v[0] - n;
+        o[1] += 2 * n - 2 * v[1];
+        o[2] += n - 2 * v[2];
     }
 }
 
@@ -509,12 +513,22 @@ void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, 
                            partials);
 }
 
+uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_blocks) {
+    const uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
+    return (max_blocks && blocks > max_blocks) ? max_blocks : blocks;
+}
+
+hipError_t launch_obs_finish(const int64_t* partials, uint32_t n_blocks, uint32_t n_rec, uint32_t stride,
+                             int64_t* obs, hipStream_t st) {
+    hipLaunchKernelGGL(k_obs_finish, dim3(n_rec), dim3(1024), 0, st, partials, n_blocks, stride, obs);
+    return hipGetLastError();
+}
+
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
-                            int64_t* obs, hipStream_t st, uint32_t max_blocks, int64_t* partials, bool general) {
+                            int64_t* obs, hipStream_t st, uint32_t max_blocks, int64_t* partials, bool general,
+                            bool finish) {
     const bool paired = !general && thresholds_paired(dp.T);
-    uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
-    if (max_blocks && blocks > max_blocks)
-        blocks = max_blocks;
+    const uint32_t blocks = half_step_blocks(layout, G, paired, max_blocks);
     const dim3 grid(blocks), block(256);
     const bool complement = dp.rng_xor != 0;
 #define SD_HALF(LAY)                                                                                       \
@@ -539,8 +553,8 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
             return hipErrorInvalidValue;
     }
 #undef SD_HALF
-    if (which == 1 && obs != nullptr && partials != nullptr)
-        hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(1024), 0, st, partials, blocks, obs);
+    if (which == 1 && obs != nullptr && partials != nullptr && finish)
+        hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(1024), 0, st, partials, blocks, 0u, obs);
     return hipGetLastError();
 }
 

@@ -56,9 +56,17 @@ inline uint32_t fdiv_host(uint32_t n, const FastDiv& f) {
 // one-workgroup kernel adds M, A, B into obs; without partials every
 // workgroup adds into obs with atomics.
 // general: use the six-class compare even when the table is paired.
+// finish = false leaves the partial sums in partials for a later
+// launch_obs_finish that handles several records at once.
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
                             int64_t* obs, hipStream_t st, uint32_t max_blocks = 0, int64_t* partials = nullptr,
-                            bool general = false);
+                            bool general = false, bool finish = true);
+// Workgroups of a half-step launch (the partial sums it leaves per record).
+uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_blocks);
+// Adds n_rec records into obs[3 * r ...]: record r from the n_blocks partial
+// sums at partials + r * stride.
+hipError_t launch_obs_finish(const int64_t* partials, uint32_t n_blocks, uint32_t n_rec, uint32_t stride,
+                             int64_t* obs, hipStream_t st);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
                        hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);
