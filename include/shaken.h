@@ -118,7 +118,10 @@ SD_API sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t lay
  * k_steps full steps of one chain, steps step0 .. step0+k_steps-1, in place:
  * (lattices of at most 65536 sites with L % 64 == 0 run in one workgroup with
  * both lattices held in LDS, one launch for all steps; larger ones use two
- * grid-wide launches per step; the result is the same bit for bit)
+ * grid-wide launches per step and, with obs, one more launch per chunk of
+ * records, whose partial sums wait in a 512 KiB device buffer the library
+ * allocates once per (device, stream) and keeps; the result is the same bit
+ * for bit)
  * sigma (device) is updated, tau (device, same size) receives the last
  * half-step-A lattice (its input content is ignored).  If obs (device) is not
  * NULL it receives, after every obs_every-th step, the int64 triple
