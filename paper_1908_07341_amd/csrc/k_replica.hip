@@ -189,36 +189,95 @@ __global__ __launch_bounds__(64 * kWaves) void k_replica_half(const uint64_t* __
     }
 }
 
-// Block (r, y) sums replica r's (M, A, B) over sites y * chunk .. and adds
-// them to out[3 r ...] (zeroed before the launch).
+// Sites per lane of k_replica_observe: the bit-sliced counters have eight
+// planes, so every count stays below 256.
+constexpr uint32_t kObsWordsPerLane = 128;
+constexpr uint32_t kWavesObs = 4;   // 256 threads
+constexpr uint32_t kObsRow = 33;   // padded row of the transposition buffer (32 replicas)
+
+__device__ __forceinline__ void ripple_add(uint64_t (&P)[8], uint64_t w) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t carry = P[b] & w;
+        P[b] ^= w;
+        w = carry;
+    }
+}
+
+// All 64 replicas' (M, A, B) in one pass over the sites.  Lane t of the
+// workgroup reads site words s0 + 256 k + t and adds, per quantity (+1
+// spins, sigma != tau_up, sigma != tau_right, sigma != tau), the word's bits
+// into eight bit-sliced counter planes, one count per replica bit.  Each lane
+// then decodes its counts per quantity, 32 replicas at a time, into a padded
+// LDS row (33 words, so that rows and columns are read and written without
+// bank conflicts); lane l sums column l mod 32 over half of the wavefront's
+// rows and adds it to the workgroup's count of that replica.  One lane per
+// replica adds the workgroup's contributions to out[3 r ...] (zeroed before
+// the launch).
 __global__ __launch_bounds__(256) void k_replica_observe(const uint64_t* __restrict__ sig,
                                                          const uint64_t* __restrict__ tau, uint32_t L, FastDiv divL,
-                                                         uint32_t chunk, int64_t* __restrict__ out) {
-    __shared__ int64_t red[4 * 4];
-    const uint32_t r = blockIdx.x;
+                                                         int64_t* __restrict__ out) {
+    __shared__ uint32_t rows[kWavesObs][64 * kObsRow];
+    __shared__ uint32_t blk[4][64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    blk[threadIdx.x >> 6][threadIdx.x & 63u] = 0u;
+    __syncthreads();
     const uint32_t n = L * L;
-    const uint32_t s0 = blockIdx.y * chunk;
-    const uint32_t s1 = s0 + chunk < n ? s0 + chunk : n;
-    int64_t v[4] = {0, 0, 0, 0};   // +1 spins, sigma != tau_up, sigma != tau_right, sigma != tau
-    for (uint32_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+    const uint32_t s0 = blockIdx.x * (256u * kObsWordsPerLane);
+    uint64_t P[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            P[q][b] = 0ull;
+    for (uint32_t k = 0; k < kObsWordsPerLane; ++k) {
+        const uint32_t s = s0 + 256u * k + threadIdx.x;
+        if (s >= n)
+            break;
         const uint32_t j = fdiv(s, divL);
         const uint32_t i = s - j * L;
         const uint64_t x = sig[s];
-        const uint64_t tu = tau[(j == L - 1 ? 0 : j + 1) * L + i];
-        const uint64_t tr = tau[j * L + (i == L - 1 ? 0 : i + 1)];
-        const uint64_t ts = tau[s];
-        v[0] += (int64_t)((x >> r) & 1u);
-        v[1] += (int64_t)(((x ^ tu) >> r) & 1u);
-        v[2] += (int64_t)(((x ^ tr) >> r) & 1u);
-        v[3] += (int64_t)(((x ^ ts) >> r) & 1u);
+        ripple_add(P[0], x);
+        ripple_add(P[1], x ^ tau[(j == L - 1 ? 0 : j + 1) * L + i]);
+        ripple_add(P[2], x ^ tau[j * L + (i == L - 1 ? 0 : i + 1)]);
+        ripple_add(P[3], x ^ tau[s]);
     }
-    block_sum_i64<4>(v, red);
-    if (threadIdx.x == 0 && s1 > s0) {
-        const int64_t N = (int64_t)(s1 - s0);
+    uint32_t* row = rows[wave];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+                uint32_t c = 0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    c |= (uint32_t)((P[q][b] >> (32 * h + r)) & 1ull) << b;
+                row[lane * kObsRow + r] = c;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint32_t col = lane & 31u, first = (lane >> 5) * 32u;
+            uint32_t sum = 0;
+            for (uint32_t l = 0; l < 32u; ++l)
+                sum += row[(first + l) * kObsRow + col];
+            atomicAdd(&blk[q][32u * h + col], sum);
+            // every lane's reads of the rows precede the next writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64u) {
+        const uint32_t r = threadIdx.x;
+        const uint32_t e = s0 + 256u * kObsWordsPerLane < n ? s0 + 256u * kObsWordsPerLane : n;
+        const int64_t N = e > s0 ? (int64_t)(e - s0) : 0;
         unsigned long long* o = reinterpret_cast<unsigned long long*>(out + 3 * r);
-        atomicAdd(o, (unsigned long long)(2 * v[0] - N));
-        atomicAdd(o + 1, (unsigned long long)(2 * N - 2 * (v[1] + v[2])));
-        atomicAdd(o + 2, (unsigned long long)(N - 2 * v[3]));
+        atomicAdd(o, (unsigned long long)(2 * (int64_t)blk[0][r] - N));
+        atomicAdd(o + 1, (unsigned long long)(2 * N - 2 * ((int64_t)blk[1][r] + (int64_t)blk[2][r])));
+        atomicAdd(o + 2, (unsigned long long)(N - 2 * (int64_t)blk[3][r]));
     }
 }
 
@@ -247,10 +306,9 @@ hipError_t launch_replica_observe(const uint64_t* sigma, const uint64_t* tau, ui
     if (e != hipSuccess)
         return e;
     const uint32_t n = L * L;
-    const uint32_t chunk = 65536u;
-    const uint32_t slices = (n + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_replica_observe, dim3(kReplicas, slices), dim3(256), 0, st, sigma, tau, L, make_fastdiv(L),
-                       chunk, out);
+    const uint32_t per_block = 256u * kObsWordsPerLane;
+    hipLaunchKernelGGL(k_replica_observe, dim3((n + per_block - 1) / per_block), dim3(256), 0, st, sigma, tau, L,
+                       make_fastdiv(L), out);
     return hipGetLastError();
 }
 

@@ -64,6 +64,30 @@ def test_replicas_equal_single_chains(oracle, L, k):
     assert np.array_equal(got_s[0], rs) and np.array_equal(got_t[0], rt)
 
 
+@pytest.mark.parametrize("L", [200, 256, 512])
+def test_replica_observe_over_several_workgroups(L):
+    # random replica words on lattices that span two or more workgroups of
+    # the observables kernel (the last one partial at L = 200): every
+    # replica's (M, A, B) against sd_observe on its own unpacked pair
+    print(f"replica observables L={L}", flush=True)
+    rng = np.random.default_rng(L)
+    info = np.iinfo(np.int64)
+    sw = rng.integers(info.min, info.max, size=L * L, dtype=np.int64, endpoint=True)
+    tw = rng.integers(info.min, info.max, size=L * L, dtype=np.int64, endpoint=True)
+    obs = torch.empty(192, dtype=torch.int64, device="cuda")
+    sd.sd_replica_observe(torch.from_numpy(sw).cuda(), torch.from_numpy(tw).cuda(), L, obs)
+    obs = obs.cpu().numpy().reshape(64, 3)
+    S, T = inputs.unpack_replicas(sw, L), inputs.unpack_replicas(tw, L)
+    for r in range(64):
+        s1, t1 = sd.new_lattice(L, sd.SD_P64), sd.new_lattice(L, sd.SD_P64)
+        s1.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(S[r])))
+        t1.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(T[r])))
+        o1 = torch.empty(3, dtype=torch.int64, device="cuda")
+        sd.sd_observe(s1, t1, L, sd.SD_P64, o1)
+        torch.cuda.synchronize()
+        assert np.array_equal(o1.cpu().numpy(), obs[r]), r
+
+
 def test_replicas_with_equal_parameters_are_a_monotone_coupling():
     # 64 copies of one (J, q) from all +1 (even replicas) and all -1 (odd):
     # shared uniforms keep every top copy above its bottom copy
