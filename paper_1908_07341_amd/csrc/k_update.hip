@@ -150,7 +150,7 @@ __device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t 
 }
 
 template <int LAYOUT>
-__device__ __forceinline__ void scatter(void* dst, const Geom& G, uint32_t g, uint64_t bits, uint64_t valid) {
+__device__ __forceinline__ void scatter(void* dst, const Geom& /*G*/, uint32_t g, uint64_t bits, uint64_t valid) {
     if constexpr (LAYOUT == kLayP64 || LAYOUT == kLayBits) {
         static_cast<uint64_t*>(dst)[g] = bits;
     } else if constexpr (LAYOUT == kLayP32) {
@@ -271,7 +271,6 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
                                                const DrawParams& dp, const PlaneMasks& pm, const uint32_t* T24,
                                                WaveList& wl, uint32_t tile0, uint32_t lane, ObsAcc& acc) {
     constexpr int kWordsPerLane = WPL;
-    constexpr uint32_t kWaveTile = 64u * kWordsPerLane;
     constexpr bool kRowWalk = LAYOUT == kLayP64 || LAYOUT == kLayI8Row;
     uint64_t lt[kWordsPerLane], c[kWordsPerLane], n1[kWordsPerLane], n2[kWordsPerLane], valid[kWordsPerLane];
     uint32_t slot[kWordsPerLane];
