@@ -76,7 +76,9 @@ sd_status sd_trajectories(const void* sigma0, void* traj, int32_t n_traj, int32_
         e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess)
         return hip_fail(e, "sd_trajectories");
-    const uint32_t threads = n_words >= 2048u ? 512u : 256u;
+    // 512 threads from 1024 words up: 256 trajectories of 256^2 (one workgroup each) leave
+    // the CUs short of waves at 256 threads
+    const uint32_t threads = n_words >= 1024u ? 512u : 256u;
     if (L % 8 == 0 && batch_lds_bytes(n_words, threads) <= (size_t)max_lds) {
         e = launch_trajectories_lds(sigma0, traj, (uint32_t)n_traj, L, J, q, seed, stream0, step0, k_steps, threads,
                                     st);
