@@ -476,18 +476,16 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
 // word are 64-bit windows of the string (rows need not start on a word).
 // ---------------------------------------------------------------------------
 
-// Bits p .. p+63 of the string (indices mod N), p < N.
-__device__ __forceinline__ uint64_t bit_window(const uint64_t* lat, uint32_t n_words, uint32_t p) {
-    const uint32_t q = p >> 6, sh = p & 63u;
+// Bits 64 g + off .. 64 g + off + 63 of the string (indices mod N = 64
+// n_words) for g < n_words and off < N.  Since 64 g is a whole number of
+// words, the window starts off >> 6 words after g, at bit off & 63.
+__device__ __forceinline__ uint64_t bit_window(const uint64_t* lat, uint32_t n_words, uint32_t g, uint32_t off) {
+    uint32_t q = g + (off >> 6);
+    q = q >= n_words ? q - n_words : q;
+    const uint32_t sh = off & 63u;
     const uint64_t w0 = lat[q];
     const uint64_t w1 = lat[q + 1u == n_words ? 0u : q + 1u];
     return sh ? ((w0 >> sh) | (w1 << (64u - sh))) : w0;
-}
-
-// (a + b) mod N for a < N, b < N, in 64-bit arithmetic.
-__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t N) {
-    const uint64_t t = (uint64_t)a + b;
-    return (uint32_t)(t >= N ? t - N : t);
 }
 
 // Bits b of word g whose site is in column r of its row ((64 g + b) % L == r).
@@ -495,6 +493,8 @@ __device__ __forceinline__ uint64_t column_mask(uint32_t g, uint32_t L, const Fa
     const uint32_t s0 = 64u * g;
     const uint32_t m = s0 - fdiv(s0, divL) * L;   // column of bit 0
     uint32_t b = r >= m ? r - m : r + L - m;
+    if (L >= 64u)   // at most one site of the word lies in column r
+        return b < 64u ? (1ull << b) : 0ull;
     uint64_t mask = 0;
     for (; b < 64u; b += L)
         mask |= 1ull << b;
@@ -509,20 +509,19 @@ template <int WHICH>
 __device__ __forceinline__ void gather_bits(const uint64_t* lat, uint32_t L, uint32_t n_words, const FastDiv& divL,
                                             uint32_t g, uint64_t& c, uint64_t& n1, uint64_t& n2) {
     const uint32_t N = 64u * n_words;
-    const uint32_t s0 = 64u * g;
     c = lat[g];
     if constexpr (WHICH == 0) {
-        n1 = bit_window(lat, n_words, add_mod(s0, N - L, N));
+        n1 = bit_window(lat, n_words, g, N - L);
         const uint64_t prev = lat[g == 0 ? n_words - 1u : g - 1u];
         const uint64_t base = (c << 1) | (prev >> 63);
-        const uint64_t wrap = bit_window(lat, n_words, add_mod(s0, L - 1u, N));
+        const uint64_t wrap = bit_window(lat, n_words, g, L - 1u);
         const uint64_t col0 = column_mask(g, L, divL, 0u);
         n2 = (base & ~col0) | (wrap & col0);
     } else {
-        n1 = bit_window(lat, n_words, add_mod(s0, L, N));
+        n1 = bit_window(lat, n_words, g, L);
         const uint64_t next = lat[g + 1u == n_words ? 0u : g + 1u];
         const uint64_t base = (c >> 1) | (next << 63);
-        const uint64_t wrap = bit_window(lat, n_words, add_mod(s0, N + 1u - L, N));
+        const uint64_t wrap = bit_window(lat, n_words, g, N + 1u - L);
         const uint64_t last = column_mask(g, L, divL, L - 1u);
         n2 = (base & ~last) | (wrap & last);
     }
