@@ -6,9 +6,12 @@ recorded every 10 steps.  One step = two half-steps = 2 L^2 spin updates.
 W untimed warm-up steps are followed by exactly K timed steps.
 
 Also reported on the same JSON line:
-  roofline      - the half-step kernel against the VALU peak it is bound by
+  roofline      - the half-step kernel's algorithmic HBM rate against the 8 TB/s
+                  peak (the 70% target), and the VALU roofline that binds it
   cpu_baseline  - the CPU oracle on a bounded sample of the same workload: one
-                  thread, and (all_cores) one chain per host core at once
+                  pinned thread, and (all_cores) one chain per host core at
+                  once; the GPU's lattices after the same steps are compared
+                  with the oracle's
   int8_sweep    - 1024^2 int8 lattices at q = J in {0.2, ..., 1.0}, 10^4 steps
                   each, (M, A, B) every step, D(r <= 512) every 100 steps
   batched_scan  - 4096 chains, (q, J) on a 64 x 64 grid, L in {128, 256, 512},
@@ -52,6 +55,10 @@ HBM_PEAK_GBS = 8000.0
 # 2 logic ops) per 32 sites.
 PHILOX_CALLS_PER_SITE = 4.0 / 64.0 + 1.0 / 256.0
 OPS_PER_SPIN_UPDATE = PHILOX_CALLS_PER_SITE * 10 * 4 + 8 * 3 / 32.0
+# Algorithmic HBM bytes per spin update of a packed half-step: the site's bit
+# of the source lattice read and its new bit written (neighbour words are
+# re-reads served by the caches).
+ALG_BYTES_PER_SPIN_UPDATE = 0.25
 
 
 # Sources whose content determines the half-step kernel; a traffic figure from
@@ -172,6 +179,9 @@ def parse():
                    help="only the coupling-from-the-past samples (32x32, J near the square-lattice critical value)")
     p.add_argument("--table1", action="store_true",
                    help="only the diagonal-correlation comparison with Table 1 (32x32, all (q, J) rows)")
+    p.add_argument("--cpu-plan", action="store_true",
+                   help="only the oracle on the CPU baseline plan's workloads (C1, a C2 point, 64 C4 chains, "
+                        "a C5 sample), one pinned core per job")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="write the half-step traffic record from two rocprofv3 counter CSVs and exit")
     return p.parse_args()
@@ -227,6 +237,29 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
             "run_choice": list(sd.sd_tuned_choice(L, sd.SD_I8))}
 
 
+PREROLL_S = 0.5   # untimed half-steps on scratch lattices before the timed region
+
+
+def preroll(sd, torch, L, seconds=PREROLL_S):
+    """Untimed work on scratch lattices of the benchmark's size for a fixed
+    wall time, so that the timed steps start with the GPU at its working
+    clocks whatever K is (a short timed region would otherwise include the
+    clock ramp).  The chain that is timed is not touched."""
+    a, b = sd.new_lattice(L, sd.SD_P64), sd.new_lattice(L, sd.SD_P64)
+    sd.sd_init(a, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 2, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        sd.sd_run(a, b, L, sd.SD_P64, 0.5, 0.5, 2, 0, n, 20, None, 0)
+        torch.cuda.synchronize()
+        n += 20
+    return {"seconds": time.perf_counter() - t0, "steps": n}
+
+
+LAUNCH_REPS = 250   # steps timed without observables for the per-launch duration
+
+
 def bench_single(sd, torch, L, K, W):
     J = q = 0.5
     obs_every = 10
@@ -237,6 +270,7 @@ def bench_single(sd, torch, L, K, W):
         sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, 0, W, None, 0)
     obs = torch.zeros((max(K // obs_every, 1), 3), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
+    pre = preroll(sd, torch, L)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -248,30 +282,62 @@ def bench_single(sd, torch, L, K, W):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     m = obs[-1, 0].item() / (L * L)
-    # per-launch duration of the half-step kernel: the same K steps of launches,
-    # timed again without observables so that only the two half-step kernels run
+    # per-launch duration of the half-step kernel: LAUNCH_REPS further steps
+    # without observables (only the two half-step kernels run), timed with HIP
+    # events on the stream they are launched on
     e2 = torch.cuda.Event(enable_timing=True)
     e3 = torch.cuda.Event(enable_timing=True)
-    reps = min(K, 200)
     e2.record(stream)
-    sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, W + K, reps, None, 0)
+    sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, 1, 0, W + K, LAUNCH_REPS, None, 0)
     e3.record(stream)
     torch.cuda.synchronize()
-    launch_ms = e2.elapsed_time(e3) / (2 * reps)
-    return dict(wall_s=wall, event_ms=ev_ms, launch_ms=launch_ms, m_final=m)
+    launch_ms = e2.elapsed_time(e3) / (2 * LAUNCH_REPS)
+    return dict(wall_s=wall, event_ms=ev_ms, launch_ms=launch_ms, m_final=m, preroll=pre)
 
 
-def bench_cpu(L, n_steps):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_cpu(sd, torch, L, n_steps):
+    """The oracle on the first n_steps of the headline chain (same start, seed
+    and stream), on one host core (the thread pinned to the first CPU it may
+    use), and the GPU's lattices after the same steps compared with the
+    oracle's, byte for byte."""
     from oracle import oracle as orc
     orc.build(force=False)
+    cores = sorted(os.sched_getaffinity(0))
     s0 = orc.init(L, orc.INIT_RANDOM, 0.5, 1, 0)
-    t0 = time.perf_counter()
-    orc.run(s0, 0.5, 0.5, 1, 0, 0, n_steps)
-    dt = time.perf_counter() - t0
+    os.sched_setaffinity(0, {cores[0]})
+    try:
+        t0 = time.perf_counter()
+        ref_s, ref_t, _ = orc.run(s0, 0.5, 0.5, 1, 0, 0, n_steps)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    del s0
+    sigma, tau = sd.new_lattice(L, sd.SD_P64), sd.new_lattice(L, sd.SD_P64)
+    sd.sd_init(sigma, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, 1, 0)
+    sd.sd_run(sigma, tau, L, sd.SD_P64, 0.5, 0.5, 1, 0, 0, n_steps, None, 0)
+    torch.cuda.synchronize()
+    from paper_1908_07341_amd import inputs
+    same = (np.array_equal(sigma.view(torch.uint8).view(-1).cpu().numpy(), inputs.pack_bits(ref_s)) and
+            np.array_equal(tau.view(torch.uint8).view(-1).cpu().numpy(), inputs.pack_bits(ref_t)))
+    del ref_s, ref_t
     ups = 2.0 * L * L * n_steps / dt
     return {"value": ups / 1e9, "unit": "spin updates/ns", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} full step(s) of the {L}x{L} chain (J=q=0.5, random start) on one host core "
-                      f"in {dt:.1f} s", "seconds": dt, "all_cores": bench_cpu_all_cores(L, n_steps)}
+            "sample": f"{n_steps} full step(s) of the {L}x{L} chain (J=q=0.5, random start, seed 1, stream 0) on "
+                      f"one host core (thread pinned to CPU {cores[0]}) in {dt:.1f} s",
+            "seconds": dt, "cpu_model": cpu_model(), "host_cpus": len(cores),
+            "gpu_lattices_bit_identical": bool(same),
+            "all_cores": bench_cpu_all_cores(L, n_steps)}
 
 
 def bench_cpu_all_cores(L, n_steps, max_cores=16):
@@ -291,6 +357,106 @@ def bench_cpu_all_cores(L, n_steps, max_cores=16):
     return {"value": ups / 1e9, "unit": "spin updates/ns", "cores": n,
             "sample": f"{n} independent {L}x{L} chains (streams 0..{n - 1}), {n_steps} full step(s) each, "
                       f"one thread per core, in {dt:.1f} s"}
+
+
+def bench_cpu_plan(n_c5=8):
+    """The oracle on the workloads of the CPU baseline plan, each job on a
+    host core of its own (the thread pinned with sched_setaffinity), all jobs
+    at once: C1 in full (64^2 all +1, J=0.4, q=0.6, 10^4 steps, records every
+    step); one C2 point in full (1024^2, q=J=0.6, 10^4 steps, records every
+    step, D(r <= 512) every 100); 64 chains of the C4 scan (all three sizes,
+    5000 steps, records every step), spread over the remaining cores; and
+    n_c5 trajectories of the C5 set in full (256^2, 2000 steps: the chain
+    and the 12 counts of its transitions).  No GPU work."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as orc
+    from paper_1908_07341_amd import inputs
+    orc.build(force=False)
+    cores = sorted(os.sched_getaffinity(0))
+    if len(cores) < 4:
+        raise SystemExit("--cpu-plan needs at least 4 host cores")
+
+    def pinned(core, fn):
+        def run():
+            os.sched_setaffinity(0, {core})
+            t0 = time.perf_counter()
+            out = fn()
+            return time.perf_counter() - t0, out
+        return run
+
+    def c1():
+        s0 = np.ones((64, 64), np.int8)
+        return orc.run(s0, 0.4, 0.6, 1, 0, 0, 10000, obs_every=1)[2].shape[0]
+
+    def c2():
+        L, n_steps, every = 1024, 10000, 100
+        sig = orc.init(L, orc.INIT_RANDOM, 0.5, 1, 2)
+        tau = None
+        for blk in range(n_steps // every):
+            sig, tau, _ = orc.run(sig, 0.6, 0.6, 1, 2, every * blk, every, obs_every=1, tau=tau)
+            orc.corr_row(sig, 512)
+        return n_steps
+
+    qv, Jv, Lv = inputs.scan_table()
+    rng = np.random.default_rng(5)
+    chains = []
+    for size in (128, 256, 512):
+        chains += rng.choice(np.flatnonzero(Lv == size), size=21 if size != 512 else 22, replace=False).tolist()
+
+    def c4_chain(c):
+        Lc = int(Lv[c])
+        s0 = orc.init(Lc, orc.INIT_RANDOM, 0.5, 1, c)
+        orc.run(s0, float(Jv[c]), float(qv[c]), 1, c, 0, 5000, obs_every=1)
+        return 2.0 * Lc * Lc * 5000
+
+    def c5_one(a):
+        L, k = 256, 2000
+        X = orc.trajectory(orc.init(L, orc.INIT_RANDOM, 0.5, 1, a), 0.45, 0.7, 1, a, 0, k)
+        orc.loglik_counts(X[None])
+        return 2 * k * L * L
+
+    jobs = [("C1", cores[0], c1), ("C2", cores[1], c2)]
+    c5_cores = cores[2:3]
+    c4_cores = cores[3:]
+    results = {}
+    with ThreadPoolExecutor(max_workers=len(cores)) as ex:
+        futs = {name: ex.submit(pinned(core, fn)) for name, core, fn in jobs}
+
+        def c4_worker(core, mine):
+            os.sched_setaffinity(0, {core})
+            t0 = time.perf_counter()
+            ups = sum(c4_chain(c) for c in mine)
+            return time.perf_counter() - t0, ups
+
+        def c5_worker(core):
+            os.sched_setaffinity(0, {core})
+            t0 = time.perf_counter()
+            n = sum(c5_one(a) for a in range(n_c5))
+            return time.perf_counter() - t0, n
+
+        f4 = [ex.submit(c4_worker, core, chains[i::len(c4_cores)]) for i, core in enumerate(c4_cores)]
+        f5 = ex.submit(c5_worker, c5_cores[0])
+        dt1, n1 = futs["C1"].result()
+        dt2, n2 = futs["C2"].result()
+        r4 = [f.result() for f in f4]
+        dt5, n5 = f5.result()
+    ups4 = sum(u for _, u in r4)
+    core_s4 = sum(t for t, _ in r4)
+    results["C1"] = {"what": "64x64 all +1, J=0.4, q=0.6, 10^4 steps, (M,A,B) every step, one core",
+                     "seconds": dt1, "spin_updates_per_ns": 2.0 * 64 * 64 * 10000 / dt1 / 1e9}
+    results["C2_one_point"] = {"what": "1024x1024 random start, q=J=0.6, 10^4 steps, (M,A,B) every step, "
+                                       "D(r<=512) every 100 steps, one core",
+                               "seconds": dt2, "spin_updates_per_ns": 2.0 * 1024 * 1024 * 10000 / dt2 / 1e9}
+    results["C4_64_chains"] = {"what": f"{len(chains)} chains of the scan (21 of 128^2, 21 of 256^2, 22 of 512^2), "
+                                       f"5000 steps, (M,A,B) every step, on {len(c4_cores)} cores",
+                               "wall_seconds": max(t for t, _ in r4), "core_seconds": core_s4,
+                               "spin_updates_per_ns_per_core": ups4 / core_s4 / 1e9,
+                               "chain_steps_per_s_per_core": len(chains) * 5000 / core_s4}
+    results["C5_sample"] = {"what": f"{n_c5} trajectories of 256^2, 2000 steps at (0.45, 0.7): chain and "
+                                    f"counts of every transition, one core",
+                            "seconds": dt5, "transitions_per_ns": n5 / dt5 / 1e9,
+                            "full_set_seconds_estimated": dt5 * 256 / n_c5}
+    return {"cpu_model": cpu_model(), "host_cpus": len(cores), "kind": "oracle", "jobs": results}
 
 
 def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
@@ -687,6 +853,9 @@ def main():
             json.dump(rec, f, indent=1)
         print(json.dumps({"kernel": rec["kernel"], "bytes_per_launch": rec["bytes_per_launch"]}))
         return
+    if args.cpu_plan:
+        print(json.dumps({"cpu_plan": bench_cpu_plan()}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the shaken-dynamics path here is "
                                    "built and measured for a single MI355X (a chain would shard by row bands "
@@ -730,11 +899,14 @@ def main():
     value = updates / (r["wall_s"] * 1e9)
     log(f"[bench] {value:.1f} spin updates/ns; half-step launch {r['launch_ms']*1e3:.1f} us")
     per_launch_updates = L * L
-    achieved = OPS_PER_SPIN_UPDATE * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e12
-    peak = VALU_PEAK_OPS / 1e12
+    launch_s = r["launch_ms"] * 1e-3
+    hbm_gbs = ALG_BYTES_PER_SPIN_UPDATE * per_launch_updates / launch_s / 1e9
+    alu_achieved = OPS_PER_SPIN_UPDATE * per_launch_updates / launch_s / 1e12
+    alu_peak = VALU_PEAK_OPS / 1e12
     traffic, traffic_kernel = measured_traffic()
-    kernel = {0: "built-in rule", 1: "single-workgroup LDS kernel"}.get(
-        choice[0], f"k_half_step on {choice[1]}-bit words, {choice[2]} workgroups")
+    blocks = choice[2]
+    kernel = {1: "single-workgroup LDS kernel"}.get(
+        choice[0], f"k_half_step on {choice[1]}-bit words, {blocks} workgroups of 256 threads")
     out = {
         "metric": METRIC, "value": value, "unit": "spin updates/ns", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": r["wall_s"] * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -742,12 +914,19 @@ def main():
         "config": {"workload": f"single chain {L}x{L} periodic, bit-packed 64 spins/word, random start (p=0.5), "
                                f"J=0.5, q=0.5, observables (M,A,B) every 10 steps",
                    "L": L, "layout": "P64", "J": 0.5, "q": 0.5, "obs_every": 10, "seed": 1},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": traffic, "traffic_kernel": traffic_kernel,
-                     "kernel": kernel, "tuned_choice": list(choice), "launch_us": r["launch_ms"] * 1e3,
-                     "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
-                     "hbm_algorithmic_GBps": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9,
-                     "hbm_frac": 0.25 * per_launch_updates / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        # HBM roofline of the half-step kernel (the figure the 70% target is
+        # set on) from its algorithmic bytes, and beside it the VALU roofline
+        # that actually binds it
+        "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_kernel": traffic_kernel,
+                     "kernel": kernel, "launch_us": r["launch_ms"] * 1e3, "launches_timed": 2 * LAUNCH_REPS,
+                     "bytes_per_spin_update": ALG_BYTES_PER_SPIN_UPDATE, "target_frac": 0.70,
+                     "binding_resource": "alu",
+                     "alu": {"achieved": alu_achieved, "peak": alu_peak, "unit": "T lane-ops/s",
+                             "frac": alu_achieved / alu_peak, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
+                             "hbm_frac_at_alu_peak": ALG_BYTES_PER_SPIN_UPDATE * VALU_PEAK_OPS /
+                             OPS_PER_SPIN_UPDATE / 1e9 / HBM_PEAK_GBS},
+                     "tuned_choice": list(choice), "preroll": r["preroll"]},
         "m_final": r["m_final"],
     }
     if not args.no_c2:
@@ -771,7 +950,7 @@ def main():
         log(f"[bench] replicas {out['replicas']['spin_updates_per_ns']:.0f} spin updates/ns over 64 chains")
     if not args.no_cpu:
         log(f"[bench] CPU oracle, {args.cpu_steps} step(s) at L={L}")
-        out["cpu_baseline"] = bench_cpu(L, args.cpu_steps)
+        out["cpu_baseline"] = bench_cpu(sd, torch, L, args.cpu_steps)
         log(f"[bench] CPU {out['cpu_baseline']['value']:.4f} spin updates/ns")
     print(json.dumps(out), flush=True)
 

@@ -152,7 +152,9 @@ SD_API sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, doubl
 SD_API sd_status sd_tune(int32_t L, int32_t layout, const char* tune_cache_path, void* hip_stream);
 
 /* The choice sd_run currently uses for (L, layout): mode 0 = built-in rule,
- * 1 = LDS kernel, 2 = grid kernels; word width; workgroups; workgroup size. */
+ * 1 = LDS kernel, 2 = grid kernels; word width; the workgroups of each
+ * half-step launch when sd_run takes the grid kernels; the LDS kernel's
+ * workgroup size. */
 SD_API sd_status sd_tuned_choice(int32_t L, int32_t layout, int32_t* mode, int32_t* width, int32_t* blocks,
                                  int32_t* threads);
 

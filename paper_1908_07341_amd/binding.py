@@ -115,6 +115,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, nbytes: int, what: str) -> None:
+    """Raise ValueError if tensor t holds fewer than nbytes bytes.  The ABI
+    takes raw pointers and cannot check lengths, so every wrapper checks the
+    tensors it passes against what the library will read or write.  (A raw
+    integer address is passed through unchecked.)"""
+    if t is None or isinstance(t, int):
+        return
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what}: tensor holds {have} bytes, the call needs {nbytes}")
+
+
+def _lattice(t, L: int, layout: int, what: str) -> None:
+    nb = sd_lattice_bytes(L, layout)
+    if nb:   # an unsupported (L, layout) is reported by the library itself
+        _need(t, nb, what)
+
+
 def _stream(hip_stream):
     if hip_stream is None:
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -138,69 +156,117 @@ def sd_threshold_table(J: float, q: float) -> list:
 
 
 def sd_init(lattice, L, layout, kind, p_up=0.5, seed=1, stream=0, hip_stream=None) -> None:
+    _lattice(lattice, L, layout, "sd_init")
     _check(lib().sd_init(_ptr(lattice), L, layout, kind, float(p_up), seed, stream, _stream(hip_stream)))
 
 
 def sd_half_step(src, dst, L, layout, which, J, q, seed, stream, t, flags=0, hip_stream=None) -> None:
+    _lattice(src, L, layout, "sd_half_step(src)")
+    _lattice(dst, L, layout, "sd_half_step(dst)")
     _check(lib().sd_half_step(_ptr(src), _ptr(dst), L, layout, which, float(J), float(q), seed, stream, t, flags,
                               _stream(hip_stream)))
 
 
+def _run_sizes(name, sigma, tau, L, layout, k_steps, obs, obs_every) -> None:
+    _lattice(sigma, L, layout, f"{name}(sigma)")
+    _lattice(tau, L, layout, f"{name}(tau)")
+    if obs is not None and obs_every:
+        _need(obs, 24 * (k_steps // obs_every), f"{name}(obs)")
+
+
 def sd_run(sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs=None, obs_every=0, flags=0,
            hip_stream=None) -> None:
+    _run_sizes("sd_run", sigma, tau, L, layout, k_steps, obs, obs_every)
     _check(lib().sd_run(_ptr(sigma), _ptr(tau), L, layout, float(J), float(q), seed, stream, step0, k_steps,
                         _ptr(obs), obs_every, flags, _stream(hip_stream)))
 
 
 def sd_observe(sigma, tau, L, layout, out3, hip_stream=None) -> None:
+    _lattice(sigma, L, layout, "sd_observe(sigma)")
+    _lattice(tau, L, layout, "sd_observe(tau)")
+    _need(out3, 24, "sd_observe(out3)")
     _check(lib().sd_observe(_ptr(sigma), _ptr(tau), L, layout, _ptr(out3), _stream(hip_stream)))
 
 
 def sd_corr_row(sigma, L, layout, rmax, out, hip_stream=None) -> None:
+    _lattice(sigma, L, layout, "sd_corr_row(sigma)")
+    _need(out, 8 * (rmax + 1), "sd_corr_row(out)")
     _check(lib().sd_corr_row(_ptr(sigma), L, layout, rmax, _ptr(out), _stream(hip_stream)))
 
 
 def sd_corr_diag(sigma, L, layout, lmax, out, hip_stream=None) -> None:
+    _lattice(sigma, L, layout, "sd_corr_diag(sigma)")
+    _need(out, 16 * (lmax + 1), "sd_corr_diag(out)")
     _check(lib().sd_corr_diag(_ptr(sigma), L, layout, lmax, _ptr(out), _stream(hip_stream)))
 
 
 def sd_trajectory(sigma0, traj, L, layout, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:
+    _lattice(sigma0, L, layout, "sd_trajectory(sigma0)")
+    _need(traj, (2 * k_steps + 1) * sd_lattice_bytes(L, layout), "sd_trajectory(traj)")
     _check(lib().sd_trajectory(_ptr(sigma0), _ptr(traj), L, layout, float(J), float(q), seed, stream, step0,
                                k_steps, _stream(hip_stream)))
 
 
 def sd_trajectories(sigma0, traj, n_traj, L, layout, J, q, seed, stream0, step0, k_steps, hip_stream=None) -> None:
+    nb = sd_lattice_bytes(L, layout)
+    _need(sigma0, max(n_traj, 0) * nb, "sd_trajectories(sigma0)")
+    _need(traj, max(n_traj, 0) * (2 * k_steps + 1) * nb, "sd_trajectories(traj)")
     _check(lib().sd_trajectories(_ptr(sigma0), _ptr(traj), n_traj, L, layout, float(J), float(q), seed, stream0, step0,
                                  k_steps, _stream(hip_stream)))
 
 
+def _traj_bytes(n_traj, n_lat, L) -> int:
+    return max(n_traj, 0) * max(n_lat, 0) * (L * L // 8 if L > 0 else 0)
+
+
 def sd_loglik_counts(traj, n_traj, n_lat, L, counts12, hip_stream=None) -> None:
+    _need(traj, _traj_bytes(n_traj, n_lat, L), "sd_loglik_counts(traj)")
+    _need(counts12, 96, "sd_loglik_counts(counts12)")
     _check(lib().sd_loglik_counts(_ptr(traj), n_traj, n_lat, L, _ptr(counts12), _stream(hip_stream)))
 
 
 def sd_loglik_fwd(counts12, Jq, ll, hip_stream=None) -> None:
+    _need(counts12, 96, "sd_loglik_fwd(counts12)")
+    _need(Jq, 8, "sd_loglik_fwd(Jq)")
+    _need(ll, 4, "sd_loglik_fwd(ll)")
     _check(lib().sd_loglik_fwd(_ptr(counts12), _ptr(Jq), _ptr(ll), _stream(hip_stream)))
 
 
 def sd_loglik_bwd(counts12, Jq, g_out, grad, hip_stream=None) -> None:
+    _need(counts12, 96, "sd_loglik_bwd(counts12)")
+    _need(Jq, 8, "sd_loglik_bwd(Jq)")
+    _need(g_out, 4, "sd_loglik_bwd(g_out)")
+    _need(grad, 8, "sd_loglik_bwd(grad)")
     _check(lib().sd_loglik_bwd(_ptr(counts12), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
 
 
 def sd_loglik_stats(traj, n_traj, n_lat, L, stats6, hip_stream=None) -> None:
+    _need(traj, _traj_bytes(n_traj, n_lat, L), "sd_loglik_stats(traj)")
+    _need(stats6, 48, "sd_loglik_stats(stats6)")
     _check(lib().sd_loglik_stats(_ptr(traj), n_traj, n_lat, L, _ptr(stats6), _stream(hip_stream)))
 
 
 def sd_loglik_fwd_stats(stats6, Jq, ll, hip_stream=None) -> None:
+    _need(stats6, 48, "sd_loglik_fwd_stats(stats6)")
+    _need(Jq, 8, "sd_loglik_fwd_stats(Jq)")
+    _need(ll, 4, "sd_loglik_fwd_stats(ll)")
     _check(lib().sd_loglik_fwd_stats(_ptr(stats6), _ptr(Jq), _ptr(ll), _stream(hip_stream)))
 
 
 def sd_loglik_bwd_stats(stats6, Jq, g_out, grad, hip_stream=None) -> None:
+    _need(stats6, 48, "sd_loglik_bwd_stats(stats6)")
+    _need(Jq, 8, "sd_loglik_bwd_stats(Jq)")
+    _need(g_out, 4, "sd_loglik_bwd_stats(g_out)")
+    _need(grad, 8, "sd_loglik_bwd_stats(grad)")
     _check(lib().sd_loglik_bwd_stats(_ptr(stats6), _ptr(Jq), _ptr(g_out), _ptr(grad), _stream(hip_stream)))
 
 
 def sd_propp_wilson(samples, work, n_samples, L, J, q, seed, stream0, step_end, T0, T_max,
                     hip_stream=None) -> list:
     """Coupling-from-the-past samples into `samples`; returns T_used (n_samples ints)."""
+    nb = sd_lattice_bytes(L, SD_P64)
+    _need(samples, max(n_samples, 0) * nb, "sd_propp_wilson(samples)")
+    _need(work, 4 * max(n_samples, 0) * nb, "sd_propp_wilson(work)")
     T_used = (ctypes.c_int64 * max(n_samples, 1))()
     _check(lib().sd_propp_wilson(_ptr(samples), _ptr(work), n_samples, L, J, q, seed, stream0, step_end, T0, T_max,
                                  ctypes.cast(T_used, ctypes.c_void_p), _stream(hip_stream)))
@@ -213,6 +279,10 @@ def sd_replica_lattice_bytes(L: int) -> int:
 
 def sd_replica_run(sigma, tau, L, J, q, seed, stream, step0, k_steps, hip_stream=None) -> None:
     """64 chains sharing one stream; J and q: 64 floats each (host)."""
+    nb = sd_replica_lattice_bytes(L)
+    if nb:
+        _need(sigma, nb, "sd_replica_run(sigma)")
+        _need(tau, nb, "sd_replica_run(tau)")
     Ja = (ctypes.c_double * 64)(*[float(x) for x in J])
     qa = (ctypes.c_double * 64)(*[float(x) for x in q])
     if len(J) != 64 or len(q) != 64:
@@ -222,6 +292,11 @@ def sd_replica_run(sigma, tau, L, J, q, seed, stream, step0, k_steps, hip_stream
 
 
 def sd_replica_observe(sigma, tau, L, out, hip_stream=None) -> None:
+    nb = sd_replica_lattice_bytes(L)
+    if nb:
+        _need(sigma, nb, "sd_replica_observe(sigma)")
+        _need(tau, nb, "sd_replica_observe(tau)")
+    _need(out, 192 * 8, "sd_replica_observe(out)")
     _check(lib().sd_replica_observe(_ptr(sigma), _ptr(tau), L, _ptr(out), _stream(hip_stream)))
 
 
@@ -274,14 +349,22 @@ def sd_batch_launch_shape(plan: sd_batch_plan, bucket: int):
 
 
 def sd_batch_init(plan: sd_batch_plan, lattices, kind, p_up=0.5, hip_stream=None) -> None:
+    _need(lattices, sd_batch_lattice_bytes(plan), "sd_batch_init(lattices)")
     _check(lib().sd_batch_init(plan.handle, _ptr(lattices), kind, float(p_up), _stream(hip_stream)))
 
 
+def _batch_sizes(name, plan, lattices, traces) -> None:
+    _need(lattices, sd_batch_lattice_bytes(plan), f"{name}(lattices)")
+    _need(traces, 8 * sd_batch_trace_len(plan), f"{name}(traces)")
+
+
 def sd_batch_run(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None) -> None:
+    _batch_sizes("sd_batch_run", plan, lattices, traces)
     _check(lib().sd_batch_run(plan.handle, _ptr(lattices), _ptr(traces), step0, _stream(hip_stream)))
 
 
 def sd_batch_run_direct(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None) -> None:
+    _batch_sizes("sd_batch_run_direct", plan, lattices, traces)
     _check(lib().sd_batch_run_direct(plan.handle, _ptr(lattices), _ptr(traces), step0, _stream(hip_stream)))
 
 

@@ -173,9 +173,9 @@ uint32_t lds_max_words() {
     return w;
 }
 
-int64_t* partials_workspace(hipStream_t st) {
+Workspace* partials_workspace(hipStream_t st) {
     static std::mutex mu;
-    static std::map<std::pair<int, hipStream_t>, int64_t*> spaces;
+    static std::map<std::pair<int, hipStream_t>, Workspace*> spaces;   // kept until the process ends
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return nullptr;
@@ -194,8 +194,108 @@ int64_t* partials_workspace(hipStream_t st) {
         (void)hipGetLastError();
         return nullptr;
     }
-    spaces[key] = p;
-    return p;
+    Workspace* w = new Workspace;
+    w->p = p;
+    spaces[key] = w;
+    return w;
+}
+
+// The step loop behind sd_run.  The grid kernels of a recorded half-step B
+// leave per-workgroup partial sums in a device buffer of kPartialsWords
+// int64: the per-(device, stream) workspace (null under stream capture:
+// atomics into the records instead).
+sd_status run_chain(const char* name, void* sigma, void* tau, int32_t L, int32_t layout, double J, double q,
+                    uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,
+                    uint32_t obs_every, uint32_t flags, void* hip_stream) {
+    sd_status s = check_lattice(sigma, L, layout, name);
+    if (s == SD_OK)
+        s = check_lattice(tau, L, layout, name);
+    if (s != SD_OK)
+        return s;
+    if (!std::isfinite(J) || !std::isfinite(q))
+        return fail(SD_EINVAL, "%s: J and q must be finite", name);
+    if (step0 + (uint64_t)k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "%s: step indices must stay below 2^29", name);
+    if (obs && obs_every == 0)
+        return fail(SD_EINVAL, "%s: obs given without obs_every", name);
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GLOBAL_KERNELS | SD_FLAG_GENERAL_COMPARE))
+        return fail(SD_EINVAL, "%s: unknown flags", name);
+    if (overlap(sigma, tau, lattice_bytes(L, layout)))
+        return fail(SD_EINVAL, "%s: sigma and tau overlap", name);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, sigma) == kLayI8Row &&
+                                     kernel_layout(L, layout, tau) == kLayI8Row)
+                                        ? kLayI8Row
+                                        : kLayI8Any)
+                                 : kernel_layout(L, layout, sigma);
+    const RunChoice ch = run_choice(L, layout);
+    if (layout != SD_I8 && L % 64 == 0)
+        klay = ch.width == 32 ? kLayP32 : kLayP64;
+    const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
+    const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
+    const uint32_t lds_words = ch.mode == 1 ? lds_max_words() : kSingleLdsMaxWords;
+    const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0) ||
+                         klay == kLayBits) &&
+                        n_words <= lds_words && ch.mode != 2 && !(flags & SD_FLAG_GLOBAL_KERNELS);
+    if (lds_ok) {
+        if (k_steps == 0)
+            return SD_OK;
+        hipError_t e = launch_single_chain_lds(sigma, tau, L, klay == kLayI8Row, J, q, seed, stream, step0, k_steps,
+                                               n_rec ? obs : nullptr, obs_every, flags, ch.threads, st);
+        return e == hipSuccess ? SD_OK : hip_fail(e, name);
+    }
+    const Geom G = make_geom(L, klay);
+    hipError_t e = hipSuccess;
+    int64_t* partials = nullptr;
+    std::unique_lock<std::mutex> hold;   // keeps this call's use of the workspace contiguous on the stream
+    if (n_rec) {
+        Workspace* ws = partials_workspace(st);
+        if (ws) {
+            hold = std::unique_lock<std::mutex>(ws->mu);
+            partials = ws->p;
+        }
+    }
+    // the table and keys once; only the time index changes from step to step
+    const DrawParams base = dynamics_params(J, q, seed, stream, 0u, flags & SD_FLAG_COMPLEMENT_RNG);
+    const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
+    // Each record's workgroup sums go to a slot of their own in the partials
+    // workspace; one finishing launch adds a whole chunk of records, so that
+    // frequent records cost no third launch per step.
+    const uint32_t blocks = half_step_blocks(klay, G, !general && thresholds_paired(base.T), ch.blocks);
+    const uint32_t stride = 4u * blocks;
+    if (n_rec && stride > kPartialsWords)
+        return fail(SD_EINVAL, "%s: %u workgroups need %u partial sums per record, more than the %zu of the "
+                    "scratch buffer", name, blocks, stride, kPartialsWords);
+    const uint32_t chunk = (uint32_t)(kPartialsWords / stride);
+    if (n_rec)
+        e = launch_fill_i64(obs, (size_t)n_rec * 3u, 0, st);
+    uint32_t pending = 0;   // records whose sums wait in the workspace
+    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
+        const uint64_t n = step0 + m;
+        DrawParams dp = base;
+        dp.t = (uint32_t)(2 * n);
+        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks, nullptr, general);
+        if (e != hipSuccess)
+            break;
+        dp.t = (uint32_t)(2 * n + 1);
+        if (n_rec && (m + 1) % obs_every == 0 && !partials) {
+            // no workspace (first use under stream capture): atomics into the record
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)((m + 1) / obs_every - 1), st,
+                                 ch.blocks, nullptr, general);
+        } else if (n_rec && (m + 1) % obs_every == 0) {
+            const uint32_t r = (m + 1) / obs_every - 1;
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)r, st, ch.blocks,
+                                 partials + (size_t)pending * stride, general, false);
+            ++pending;
+            if (e == hipSuccess && (pending == chunk || r + 1 == n_rec)) {
+                e = launch_obs_finish(partials, blocks, pending, stride, obs + 3u * (size_t)(r + 1 - pending), st);
+                pending = 0;
+            }
+        } else {
+            e = launch_half_step(klay, 1, tau, sigma, G, dp, nullptr, st, ch.blocks, nullptr, general);
+        }
+    }
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
 }
 
 }  // namespace sd
@@ -286,84 +386,8 @@ sd_status sd_half_step(const void* src, void* dst, int32_t L, int32_t layout, in
 sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
                  uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
                  uint32_t flags, void* hip_stream) {
-    sd_status s = check_lattice(sigma, L, layout, "sd_run(sigma)");
-    if (s == SD_OK)
-        s = check_lattice(tau, L, layout, "sd_run(tau)");
-    if (s != SD_OK)
-        return s;
-    if (!std::isfinite(J) || !std::isfinite(q))
-        return fail(SD_EINVAL, "sd_run: J and q must be finite");
-    if (step0 + (uint64_t)k_steps > (1ull << 29))
-        return fail(SD_EINVAL, "sd_run: step indices must stay below 2^29");
-    if (obs && obs_every == 0)
-        return fail(SD_EINVAL, "sd_run: obs given without obs_every");
-    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GLOBAL_KERNELS | SD_FLAG_GENERAL_COMPARE))
-        return fail(SD_EINVAL, "sd_run: unknown flags");
-    if (overlap(sigma, tau, lattice_bytes(L, layout)))
-        return fail(SD_EINVAL, "sd_run: sigma and tau overlap");
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    int klay = (layout == SD_I8) ? ((kernel_layout(L, layout, sigma) == kLayI8Row &&
-                                     kernel_layout(L, layout, tau) == kLayI8Row)
-                                        ? kLayI8Row
-                                        : kLayI8Any)
-                                 : kernel_layout(L, layout, sigma);
-    const RunChoice ch = run_choice(L, layout);
-    if (layout != SD_I8 && L % 64 == 0)
-        klay = ch.width == 32 ? kLayP32 : kLayP64;
-    const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
-    const uint32_t n_words = (uint32_t)(((uint64_t)L * (uint64_t)L) / 64u);
-    const uint32_t lds_words = ch.mode == 1 ? lds_max_words() : kSingleLdsMaxWords;
-    const bool lds_ok = (klay == kLayP64 || klay == kLayI8Row || (klay == kLayP32 && L % 64 == 0) ||
-                         klay == kLayBits) &&
-                        n_words <= lds_words && ch.mode != 2 && !(flags & SD_FLAG_GLOBAL_KERNELS);
-    if (lds_ok) {
-        if (k_steps == 0)
-            return SD_OK;
-        hipError_t e = launch_single_chain_lds(sigma, tau, L, klay == kLayI8Row, J, q, seed, stream, step0, k_steps,
-                                               n_rec ? obs : nullptr, obs_every, flags, ch.threads, st);
-        return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
-    }
-    const Geom G = make_geom(L, klay);
-    hipError_t e = hipSuccess;
-    int64_t* partials = n_rec ? partials_workspace(st) : nullptr;
-    if (n_rec)
-        e = launch_fill_i64(obs, (size_t)n_rec * 3u, 0, st);
-    // the table and keys once; only the time index changes from step to step
-    const DrawParams base = dynamics_params(J, q, seed, stream, 0u, flags & SD_FLAG_COMPLEMENT_RNG);
-    const bool general = (flags & SD_FLAG_GENERAL_COMPARE) != 0;
-    // Each record's workgroup sums go to a slot of their own in the partials
-    // workspace; one finishing launch adds a whole chunk of records, so that
-    // frequent records cost no third launch per step.
-    const uint32_t blocks = half_step_blocks(klay, G, !general && thresholds_paired(base.T), ch.blocks);
-    const uint32_t stride = 4u * blocks;
-    const uint32_t chunk = (uint32_t)(kPartialsWords / stride);
-    uint32_t pending = 0;   // records whose sums wait in the workspace
-    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
-        const uint64_t n = step0 + m;
-        DrawParams dp = base;
-        dp.t = (uint32_t)(2 * n);
-        e = launch_half_step(klay, 0, sigma, tau, G, dp, nullptr, st, ch.blocks, nullptr, general);
-        if (e != hipSuccess)
-            break;
-        dp.t = (uint32_t)(2 * n + 1);
-        if (n_rec && (m + 1) % obs_every == 0 && !partials) {
-            // no workspace (first use under stream capture): atomics into the record
-            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)((m + 1) / obs_every - 1), st,
-                                 ch.blocks, nullptr, general);
-        } else if (n_rec && (m + 1) % obs_every == 0) {
-            const uint32_t r = (m + 1) / obs_every - 1;
-            e = launch_half_step(klay, 1, tau, sigma, G, dp, obs + 3u * (size_t)r, st, ch.blocks,
-                                 partials + (size_t)pending * stride, general, false);
-            ++pending;
-            if (e == hipSuccess && (pending == chunk || r + 1 == n_rec)) {
-                e = launch_obs_finish(partials, blocks, pending, stride, obs + 3u * (size_t)(r + 1 - pending), st);
-                pending = 0;
-            }
-        } else {
-            e = launch_half_step(klay, 1, tau, sigma, G, dp, nullptr, st, ch.blocks, nullptr, general);
-        }
-    }
-    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_run");
+    return run_chain("sd_run", sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs, obs_every, flags,
+                     hip_stream);
 }
 
 sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,
@@ -446,17 +470,27 @@ sd_status sd_tune(int32_t L, int32_t layout, const char* tune_cache_path, void* 
             c.threads = th;
             cands.push_back(c);
         }
-    const uint32_t tiles = (uint32_t)((n_words + 1023u) / 1024u);
     for (int width : {64, 32}) {
         if (width == 32 && (layout == SD_I8 || L % 64 != 0))
             continue;
-        for (uint32_t b : {256u, 512u, 1024u, 2048u, 4096u}) {
-            if (b > 2 * tiles && b != 256u)
+        // only grids that differ: a cap above one workgroup per four tiles
+        // launches the same grid as the uncapped one
+        int klay = kernel_layout(L, layout, nullptr);
+        if (layout != SD_I8 && L % 64 == 0)
+            klay = width == 32 ? kLayP32 : kLayP64;
+        if (layout == SD_I8)
+            klay = L % 64 == 0 ? kLayI8Row : kLayI8Any;
+        const Geom G = make_geom(L, klay);
+        uint32_t last = 0;
+        for (uint32_t b : {256u, 512u, 1024u, 2048u, 4096u, 8192u}) {
+            const uint32_t launched = half_step_blocks(klay, G, true, b);
+            if (launched == last)
                 continue;
+            last = launched;
             RunChoice c;
             c.mode = 2;
             c.width = width;
-            c.blocks = b;
+            c.blocks = launched;
             cands.push_back(c);
         }
     }
@@ -536,7 +570,14 @@ sd_status sd_tuned_choice(int32_t L, int32_t layout, int32_t* mode, int32_t* wid
     const RunChoice c = run_choice(L, layout);
     if (mode) *mode = c.mode;
     if (width) *width = c.width;
-    if (blocks) *blocks = (int32_t)c.blocks;
+    if (blocks) {
+        // the grid sd_run launches per half-step when it takes the grid kernels
+        // (paired compare, the form every threshold table takes)
+        int klay = layout == SD_I8 ? (L % 64 == 0 ? kLayI8Row : kLayI8Any) : kernel_layout(L, layout, nullptr);
+        if (layout != SD_I8 && L % 64 == 0)
+            klay = c.width == 32 ? kLayP32 : kLayP64;
+        *blocks = (int32_t)half_step_blocks(klay, make_geom(L, klay), true, c.blocks);
+    }
     if (threads) *threads = (int32_t)c.threads;
     return SD_OK;
 }

@@ -18,6 +18,14 @@ namespace {
 
 constexpr int kTailCap = 1024;
 
+// The 64-bit-word layout when every row is a whole number of 64-word chunks
+// (L % 4096 == 0): the 64 words a wavefront handles at once then lie in one
+// row, so the row and its neighbour rows are wavefront-uniform addresses
+// and the word before (after) a lane's word is the next lower (higher)
+// lane's word.  Same bytes as kLayP64; only the half-step kernel tells the
+// two apart.
+constexpr int kLayP64Rows = 16;
+
 __device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t x) {
     // byte k of x is 0x01 (+1) or 0xFF (-1); bit k of the result is 1 for +1
     uint32_t y = (~x >> 7) & 0x01010101u;
@@ -63,7 +71,7 @@ template <int LAYOUT, int WHICH>
 __device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t g, uint64_t& c, uint64_t& n1,
                                        uint64_t& n2, uint64_t& valid) {
     valid = ~0ull;
-    if constexpr (LAYOUT == kLayP64) {
+    if constexpr (LAYOUT == kLayP64 || LAYOUT == kLayP64Rows) {
         const uint64_t* s = static_cast<const uint64_t*>(src);
         const uint32_t W = G.words_row;
         const uint32_t j = fdiv(g, G.div_row);
@@ -151,7 +159,7 @@ __device__ __forceinline__ void gather(const void* src, const Geom& G, uint32_t 
 
 template <int LAYOUT>
 __device__ __forceinline__ void scatter(void* dst, const Geom& /*G*/, uint32_t g, uint64_t bits, uint64_t valid) {
-    if constexpr (LAYOUT == kLayP64 || LAYOUT == kLayBits) {
+    if constexpr (LAYOUT == kLayP64 || LAYOUT == kLayP64Rows || LAYOUT == kLayBits) {
         static_cast<uint64_t*>(dst)[g] = bits;
     } else if constexpr (LAYOUT == kLayP32) {
         uint32_t* d = static_cast<uint32_t*>(dst);
@@ -207,6 +215,17 @@ __device__ __forceinline__ void gather_row(const void* src, const Geom& G, uint3
     }
 }
 
+// 64-bit word at a wavefront-uniform base plus a 32-bit byte offset, the
+// form the global load and store instructions take directly (scalar base,
+// vector offset), with no 64-bit address arithmetic per lane.
+__device__ __forceinline__ uint64_t load_at(const uint64_t* base, uint32_t byte_off) {
+    return *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+__device__ __forceinline__ void store_at(uint64_t* base, uint32_t byte_off, uint64_t v) {
+    *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // One half-step.  Each wavefront walks tiles of kWaveTile consecutive words;
 // lane l owns words l, l + 64, ... of its tile (coalesced loads and stores).
 // For every word it draws the eight planes and compares them (decided sites
@@ -224,7 +243,8 @@ __device__ __forceinline__ void gather_row(const void* src, const Geom& G, uint3
 // Words per lane and tile: 4 for the paired compare on bit-packed layouts,
 // 2 where the general compare or the int8 loads need more registers.
 constexpr int words_per_lane(int layout, bool paired) {
-    return (paired && (layout == kLayP64 || layout == kLayP32 || layout == kLayBits)) ? 4 : 2;
+    return (paired && (layout == kLayP64 || layout == kLayP64Rows || layout == kLayP32 || layout == kLayBits)) ? 4
+                                                                                                             : 2;
 }
 constexpr int kMaxWordsPerLane = 4;
 constexpr uint32_t kMaxWaveTile = 64u * kMaxWordsPerLane;
@@ -276,7 +296,45 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
     uint32_t slot[kWordsPerLane];
     // all loads of the tile first, so that their latency overlaps the Philox
     // work of the first words
-    if constexpr (kRowWalk) {
+    if constexpr (LAYOUT == kLayP64Rows) {
+        static_assert(FULL, "row-chunk tiles are whole");
+        // tile0 is wavefront-uniform: chunk k of the tile is words w0 .. w0 + 63
+        // of row j, loaded as one uniform row address plus the lane offset
+        const uint64_t* s = static_cast<const uint64_t*>(src);
+        const uint32_t W = G.words_row;
+#pragma unroll
+        for (int k = 0; k < kWordsPerLane; ++k) {
+            const uint32_t g0 = tile0 + 64u * k;
+            const uint32_t j = fdiv(g0, G.div_row);
+            const uint32_t w0 = g0 - j * W;
+            const uint64_t* row = s + (size_t)j * W;
+            const uint32_t off = 8u * (w0 + lane);
+            c[k] = load_at(row, off);
+            const uint32_t c_lo = (uint32_t)c[k], c_hi = (uint32_t)(c[k] >> 32);
+            if constexpr (WHICH == 0) {
+                const uint64_t* nrow = s + (size_t)(j == 0 ? G.L - 1 : j - 1) * W;
+                n1[k] = load_at(nrow, off);                                                // down
+                // high half of the word before: the lower lane's, the row's
+                // wrap-around word for lane 0
+                const uint32_t edge = reinterpret_cast<const uint32_t*>(row + (w0 == 0 ? W - 1 : w0 - 1))[1];
+                const uint32_t prev_hi = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)c_hi, 0x138, 0xF,
+                                                                               0xF, false);   // wave_shr:1
+                n2[k] = (uint64_t)__builtin_amdgcn_alignbit(c_lo, prev_hi, 31) |            // left
+                        ((uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 31) << 32);
+            } else {
+                const uint64_t* nrow = s + (size_t)(j == G.L - 1 ? 0 : j + 1) * W;
+                n1[k] = load_at(nrow, off);                                                // up
+                // low half of the word after: the higher lane's, the row's
+                // wrap-around word for lane 63
+                const uint32_t edge = reinterpret_cast<const uint32_t*>(row + (w0 + 64u == W ? 0 : w0 + 64u))[0];
+                const uint32_t next_lo = (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)c_lo, 0x130, 0xF,
+                                                                               0xF, false);   // wave_shl:1
+                n2[k] = (uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 1) |                // right
+                        ((uint64_t)__builtin_amdgcn_alignbit(next_lo, c_hi, 1) << 32);
+            }
+            valid[k] = ~0ull;
+        }
+    } else if constexpr (kRowWalk) {
         const uint32_t g0 = tile0 + lane;
         uint32_t j = fdiv(g0, G.div_row);
         uint32_t w = g0 - j * G.words_row;
@@ -347,7 +405,10 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
         const uint32_t g = tile0 + lane + 64u * k;
         const uint64_t bits = FULL ? (lt[k] | wl.und[slot[k]]) : ((lt[k] | wl.und[slot[k]]) & valid[k]);
         if (FULL || g < G.n_groups) {
-            scatter<LAYOUT>(dst, G, g, bits, valid[k]);
+            if constexpr (LAYOUT == kLayP64Rows)
+                store_at(static_cast<uint64_t*>(dst) + (tile0 + 64u * k), 8u * lane, bits);
+            else
+                scatter<LAYOUT>(dst, G, g, bits, valid[k]);
             if constexpr (OBS) {
                 acc.pc += __popcll(bits);
                 acc.d_up += __popcll((bits ^ n1[k]) & valid[k]);
@@ -389,16 +450,19 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
     const uint32_t n_tiles = (G.n_groups + kWaveTile - 1) / kWaveTile;
     // tiles whose every word holds 64 lattice sites
     const uint32_t n_full = (uint32_t)((uint64_t)G.n_sites / (64ull * kWaveTile));
-    for (uint32_t tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); tile < n_tiles;
-         tile += gridDim.x * kWavesPerBlock) {
+    // the wavefront's index in the workgroup, as a uniform value (tile
+    // origins then stay in scalar registers)
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int kPartLayout = LAYOUT == kLayP64Rows ? kLayP64 : LAYOUT;
+    for (uint32_t tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
         if (tile < n_full) {
             half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, true, words_per_lane(LAYOUT, PAIRED)>(
                 src, dst, G, dp, pm, sh.T24, wl, tile * kWaveTile, lane, acc);
         } else {
             // the last, partial tile: 64 words at a time, with bounds checks
             for (uint32_t sub = tile * kWaveTile; sub < (tile + 1) * kWaveTile; sub += 64u)
-                half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, false, 1>(src, dst, G, dp, pm, sh.T24, wl,
-                                                                                  sub, lane, acc);
+                half_step_tile<kPartLayout, WHICH, PAIRED, COMPLEMENT, OBS, false, 1>(src, dst, G, dp, pm, sh.T24,
+                                                                                       wl, sub, lane, acc);
         }
     }
     if constexpr (OBS) {
@@ -487,12 +551,6 @@ uint32_t grid_for(uint32_t n_groups) {
     return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
 }
 
-uint32_t grid_for_tiles(uint32_t n_groups, uint32_t wave_tile) {
-    const uint32_t tiles = (n_groups + wave_tile - 1) / wave_tile;
-    const uint32_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
-}
-
 }  // namespace
 
 template <int LAY, int WHICH, bool OBS>
@@ -513,8 +571,14 @@ void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, 
 }
 
 uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_blocks) {
-    const uint32_t blocks = grid_for_tiles(G.n_groups, 64u * words_per_lane(layout, paired));
-    return (max_blocks && blocks > max_blocks) ? max_blocks : blocks;
+    // one workgroup per four wavefront tiles; at most kMaxBlocks by default,
+    // at most max_blocks when the caller gives a cap
+    const uint32_t wave_tile = 64u * words_per_lane(layout, paired);
+    const uint32_t tiles = (G.n_groups + wave_tile - 1) / wave_tile;
+    uint32_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    blocks = blocks ? blocks : 1u;
+    const uint32_t cap = max_blocks ? max_blocks : kMaxBlocks;
+    return blocks > cap ? cap : blocks;
 }
 
 hipError_t launch_obs_finish(const int64_t* partials, uint32_t n_blocks, uint32_t n_rec, uint32_t stride,
@@ -542,7 +606,9 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
             launch_half_step_mode<LAY, 1, true>(paired, complement, grid, block, st, src, dst, G, dp, obs,  \
                                                 partials);                                                 \
         break;
-    switch (layout) {
+    const int klay = (layout == kLayP64 && G.words_row % 64u == 0) ? kLayP64Rows : layout;
+    switch (klay) {
+        SD_HALF(kLayP64Rows)
         SD_HALF(kLayP64)
         SD_HALF(kLayP32)
         SD_HALF(kLayI8Row)

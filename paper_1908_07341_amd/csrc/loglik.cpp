@@ -107,8 +107,12 @@ sd_status loglik_sums(const char* name, const void* traj, int32_t n_traj, int32_
     if (reinterpret_cast<uintptr_t>(traj) & 7u)
         return fail(SD_EINVAL, "%s: trajectories must be 8-byte aligned", name);
     const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    Workspace* ws = partials_workspace(st);
+    std::unique_lock<std::mutex> hold;   // keeps this call's use of the workspace contiguous on the stream
+    if (ws)
+        hold = std::unique_lock<std::mutex>(ws->mu);
     hipError_t e = launch_loglik_counts(traj, (uint32_t)n_traj, (uint32_t)n_lat, (uint32_t)L, out, paired, st,
-                                        partials_workspace(st), kPartialsWords);
+                                        ws ? ws->p : nullptr, kPartialsWords);
     return e == hipSuccess ? SD_OK : hip_fail(e, name);
 }
 

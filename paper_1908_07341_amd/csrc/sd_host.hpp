@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "shaken.h"
 #include "sd_kernels.hpp"
 
@@ -22,8 +24,15 @@ DrawParams dynamics_params(double J, double q, uint64_t seed, uint32_t stream, u
 // Device scratch of kPartialsWords int64 for per-workgroup partial sums, one
 // per (device, stream), allocated on first use and kept for the process.
 // Null when it does not exist yet and cannot be made now (the stream is
-// being captured, or the allocation failed); callers then use atomics.
+// being captured, or the allocation failed); callers then use atomics.  A
+// call holds mu while it enqueues the launches that write and read p, so
+// that calls from several host threads on one stream do not interleave
+// their use of the slots.
 constexpr size_t kPartialsWords = 65536;
-int64_t* partials_workspace(hipStream_t st);
+struct Workspace {
+    int64_t* p = nullptr;
+    std::mutex mu;
+};
+Workspace* partials_workspace(hipStream_t st);
 
 }  // namespace sd

@@ -50,18 +50,20 @@ inline uint32_t fdiv_host(uint32_t n, const FastDiv& f) {
 }
 
 // max_blocks = 0: the default grid (four wavefront tiles per workgroup, at
-// most kMaxBlocks workgroups); otherwise at most max_blocks workgroups walk
-// the tiles.  With obs (half-step B only) and partials (device scratch of
-// 4 * kMaxBlocks int64), the workgroups' partial sums go to partials and a
-// one-workgroup kernel adds M, A, B into obs; without partials every
-// workgroup adds into obs with atomics.
+// most kMaxBlocks workgroups); otherwise at most max_blocks workgroups (and
+// never more than one per four tiles) walk the tiles.  With obs (half-step B
+// only) and partials (device scratch of 4 int64 per workgroup), the
+// workgroups' partial sums go to partials and a one-workgroup kernel adds
+// M, A, B into obs; without partials every workgroup adds into obs with
+// atomics.
 // general: use the six-class compare even when the table is paired.
 // finish = false leaves the partial sums in partials for a later
 // launch_obs_finish that handles several records at once.
 hipError_t launch_half_step(int layout, int which, const void* src, void* dst, const Geom& G, const DrawParams& dp,
                             int64_t* obs, hipStream_t st, uint32_t max_blocks = 0, int64_t* partials = nullptr,
                             bool general = false, bool finish = true);
-// Workgroups of a half-step launch (the partial sums it leaves per record).
+// Workgroups of a half-step launch (the partial sums it leaves per record:
+// four per workgroup).
 uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_blocks);
 // Adds n_rec records into obs[3 * r ...]: record r from the n_blocks partial
 // sums at partials + r * stride.

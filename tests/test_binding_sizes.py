@@ -1,0 +1,75 @@
+"""The binding checks every tensor against the bytes the C ABI will touch
+before calling in (the ABI takes raw pointers and cannot check lengths).
+Host tensors suffice to reach the checks: an undersized tensor is rejected
+for its size, a large enough one gets past the size check and is then
+rejected for not being device memory, so no call reaches the library."""
+import pytest
+import torch
+
+import paper_1908_07341_amd as sd
+
+
+def _t(nbytes):
+    return torch.zeros(max(nbytes, 0), dtype=torch.uint8)
+
+
+def _size_error(fn, *args):
+    with pytest.raises(ValueError, match="bytes"):
+        fn(*args)
+
+
+def _passes_size_check(fn, *args):
+    with pytest.raises(ValueError, match="device tensors"):
+        fn(*args)
+
+
+@pytest.mark.parametrize("L,layout", [(64, sd.SD_P64), (40, sd.SD_P64), (96, sd.SD_P32), (17, sd.SD_I8)])
+def test_lattice_calls_check_sizes(L, layout):
+    nb = sd.sd_lattice_bytes(L, layout)
+    ok, short = _t(nb), _t(nb - 1)
+    _size_error(sd.sd_init, short, L, layout, sd.SD_INIT_UP)
+    _passes_size_check(sd.sd_init, ok, L, layout, sd.SD_INIT_UP)
+    _size_error(sd.sd_half_step, ok, short, L, layout, 0, 0.5, 0.5, 1, 0, 0)
+    _size_error(sd.sd_half_step, short, ok, L, layout, 0, 0.5, 0.5, 1, 0, 0)
+    for fn in (sd.sd_run,):
+        _size_error(fn, short, ok, L, layout, 0.5, 0.5, 1, 0, 0, 10)
+        _size_error(fn, ok, short, L, layout, 0.5, 0.5, 1, 0, 0, 10)
+        # 10 steps with a record every 3: 3 records of 24 bytes
+        _size_error(fn, ok, _t(nb), L, layout, 0.5, 0.5, 1, 0, 0, 10, _t(71), 3)
+        _passes_size_check(fn, ok, _t(nb), L, layout, 0.5, 0.5, 1, 0, 0, 10, _t(72), 3)
+    _size_error(sd.sd_observe, ok, _t(nb), L, layout, _t(23))
+    _size_error(sd.sd_corr_row, ok, L, layout, 5, _t(47))
+    _passes_size_check(sd.sd_corr_row, ok, L, layout, 5, _t(48))
+    _size_error(sd.sd_corr_diag, ok, L, layout, 5, _t(95))
+    _passes_size_check(sd.sd_corr_diag, ok, L, layout, 5, _t(96))
+
+
+def test_trajectory_and_loglik_calls_check_sizes():
+    L, k, n = 64, 3, 2
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    _size_error(sd.sd_trajectory, _t(nb), _t((2 * k + 1) * nb - 1), L, sd.SD_P64, 0.5, 0.5, 1, 0, 0, k)
+    _passes_size_check(sd.sd_trajectory, _t(nb), _t((2 * k + 1) * nb), L, sd.SD_P64, 0.5, 0.5, 1, 0, 0, k)
+    _size_error(sd.sd_trajectories, _t(n * nb - 1), _t(n * (2 * k + 1) * nb), n, L, sd.SD_P64, 0.5, 0.5, 1, 0, 0, k)
+    _size_error(sd.sd_trajectories, _t(n * nb), _t(n * (2 * k + 1) * nb - 8), n, L, sd.SD_P64, 0.5, 0.5, 1, 0, 0, k)
+    n_lat = 2 * k + 1
+    traj = _t(n * n_lat * nb)
+    _size_error(sd.sd_loglik_counts, _t(n * n_lat * nb - 1), n, n_lat, L, _t(96))
+    _size_error(sd.sd_loglik_counts, traj, n, n_lat, L, _t(95))
+    _passes_size_check(sd.sd_loglik_counts, traj, n, n_lat, L, _t(96))
+    _size_error(sd.sd_loglik_stats, traj, n, n_lat, L, _t(47))
+    _size_error(sd.sd_loglik_fwd, _t(96), _t(7), _t(4))
+    _size_error(sd.sd_loglik_bwd, _t(96), _t(8), _t(4), _t(7))
+    _size_error(sd.sd_loglik_fwd_stats, _t(47), _t(8), _t(4))
+    _size_error(sd.sd_loglik_bwd_stats, _t(48), _t(8), _t(3), _t(8))
+    _passes_size_check(sd.sd_loglik_bwd_stats, _t(48), _t(8), None, _t(8))
+
+
+def test_replica_and_propp_wilson_calls_check_sizes():
+    L = 32
+    rb = sd.sd_replica_lattice_bytes(L)
+    J = q = [0.5] * 64
+    _size_error(sd.sd_replica_run, _t(rb - 1), _t(rb), L, J, q, 1, 0, 0, 1)
+    _size_error(sd.sd_replica_observe, _t(rb), _t(rb), L, _t(192 * 8 - 1))
+    nb = sd.sd_lattice_bytes(L, sd.SD_P64)
+    _size_error(sd.sd_propp_wilson, _t(3 * nb - 1), _t(12 * nb), 3, L, 0.5, 0.5, 1, 0, 1 << 20, 4, 64)
+    _size_error(sd.sd_propp_wilson, _t(3 * nb), _t(12 * nb - 1), 3, L, 0.5, 0.5, 1, 0, 1 << 20, 4, 64)

@@ -1,9 +1,12 @@
 """Parity at the full benchmark sizes, in the launch configuration the
 benchmark times, on outputs the oracle can compute one by one:
 
+* the headline chain (16384^2 packed, J = q = 0.5, seed 1, stream 0) in the
+  launch configuration the benchmark tunes: every site of sigma and tau after
+  steps 0 and 1, and the two fused records, against the oracle;
 * the 4096-chain (q, J) scan (L from {128, 256, 512}, 5000 steps, records
-  every step): two 128^2 chains in full against the oracle, one chain of
-  every size against its own sd_run, and for every chain the last record
+  every step): one chain of every size in full against the oracle, one chain
+  of every size against its own sd_run, and for every chain the last record
   against a recount of the returned lattice pair;
 * one point of the 1024^2 int8 sweep for its full 10^4 steps: records,
   D(r) and sampled sites of a further step against the oracle;
@@ -11,6 +14,8 @@ benchmark times, on outputs the oracle can compute one by one:
   trajectory 0 lattice by lattice and its counts and paired statistics
   against the oracle; for the whole set, the site total, the pair map of
   the counts and the FP32 LL and gradient against FP64 from the counts."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -20,6 +25,8 @@ from paper_1908_07341_amd import autograd as AG
 from paper_1908_07341_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -33,6 +40,34 @@ def _unpack_many(raw: np.ndarray, L: int) -> np.ndarray:
     bits = np.unpackbits(np.ascontiguousarray(raw).view(np.uint8).reshape(raw.shape[0], -1), axis=1,
                          bitorder="little")[:, : L * L]
     return (2 * bits.astype(np.int8) - 1).reshape(-1, L, L)
+
+
+def test_C3_full_lattice_matches_oracle(oracle):
+    # the benchmark's chain and launch choice (its tune cache), two steps with
+    # a record each, compared as packed bytes: all 2^28 sites of both lattices
+    L, J, q, seed, stream = 16384, 0.5, 0.5, 1, 0
+    cache = os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json")
+    sd.sd_tune(L, sd.SD_P64, cache)
+    print(f"C3 full lattice, run choice {sd.sd_tuned_choice(L, sd.SD_P64)}", flush=True)
+    sigma = sd.new_lattice(L, sd.SD_P64)
+    tau = sd.new_lattice(L, sd.SD_P64)
+    sd.sd_init(sigma, L, sd.SD_P64, sd.SD_INIT_RANDOM, 0.5, seed, stream)
+    ref_s = oracle.init(L, oracle.INIT_RANDOM, 0.5, seed, stream)
+
+    def packed(t):
+        torch.cuda.synchronize()
+        return t.view(torch.uint8).view(-1).cpu().numpy()
+
+    assert np.array_equal(packed(sigma), inputs.pack_bits(ref_s))
+    for n in (0, 1):
+        obs = torch.full((1, 3), -7, dtype=torch.int64, device="cuda")
+        sd.sd_run(sigma, tau, L, sd.SD_P64, J, q, seed, stream, n, 1, obs, 1)
+        print(f"C3 full lattice: oracle step {n}", flush=True)
+        ref_s, ref_t, ref_o = oracle.run(ref_s, J, q, seed, stream, n, 1, obs_every=1)
+        assert np.array_equal(packed(tau), inputs.pack_bits(ref_t)), f"tau after step {n}"
+        assert np.array_equal(packed(sigma), inputs.pack_bits(ref_s)), f"sigma after step {n}"
+        assert np.array_equal(obs.cpu().numpy(), ref_o), f"record of step {n}"
+        del ref_t
 
 
 def test_C4_full_scan_sampled(oracle, tmp_path):
@@ -78,9 +113,10 @@ def test_C4_full_scan_sampled(oracle, tmp_path):
         torch.cuda.synchronize()
         assert torch.equal(sig, lat[so:so + nb]) and torch.equal(tau, lat[to:to + nb]), c
         assert torch.equal(obs, tr[c]), c
-    # two 128^2 chains in full against the oracle
-    for c in rng.choice(np.flatnonzero(Lv == 128), size=2, replace=False):
-        c = int(c)
+    # one chain of every size (128^2, 256^2, 512^2) in full against the oracle:
+    # both lattices after 5000 steps and all 5000 records
+    for size in (128, 256, 512):
+        c = int(rng.choice(np.flatnonzero(Lv == size)))
         Lc, nb, so, to = pair(c)
         print(f"C4 chain {c} L={Lc} against the oracle", flush=True)
         s0 = oracle.init(Lc, oracle.INIT_RANDOM, 0.5, 1, c)

@@ -1,7 +1,8 @@
 """GPU parity of the replica-coded chains (sd_replica_run): each of the 64
 replicas, sharing seed and stream, equals bit for bit the single chain of its
-own (J, q) run by sd_run from the same start, and replica 0 the oracle; the
-per-replica observables equal sd_observe on the unpacked lattices."""
+own (J, q) run by the oracle and by sd_run from the same start; the
+per-replica observables equal the oracle's and sd_observe's on the unpacked
+lattices."""
 import numpy as np
 import pytest
 import torch
@@ -60,8 +61,10 @@ def test_replicas_equal_single_chains(oracle, L, k):
         assert np.array_equal(inputs.unpack_bits(s1.cpu().numpy(), L), got_s[r]), r
         assert np.array_equal(inputs.unpack_bits(t1.cpu().numpy(), L), got_t[r]), r
         assert np.array_equal(o1.cpu().numpy(), obs[r]), r
-    rs, rt, _ = oracle.run(starts[0], J[0], q[0], SEED, stream, step0, k)
-    assert np.array_equal(got_s[0], rs) and np.array_equal(got_t[0], rt)
+        # every replica directly against the oracle chain of its own (J, q)
+        rs, rt, _ = oracle.run(starts[r], J[r], q[r], SEED, stream, step0, k)
+        assert np.array_equal(got_s[r], rs) and np.array_equal(got_t[r], rt), r
+        assert np.array_equal(oracle.observe(rs, rt), obs[r]), r
 
 
 @pytest.mark.parametrize("L", [200, 256, 512])
