@@ -137,6 +137,25 @@ SD_API sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, doubl
                  uint32_t flags, void* hip_stream);
 
 /*
+ * sd_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, the same results bit for bit, and no allocation, ever.  Where
+ * sd_run keeps per-workgroup partial sums of recorded steps in a buffer it
+ * allocates once per (device, stream), this call uses a fixed array of
+ * 65536 int64 (512 KiB) that the library holds in device memory per device
+ * from load until the process ends; its device address is looked up once per
+ * device, on the first call.  That array is shared by every call on the
+ * device and keeps the last call's contents (each recorded half-step writes
+ * every slot it later reads), so calls that overlap on one device — on
+ * different streams or from different host threads — race and must not be
+ * made.  EINVAL: as sd_run, and a grid whose per-record partial sums (4 per
+ * workgroup) would not fit the array.
+ */
+SD_API sd_status sd_run_noalloc(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
+                                uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
+                                uint32_t flags, void* hip_stream);
+
+/*
  * Measure and fix how sd_run executes chains of this (L, layout) on the
  * current device: the single-workgroup LDS-resident kernel (workgroup size
  * 128/256/512, lattices up to the device's LDS) or one grid-wide launch per

@@ -37,6 +37,7 @@ SIGNATURES = {
     "sd_init": (_I32, [_VP, _I32, _I32, _I32, _F64, _U64, _U32, _VP]),
     "sd_half_step": (_I32, [_VP, _VP, _I32, _I32, _I32, _F64, _F64, _U64, _U32, _U32, _U32, _VP]),
     "sd_run": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
+    "sd_run_noalloc": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
     "sd_observe": (_I32, [_VP, _VP, _I32, _I32, _VP, _VP]),
     "sd_corr_row": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_corr_diag": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
@@ -179,6 +180,13 @@ def sd_run(sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs=None, 
     _run_sizes("sd_run", sigma, tau, L, layout, k_steps, obs, obs_every)
     _check(lib().sd_run(_ptr(sigma), _ptr(tau), L, layout, float(J), float(q), seed, stream, step0, k_steps,
                         _ptr(obs), obs_every, flags, _stream(hip_stream)))
+
+
+def sd_run_noalloc(sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs=None, obs_every=0, flags=0,
+                   hip_stream=None) -> None:
+    _run_sizes("sd_run_noalloc", sigma, tau, L, layout, k_steps, obs, obs_every)
+    _check(lib().sd_run_noalloc(_ptr(sigma), _ptr(tau), L, layout, float(J), float(q), seed, stream, step0, k_steps,
+                                _ptr(obs), obs_every, flags, _stream(hip_stream)))
 
 
 def sd_observe(sigma, tau, L, layout, out3, hip_stream=None) -> None:

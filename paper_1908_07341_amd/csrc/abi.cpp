@@ -200,13 +200,42 @@ Workspace* partials_workspace(hipStream_t st) {
     return w;
 }
 
-// The step loop behind sd_run.  The grid kernels of a recorded half-step B
-// leave per-workgroup partial sums in a device buffer of kPartialsWords
-// int64: the per-(device, stream) workspace (null under stream capture:
-// atomics into the records instead).
+// Scratch memory of sd_run_noalloc: a file-scope device array (each device
+// holds its own copy until the process ends), so that the call allocates
+// nothing.  Host code never uses the array's name as an address: its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+static __device__ __align__(256) int64_t scratch[kPartialsWords];
+
+sd_status scratch_ptr(const char* name, int64_t** out) {
+    static std::mutex mu;
+    static std::map<int, int64_t*> ptrs;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, name);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = ptrs.find(dev);
+    if (it != ptrs.end()) {
+        *out = it->second;
+        return SD_OK;
+    }
+    int64_t* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        return e != hipSuccess ? hip_fail(e, name) : fail(SD_EHIP, "%s: no device address for the scratch array", name);
+    ptrs[dev] = p;
+    *out = p;
+    return SD_OK;
+}
+
+// The step loop behind sd_run and sd_run_noalloc.  The grid kernels of a
+// recorded half-step B leave per-workgroup partial sums in a device buffer of
+// kPartialsWords int64: the per-(device, stream) workspace for sd_run (null
+// under stream capture: atomics into the records instead), the static scratch
+// array for sd_run_noalloc.
 sd_status run_chain(const char* name, void* sigma, void* tau, int32_t L, int32_t layout, double J, double q,
                     uint64_t seed, uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs,
-                    uint32_t obs_every, uint32_t flags, void* hip_stream) {
+                    uint32_t obs_every, uint32_t flags, void* hip_stream, bool no_alloc) {
     sd_status s = check_lattice(sigma, L, layout, name);
     if (s == SD_OK)
         s = check_lattice(tau, L, layout, name);
@@ -248,7 +277,11 @@ sd_status run_chain(const char* name, void* sigma, void* tau, int32_t L, int32_t
     hipError_t e = hipSuccess;
     int64_t* partials = nullptr;
     std::unique_lock<std::mutex> hold;   // keeps this call's use of the workspace contiguous on the stream
-    if (n_rec) {
+    if (n_rec && no_alloc) {
+        const sd_status ss = scratch_ptr(name, &partials);
+        if (ss != SD_OK)
+            return ss;
+    } else if (n_rec) {
         Workspace* ws = partials_workspace(st);
         if (ws) {
             hold = std::unique_lock<std::mutex>(ws->mu);
@@ -387,7 +420,14 @@ sd_status sd_run(void* sigma, void* tau, int32_t L, int32_t layout, double J, do
                  uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
                  uint32_t flags, void* hip_stream) {
     return run_chain("sd_run", sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs, obs_every, flags,
-                     hip_stream);
+                     hip_stream, false);
+}
+
+sd_status sd_run_noalloc(void* sigma, void* tau, int32_t L, int32_t layout, double J, double q, uint64_t seed,
+                         uint32_t stream, uint64_t step0, uint32_t k_steps, int64_t* obs, uint32_t obs_every,
+                         uint32_t flags, void* hip_stream) {
+    return run_chain("sd_run_noalloc", sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs, obs_every,
+                     flags, hip_stream, true);
 }
 
 sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,

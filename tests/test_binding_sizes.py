@@ -31,7 +31,7 @@ def test_lattice_calls_check_sizes(L, layout):
     _passes_size_check(sd.sd_init, ok, L, layout, sd.SD_INIT_UP)
     _size_error(sd.sd_half_step, ok, short, L, layout, 0, 0.5, 0.5, 1, 0, 0)
     _size_error(sd.sd_half_step, short, ok, L, layout, 0, 0.5, 0.5, 1, 0, 0)
-    for fn in (sd.sd_run,):
+    for fn in (sd.sd_run, sd.sd_run_noalloc):
         _size_error(fn, short, ok, L, layout, 0.5, 0.5, 1, 0, 0, 10)
         _size_error(fn, ok, short, L, layout, 0.5, 0.5, 1, 0, 0, 10)
         # 10 steps with a record every 3: 3 records of 24 bytes
