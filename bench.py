@@ -190,51 +190,80 @@ def parse():
 def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=512):
     """The five-point q = J sweep on 1024^2 int8 lattices: random start, 10^4
     steps per point with (M, A, B) every step and D(r <= 512) every 100 steps,
-    stream = point index.  A 1024^2 half-step is a few microseconds of kernel
-    time, so one chain is bound by launches; the points are independent and
-    run on a stream each, and also one after another on a single stream."""
+    stream = point index.  The five chains advance together through
+    sd_run_many (one launch per half-step for all of them, records fused into
+    half-step B); for comparison the same sweep with one sd_run per point, on
+    a stream each and on a single stream (a 1024^2 half-step alone fills a
+    small part of the device, so those are bound by launches)."""
     sd.sd_tune(L, sd.SD_I8, tune_cache)
     points = [0.2, 0.4, 0.6, 0.8, 1.0]
+    n_pts = len(points)
     n_blk = n_steps // corr_every
     lat = [(sd.new_lattice(L, sd.SD_I8), sd.new_lattice(L, sd.SD_I8)) for _ in points]
-    obs = torch.empty((len(points), n_steps, 3), dtype=torch.int64, device="cuda")
-    D = torch.empty((len(points), n_blk, rmax + 1), dtype=torch.int64, device="cuda")
+    obs = torch.empty((n_pts, n_steps, 3), dtype=torch.int64, device="cuda")
+    obs_blk = torch.empty((n_blk, n_pts, corr_every, 3), dtype=torch.int64, device="cuda")
+    D = torch.empty((n_pts, n_blk, rmax + 1), dtype=torch.int64, device="cuda")
     cur = torch.cuda.current_stream()
     side = [torch.cuda.Stream() for _ in points]
+    sigmas, taus = [x for x, _ in lat], [y for _, y in lat]
 
-    def sweep(streams):
+    def init():
         for a, (sigma, _) in enumerate(lat):
             sd.sd_init(sigma, L, sd.SD_I8, sd.SD_INIT_RANDOM, 0.5, 1, a)
         torch.cuda.synchronize()
+
+    def timed(body):
+        init()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(cur)
-        for st in set(streams):
-            st.wait_stream(cur)
-        for blk in range(n_blk):
-            for a, (qj, (sigma, tau)) in enumerate(zip(points, lat)):
-                sd.sd_run(sigma, tau, L, sd.SD_I8, qj, qj, 1, a, corr_every * blk, corr_every,
-                          obs[a, corr_every * blk:corr_every * (blk + 1)], 1, hip_stream=streams[a])
-                sd.sd_corr_row(sigma, L, sd.SD_I8, rmax, D[a, blk], hip_stream=streams[a])
-        for st in set(streams):
-            cur.wait_stream(st)
+        body()
         e1.record(cur)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    sweep([cur] * len(points))   # warm-up: first launches of every kernel and stream
-    ms_one = sweep([cur] * len(points))
-    ms = sweep(side)
-    updates = 2.0 * L * L * n_steps * len(points)
+    def many():
+        for blk in range(n_blk):
+            sd.sd_run_many(sigmas, taus, L, sd.SD_I8, points, points, 1, list(range(n_pts)), corr_every * blk,
+                           corr_every, obs_blk[blk], 1)
+            for a in range(n_pts):
+                sd.sd_corr_row(sigmas[a], L, sd.SD_I8, rmax, D[a, blk])
+
+    def per_point(streams):
+        def body():
+            for st in set(streams):
+                st.wait_stream(cur)
+            for blk in range(n_blk):
+                for a, (qj, (sigma, tau)) in enumerate(zip(points, lat)):
+                    sd.sd_run(sigma, tau, L, sd.SD_I8, qj, qj, 1, a, corr_every * blk, corr_every,
+                              obs[a, corr_every * blk:corr_every * (blk + 1)], 1, hip_stream=streams[a])
+                    sd.sd_corr_row(sigma, L, sd.SD_I8, rmax, D[a, blk], hip_stream=streams[a])
+            for st in set(streams):
+                cur.wait_stream(st)
+        return body
+
+    timed(many)   # warm-up: first launches of every kernel
+    ms_many = timed(many)
+    fin_many = [sigma.clone() for sigma in sigmas]
+    obs_many = obs_blk.permute(1, 0, 2, 3).reshape(n_pts, n_steps, 3).clone()
+    D_many = D.clone()
+    ms_one = timed(per_point([cur] * n_pts))
+    ms_streams = timed(per_point(side))
+    same = all(torch.equal(x, y) for x, y in zip(fin_many, sigmas)) and torch.equal(obs_many, obs) and \
+        torch.equal(D_many, D)
+    updates = 2.0 * L * L * n_steps * n_pts
     m_last = (obs[:, -1000:, 0].double().abs().mean(dim=1) / (L * L)).cpu().numpy()
     c1 = (D[:, -20:, 1].double().mean(dim=1) / (L * L)).cpu().numpy()
     return {"workload": f"{L}x{L} int8, q = J in {points}, random start, {n_steps} steps per point, "
                         f"(M, A, B) every step, D(r <= {rmax}) every {corr_every} steps",
-            "spin_updates_per_ns": updates / (ms * 1e6), "seconds": ms / 1e3, "streams": len(points),
-            "spin_updates_per_ns_one_stream": updates / (ms_one * 1e6),
+            "spin_updates_per_ns": updates / (ms_many * 1e6), "seconds": ms_many / 1e3,
+            "path": "sd_run_many: the five chains in one launch per half-step",
+            "hbm_algorithmic_GBps": 2.0 * updates / (ms_many * 1e-3) / 1e9,
+            "spin_updates_per_ns_sd_run_5_streams": updates / (ms_streams * 1e6),
+            "spin_updates_per_ns_sd_run_one_stream": updates / (ms_one * 1e6),
+            "identical_to_sd_run_per_point": bool(same),
             "D0_equals_L2": bool((D[:, :, 0] == L * L).all().item()),
             "abs_m_last_1000": [round(float(x), 4) for x in m_last],
-            "C1_row_last_20": [round(float(x), 4) for x in c1],
-            "run_choice": list(sd.sd_tuned_choice(L, sd.SD_I8))}
+            "C1_row_last_20": [round(float(x), 4) for x in c1]}
 
 
 PREROLL_S = 0.5   # untimed half-steps on scratch lattices before the timed region
@@ -589,13 +618,16 @@ def bench_loglik(sd, torch, n_traj=256, L=256, k=2000):
         with torch.no_grad():
             x += 0.5 * gg
     est = x.detach().cpu().numpy().tolist()
+    mle, se = _fp64_newton(ch)
+    within = bool(all(abs(e - t) < 3 * s_ for e, t, s_ in zip(est, (J, q), se)))
     del traj
     return {"workload": f"{n_traj} trajectories of {L}x{L}, {k} steps at (J,q)=({J},{q}), random starts",
             "transitions": int(N), "trajectory_GB": n_traj * n_lat * nb / 1e9, "generate_seconds": t_gen,
             "counts_ms": ms, "counts_GBps": gbs, "counts_hbm_frac": gbs / HBM_PEAK_GBS,
             "stats_ms": ms_st, "stats_GBps": gbs_st, "stats_hbm_frac": gbs_st / HBM_PEAK_GBS,
             "stats_equal_pair_map_of_counts": stats_consistent,
-            "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est}
+            "grad_rel_err_vs_fp64_at_start": rel, "ascent_estimate": est,
+            "fp64_mle": mle.tolist(), "standard_errors": se.tolist(), "ascent_within_3_se": within}
 
 
 def critical_J(q):
@@ -758,11 +790,9 @@ def bench_replicas(sd, torch, L, K):
 
 def bench_propp_wilson(sd, torch, L=32, n=512):
     """Exact samples of the stationary law by coupling from the past (the
-    Propp-Wilson sampler on the monotone coupling of section 3.2), at the kind
-    of points where the paper compares pi_s with the square-lattice Gibbs
-    measure: J below the square-lattice critical value, q growing.  Per point:
-    wall time, coalescence times, and the sample means of m, |m| and the
-    square-lattice bond sum per site -(1/L^2) sum_x s_x (s_right + s_up)."""
+    Propp-Wilson sampler on the monotone coupling of section 3.2) on a 32x32
+    torus at a few (q, J): per point the wall time, the coalescence times and
+    the sample means of m and |m|."""
     from paper_1908_07341_amd import inputs
     nb = sd.sd_lattice_bytes(L, sd.SD_P64)
     samples = torch.empty((n, nb), dtype=torch.uint8, device="cuda")
@@ -778,13 +808,11 @@ def bench_propp_wilson(sd, torch, L=32, n=512):
         host = samples.cpu().numpy()
         lat = np.stack([inputs.unpack_bits(host[p], L) for p in range(n)]).astype(np.int64)
         m = lat.mean(axis=(1, 2))
-        bonds = -(lat * (np.roll(lat, -1, axis=2) + np.roll(lat, -1, axis=1))).sum(axis=(1, 2)) / (L * L)
         ok = T > 0
         rows.append({"q": q, "J": J, "samples": n, "coalesced": int(ok.sum()), "seconds": dt,
                      "samples_per_s": n / dt, "mean_T": float(T[ok].mean()) if ok.any() else None,
                      "max_T": int(T.max()), "mean_m": float(m[ok].mean()), "mean_abs_m": float(np.abs(m[ok]).mean()),
-                     "sd_m": float(m[ok].std()), "mean_bond_sum_per_site": float(bonds[ok].mean()),
-                     "sd_bond_sum_per_site": float(bonds[ok].std())})
+                     "sd_m": float(m[ok].std())})
         log(f"[bench] propp-wilson q={q} J={J}: {n} samples in {dt:.2f} s, mean T {rows[-1]['mean_T']}")
     return {"workload": f"{L}x{L} torus, {n} samples per point, T from 16 doubling to at most 2^24, "
                         f"time 0 at step index 2^28, seed 1", "rows": rows, "seconds": time.perf_counter() - t_all}
@@ -832,17 +860,41 @@ def bench_table1(sd, torch, burn=2000, n_meas=4000, every=5, L=32):
             "seconds": time.perf_counter() - t0}
 
 
-def _fp64_grad(c, J, q):
+def _fp64_grad(c, J, q, exact=False):
+    """FP64 gradient of the LL of the 12 counts at (J, q), rounded to FP32
+    first unless exact (the point the FP32 kernels see)."""
+    if not exact:
+        J, q = float(np.float32(J)), float(np.float32(q))
     gJ = gq = 0.0
     for k in range(3):
         for cp in range(2):
             a, b = 2 * k - 2, 2 * cp - 1
-            h = float(np.float32(J)) * a + float(np.float32(q)) * b
+            h = J * a + q * b
             d = float(c[2 * (2 * k + cp) + 1] - c[2 * (2 * k + cp)])
             N = float(c[2 * (2 * k + cp) + 1] + c[2 * (2 * k + cp)])
             gJ += a * (d - N * math.tanh(h))
             gq += b * (d - N * math.tanh(h))
     return np.array([gJ, gq])
+
+
+def _fp64_hessian(c, J, q):
+    H = np.zeros((2, 2))
+    for k in range(3):
+        for cp in range(2):
+            a, b = 2 * k - 2, 2 * cp - 1
+            h = J * a + q * b
+            n = float(c[2 * (2 * k + cp)] + c[2 * (2 * k + cp) + 1])
+            H -= n / math.cosh(h) ** 2 * np.array([[a * a, a * b], [a * b, b * b]])
+    return H
+
+
+def _fp64_newton(c):
+    """FP64 maximum of the LL of the 12 counts (Newton from (0.2, 0.2)) and
+    its standard errors from the inverse Fisher information."""
+    theta = np.array([0.2, 0.2])
+    for _ in range(30):
+        theta = theta - np.linalg.solve(_fp64_hessian(c, *theta), _fp64_grad(c, *theta, exact=True))
+    return theta, np.sqrt(np.diag(np.linalg.inv(-_fp64_hessian(c, *theta))))
 
 
 def main():

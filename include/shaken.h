@@ -156,6 +156,28 @@ SD_API sd_status sd_run_noalloc(void* sigma, void* tau, int32_t L, int32_t layou
                                 uint32_t flags, void* hip_stream);
 
 /*
+ * n_chains (1..16) chains of one size and layout advanced together: chain a
+ * is exactly sd_run(sigma[a], tau[a], L, layout, J[a], q[a], seed,
+ * streams[a], step0, k_steps, ...), but every half-step of all the chains is
+ * one grid launch (the chains' words split into 64-word tiles, a share of
+ * the workgroups per chain), so that lattices of a few thousand words, which
+ * alone fill a small part of the device, run together at the launch rate of
+ * one.  sigma, tau: host arrays of n_chains device lattice pointers (no two of
+ * the 2 n_chains lattices may overlap); J, q, streams: host arrays of
+ * n_chains.  obs (device) NULL, or n_chains x (k_steps / obs_every) records
+ * of (M, A, B), chain-major: obs[3 * (a * (k_steps / obs_every) + r) + {0,1,2}]
+ * is sd_run's record r of chain a.  Records go through the same per-(device,
+ * stream) partial-sum buffer as sd_run (allocated on first use and kept), so
+ * a first call with records cannot be made under stream capture.  flags:
+ * SD_FLAG_COMPLEMENT_RNG, SD_FLAG_GENERAL_COMPARE.  EINVAL: bad sizes or
+ * pointers, overlapping lattices, obs without obs_every, step0 + k_steps
+ * above 2^29.
+ */
+SD_API sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, int32_t L, int32_t layout,
+                             const double* J, const double* q, uint64_t seed, const uint32_t* streams, uint64_t step0,
+                             uint32_t k_steps, int64_t* obs, uint32_t obs_every, uint32_t flags, void* hip_stream);
+
+/*
  * Measure and fix how sd_run executes chains of this (L, layout) on the
  * current device: the single-workgroup LDS-resident kernel (workgroup size
  * 128/256/512, lattices up to the device's LDS) or one grid-wide launch per

@@ -38,6 +38,7 @@ SIGNATURES = {
     "sd_half_step": (_I32, [_VP, _VP, _I32, _I32, _I32, _F64, _F64, _U64, _U32, _U32, _U32, _VP]),
     "sd_run": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
     "sd_run_noalloc": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP, _U32, _U32, _VP]),
+    "sd_run_many": (_I32, [_VP, _VP, _I32, _I32, _I32, _VP, _VP, _U64, _VP, _U64, _U32, _VP, _U32, _U32, _VP]),
     "sd_observe": (_I32, [_VP, _VP, _I32, _I32, _VP, _VP]),
     "sd_corr_row": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_corr_diag": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
@@ -187,6 +188,29 @@ def sd_run_noalloc(sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, ob
     _run_sizes("sd_run_noalloc", sigma, tau, L, layout, k_steps, obs, obs_every)
     _check(lib().sd_run_noalloc(_ptr(sigma), _ptr(tau), L, layout, float(J), float(q), seed, stream, step0, k_steps,
                                 _ptr(obs), obs_every, flags, _stream(hip_stream)))
+
+
+def sd_run_many(sigmas, taus, L, layout, J, q, seed, streams, step0, k_steps, obs=None, obs_every=0, flags=0,
+                hip_stream=None) -> None:
+    """Chains of one size advanced together; sigmas, taus: lists of device
+    lattices; J, q, streams: one value per chain; obs: [n, k_steps // obs_every, 3]."""
+    n = len(sigmas)
+    if not (len(taus) == len(J) == len(q) == len(streams) == n):
+        raise ValueError("sd_run_many: one sigma, tau, J, q and stream per chain")
+    for a in range(n):
+        _lattice(sigmas[a], L, layout, f"sd_run_many(sigma[{a}])")
+        _lattice(taus[a], L, layout, f"sd_run_many(tau[{a}])")
+    if obs is not None and obs_every:
+        _need(obs, 24 * n * (k_steps // obs_every), "sd_run_many(obs)")
+    sp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in sigmas])
+    tp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in taus])
+    Ja = (ctypes.c_double * max(n, 1))(*[float(x) for x in J])
+    qa = (ctypes.c_double * max(n, 1))(*[float(x) for x in q])
+    sa = (ctypes.c_uint32 * max(n, 1))(*[int(x) for x in streams])
+    _check(lib().sd_run_many(ctypes.cast(sp, ctypes.c_void_p), ctypes.cast(tp, ctypes.c_void_p), n, L, layout,
+                             ctypes.cast(Ja, ctypes.c_void_p), ctypes.cast(qa, ctypes.c_void_p), seed,
+                             ctypes.cast(sa, ctypes.c_void_p), step0, k_steps, _ptr(obs), obs_every, flags,
+                             _stream(hip_stream)))
 
 
 def sd_observe(sigma, tau, L, layout, out3, hip_stream=None) -> None:

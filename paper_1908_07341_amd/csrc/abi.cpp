@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -428,6 +429,106 @@ sd_status sd_run_noalloc(void* sigma, void* tau, int32_t L, int32_t layout, doub
                          uint32_t flags, void* hip_stream) {
     return run_chain("sd_run_noalloc", sigma, tau, L, layout, J, q, seed, stream, step0, k_steps, obs, obs_every,
                      flags, hip_stream, true);
+}
+
+sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, int32_t L, int32_t layout,
+                      const double* J, const double* q, uint64_t seed, const uint32_t* streams, uint64_t step0,
+                      uint32_t k_steps, int64_t* obs, uint32_t obs_every, uint32_t flags, void* hip_stream) {
+    const char* name = "sd_run_many";
+    if (n_chains < 1 || n_chains > (int32_t)kManyMax)
+        return fail(SD_EINVAL, "%s: n_chains must lie in [1, %u]", name, kManyMax);
+    if (!sigma || !tau || !J || !q || !streams)
+        return fail(SD_EINVAL, "%s: null host array", name);
+    const size_t bytes = lattice_bytes(L, layout);
+    for (int32_t a = 0; a < n_chains; ++a) {
+        sd_status s = check_lattice(sigma[a], L, layout, name);
+        if (s == SD_OK)
+            s = check_lattice(tau[a], L, layout, name);
+        if (s != SD_OK)
+            return s;
+        if (!std::isfinite(J[a]) || !std::isfinite(q[a]))
+            return fail(SD_EINVAL, "%s: J and q of chain %d must be finite", name, a);
+    }
+    // no two of the 2 n lattices may overlap
+    for (int32_t a = 0; a < 2 * n_chains; ++a)
+        for (int32_t b = a + 1; b < 2 * n_chains; ++b) {
+            const void* x = a < n_chains ? sigma[a] : tau[a - n_chains];
+            const void* y = b < n_chains ? sigma[b] : tau[b - n_chains];
+            if (overlap(x, y, bytes))
+                return fail(SD_EINVAL, "%s: lattices %d and %d overlap", name, a, b);
+        }
+    if (step0 + (uint64_t)k_steps > (1ull << 29))
+        return fail(SD_EINVAL, "%s: step indices must stay below 2^29", name);
+    if (obs && obs_every == 0)
+        return fail(SD_EINVAL, "%s: obs given without obs_every", name);
+    if (flags & ~(SD_FLAG_COMPLEMENT_RNG | SD_FLAG_GENERAL_COMPARE))
+        return fail(SD_EINVAL, "%s: unknown flags", name);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int klay;
+    if (layout == SD_I8) {
+        bool row = L % 64 == 0;
+        for (int32_t a = 0; a < n_chains; ++a)
+            row = row && kernel_layout(L, layout, sigma[a]) == kLayI8Row && kernel_layout(L, layout, tau[a]) == kLayI8Row;
+        klay = row ? kLayI8Row : kLayI8Any;
+    } else {
+        klay = kernel_layout(L, layout, sigma[0]);
+    }
+    const Geom G = make_geom(L, klay);
+    ManyChains mc;
+    std::memset(&mc, 0, sizeof mc);
+    bool paired = (flags & SD_FLAG_GENERAL_COMPARE) == 0;
+    for (int32_t a = 0; a < n_chains; ++a) {
+        mc.sigma[a] = sigma[a];
+        mc.tau[a] = tau[a];
+        threshold_table(J[a], q[a], mc.T[a]);
+        mc.stream[a] = streams[a];
+        paired = paired && thresholds_paired(mc.T[a]);
+    }
+    mc.n_chains = (uint32_t)n_chains;
+    mc.blocks_per_chain = many_blocks_per_chain(G);
+    const uint32_t n_rec = obs ? k_steps / obs_every : 0u;
+    const uint32_t stride = 4u * mc.blocks_per_chain * mc.n_chains;   // partial sums of one record
+    if (n_rec && stride > kPartialsWords)
+        return fail(SD_EINVAL, "%s: %u chains of %u workgroups need more partial sums per record than the %zu of "
+                    "the scratch buffer", name, mc.n_chains, mc.blocks_per_chain, kPartialsWords);
+    if (k_steps == 0)
+        return SD_OK;
+    int64_t* partials = nullptr;
+    std::unique_lock<std::mutex> hold;   // keeps this call's use of the workspace contiguous on the stream
+    if (n_rec) {
+        Workspace* ws = partials_workspace(st);
+        if (!ws)
+            return fail(SD_EHIP, "%s: no partial-sum buffer for this stream (stream capture before the first "
+                        "eager call on it, or out of device memory)", name);
+        hold = std::unique_lock<std::mutex>(ws->mu);
+        partials = ws->p;
+    }
+    DrawParams base = dynamics_params(0.0, 0.0, seed, 0u, 0u, flags & SD_FLAG_COMPLEMENT_RNG);
+    const uint32_t chunk = n_rec ? (uint32_t)(kPartialsWords / stride) : 1u;
+    const uint64_t obs_chain = 3ull * n_rec;
+    uint32_t pending = 0;
+    hipError_t e = hipSuccess;
+    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
+        const uint64_t n = step0 + m;
+        base.t = (uint32_t)(2 * n);
+        e = launch_half_step_many(klay, 0, mc, G, base, paired, nullptr, st);
+        if (e != hipSuccess)
+            break;
+        base.t = (uint32_t)(2 * n + 1);
+        const bool rec = n_rec && (m + 1) % obs_every == 0 && (m + 1) / obs_every <= n_rec;
+        e = launch_half_step_many(klay, 1, mc, G, base, paired, rec ? partials + (size_t)pending * stride : nullptr,
+                                  st);
+        if (rec && e == hipSuccess) {
+            const uint32_t r = (m + 1) / obs_every - 1;
+            ++pending;
+            if (pending == chunk || r + 1 == n_rec) {
+                e = launch_obs_finish_many(partials, mc.blocks_per_chain, mc.n_chains, pending, stride, obs,
+                                           obs_chain, r + 1 - pending, st);
+                pending = 0;
+            }
+        }
+    }
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
 }
 
 sd_status sd_observe(const void* sigma, const void* tau, int32_t L, int32_t layout, int64_t* out3,

@@ -306,6 +306,11 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         return fail(SD_EINVAL, "sd_batch_plan_create: unknown flags");
     if ((flags & SD_FLAG_MOMENTS) && !obs_every)
         return fail(SD_EINVAL, "sd_batch_plan_create: SD_FLAG_MOMENTS needs obs_every > 0");
+    for (int32_t c = 0; c < n_chains; ++c) {   // every descriptor before any device query
+        const sd_chain_desc& in = chains[c];
+        if (in.L < 8 || in.L > 65535 || in.L % 8 != 0 || !std::isfinite(in.J) || !std::isfinite(in.q))
+            return fail(SD_EINVAL, "sd_batch_plan_create: chain %d needs finite J, q and L a multiple of 8", c);
+    }
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess)

@@ -423,18 +423,19 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
     wave_sync_lds();
 }
 
+// One half-step of one chain by the workgroups block = 0 .. n_blocks - 1 of
+// a launch, each wavefront walking tiles of 64 * WPL words.
 // OBS (half-step B only): the workgroup sums of (#+1, #differences to the
 // up and right neighbours, #differences to the partner, #sites) go to
-// partials[4 * blockIdx.x ...] when partials is non-null (k_obs_finish turns
+// partials[4 * block ...] when partials is non-null (a finishing launch turns
 // them into M, A, B), else straight into obs through 64-bit atomics.
-template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
-__global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
-                                                   DrawParams dp, int64_t* __restrict__ obs,
-                                                   int64_t* __restrict__ partials) {
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS, int WPL>
+__device__ __forceinline__ void half_step_body(const void* __restrict__ src, void* __restrict__ dst, const Geom& G,
+                                               const DrawParams& dp, int64_t* __restrict__ obs,
+                                               int64_t* __restrict__ partials, uint32_t block, uint32_t n_blocks,
+                                               HalfStepScratch& sh, int64_t* red) {
     static_assert(!OBS || WHICH == 1, "observables are folded into half-step B");
-    constexpr uint32_t kWaveTile = 64u * words_per_lane(LAYOUT, PAIRED);
-    __shared__ HalfStepScratch sh;
-    __shared__ int64_t red[4 * 4];
+    constexpr uint32_t kWaveTile = 64u * WPL;
     ObsAcc acc;
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     const uint32_t lane = threadIdx.x & 63u;
@@ -454,10 +455,10 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
     // origins then stay in scalar registers)
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int kPartLayout = LAYOUT == kLayP64Rows ? kLayP64 : LAYOUT;
-    for (uint32_t tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
+    for (uint32_t tile = block * kWavesPerBlock + wave; tile < n_tiles; tile += n_blocks * kWavesPerBlock) {
         if (tile < n_full) {
-            half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, true, words_per_lane(LAYOUT, PAIRED)>(
-                src, dst, G, dp, pm, sh.T24, wl, tile * kWaveTile, lane, acc);
+            half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, true, WPL>(src, dst, G, dp, pm, sh.T24, wl,
+                                                                              tile * kWaveTile, lane, acc);
         } else {
             // the last, partial tile: 64 words at a time, with bounds checks
             for (uint32_t sub = tile * kWaveTile; sub < (tile + 1) * kWaveTile; sub += 64u)
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
         if (threadIdx.x == 0 && partials) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                partials[4u * blockIdx.x + i] = v[i];
+                partials[4u * block + i] = v[i];
         } else if (threadIdx.x == 0) {
             const int64_t n = v[3];
             atomicAdd(reinterpret_cast<unsigned long long*>(obs + 0), (unsigned long long)(2 * v[0] - n));
@@ -479,6 +480,40 @@ __global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src,
             atomicAdd(reinterpret_cast<unsigned long long*>(obs + 2), (unsigned long long)(n - 2 * v[2]));
         }
     }
+}
+
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
+__global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
+                                                   DrawParams dp, int64_t* __restrict__ obs,
+                                                   int64_t* __restrict__ partials) {
+    __shared__ HalfStepScratch sh;
+    __shared__ int64_t red[4 * 4];
+    half_step_body<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, words_per_lane(LAYOUT, PAIRED)>(
+        src, dst, G, dp, obs, partials, blockIdx.x, gridDim.x, sh, red);
+}
+
+// Several chains of one size advanced together: workgroups
+// chain * blocks_per_chain .. (chain + 1) * blocks_per_chain - 1 take the
+// half-step of chain `chain`, with its own lattices, threshold table and
+// stream id (the per-chain values are wavefront-uniform kernel arguments).
+// Tiles of 64 words (one word per lane) give lattices of a few thousand
+// words enough wavefronts.  Partial sums of recorded steps go to
+// partials[4 * workgroup ...], chain-major.
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
+__global__ __launch_bounds__(256) void k_half_step_many(ManyChains mc, Geom G, DrawParams base,
+                                                        int64_t* __restrict__ partials) {
+    __shared__ HalfStepScratch sh;
+    __shared__ int64_t red[4 * 4];
+    const uint32_t chain = blockIdx.x / mc.blocks_per_chain;
+    const uint32_t block = blockIdx.x - chain * mc.blocks_per_chain;
+    DrawParams dp = base;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        dp.T[i] = mc.T[chain][i];
+    dp.stream = mc.stream[chain];
+    half_step_body<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, 1>(
+        WHICH == 0 ? mc.sigma[chain] : mc.tau[chain], WHICH == 0 ? mc.tau[chain] : mc.sigma[chain], G, dp, nullptr,
+        partials + 4u * (size_t)chain * mc.blocks_per_chain, block, mc.blocks_per_chain, sh, red);
 }
 
 // Random initial lattice: site s is +1 iff r_s(t = 0, tag 1) < P, the same
@@ -538,6 +573,31 @@ __global__ __launch_bounds__(1024) void k_obs_finish(const int64_t* __restrict__
         o[0] += 2 * v[0] - n;
         o[1] += 2 * n - 2 * v[1];
         o[2] += n - 2 * v[2];
+    }
+}
+
+// Records of several chains: workgroup (r, a) = (blockIdx.x / n_chains,
+// blockIdx.x % n_chains) adds the n_blocks partials at
+// partials + r * stride + 4 * a * n_blocks into record r of chain a,
+// obs[a * obs_chain + 3 * (rec0 + r) ...].
+__global__ __launch_bounds__(256) void k_obs_finish_many(const int64_t* __restrict__ partials, uint32_t n_blocks,
+                                                         uint32_t n_chains, uint32_t stride, int64_t* __restrict__ obs,
+                                                         uint64_t obs_chain, uint32_t rec0) {
+    __shared__ int64_t red[4 * 4];
+    const uint32_t r = blockIdx.x / n_chains, a = blockIdx.x - r * n_chains;
+    const int64_t* p = partials + (size_t)r * stride + 4u * (size_t)a * n_blocks;
+    int64_t v[4] = {0, 0, 0, 0};
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] += p[4u * b + i];
+    block_sum_i64<4>(v, red);
+    if (threadIdx.x == 0) {
+        int64_t* o = obs + a * obs_chain + 3u * (size_t)(rec0 + r);
+        const int64_t n = v[3];
+        o[0] = 2 * v[0] - n;
+        o[1] = 2 * n - 2 * v[1];
+        o[2] = n - 2 * v[2];
     }
 }
 
@@ -620,6 +680,64 @@ hipError_t launch_half_step(int layout, int which, const void* src, void* dst, c
 #undef SD_HALF
     if (which == 1 && obs != nullptr && partials != nullptr && finish)
         hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(1024), 0, st, partials, blocks, 0u, obs);
+    return hipGetLastError();
+}
+
+template <int LAY, int WHICH, bool OBS>
+void launch_many_mode(bool paired, bool complement, dim3 grid, hipStream_t st, const ManyChains& mc, const Geom& G,
+                      const DrawParams& dp, int64_t* partials) {
+    if (paired && !complement)
+        hipLaunchKernelGGL((k_half_step_many<LAY, WHICH, true, false, OBS>), grid, dim3(256), 0, st, mc, G, dp,
+                           partials);
+    else if (paired)
+        hipLaunchKernelGGL((k_half_step_many<LAY, WHICH, true, true, OBS>), grid, dim3(256), 0, st, mc, G, dp,
+                           partials);
+    else if (!complement)
+        hipLaunchKernelGGL((k_half_step_many<LAY, WHICH, false, false, OBS>), grid, dim3(256), 0, st, mc, G, dp,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_half_step_many<LAY, WHICH, false, true, OBS>), grid, dim3(256), 0, st, mc, G, dp,
+                           partials);
+}
+
+uint32_t many_blocks_per_chain(const Geom& G) {
+    const uint32_t tiles = (G.n_groups + 63u) / 64u;
+    const uint32_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return blocks < kMaxBlocks ? (blocks ? blocks : 1u) : kMaxBlocks;
+}
+
+hipError_t launch_half_step_many(int layout, int which, const ManyChains& mc, const Geom& G, const DrawParams& base,
+                                 bool paired, int64_t* partials, hipStream_t st) {
+    const dim3 grid(mc.n_chains * mc.blocks_per_chain);
+    const bool complement = base.rng_xor != 0;
+    const int klay = (layout == kLayP64 && G.words_row % 64u == 0) ? kLayP64Rows : layout;
+#define SD_MANY(LAY)                                                                                       \
+    case LAY:                                                                                              \
+        if (which == 0)                                                                                    \
+            launch_many_mode<LAY, 0, false>(paired, complement, grid, st, mc, G, base, nullptr);          \
+        else if (partials == nullptr)                                                                      \
+            launch_many_mode<LAY, 1, false>(paired, complement, grid, st, mc, G, base, nullptr);          \
+        else                                                                                               \
+            launch_many_mode<LAY, 1, true>(paired, complement, grid, st, mc, G, base, partials);          \
+        break;
+    switch (klay) {
+        SD_MANY(kLayP64Rows)
+        SD_MANY(kLayP64)
+        SD_MANY(kLayP32)
+        SD_MANY(kLayI8Row)
+        SD_MANY(kLayI8Any)
+        SD_MANY(kLayBits)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef SD_MANY
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_finish_many(const int64_t* partials, uint32_t n_blocks, uint32_t n_chains, uint32_t n_rec,
+                                  uint32_t stride, int64_t* obs, uint64_t obs_chain, uint32_t rec0, hipStream_t st) {
+    hipLaunchKernelGGL(k_obs_finish_many, dim3(n_rec * n_chains), dim3(256), 0, st, partials, n_blocks, n_chains,
+                       stride, obs, obs_chain, rec0);
     return hipGetLastError();
 }
 

@@ -69,6 +69,31 @@ uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_b
 // sums at partials + r * stride.
 hipError_t launch_obs_finish(const int64_t* partials, uint32_t n_blocks, uint32_t n_rec, uint32_t stride,
                              int64_t* obs, hipStream_t st);
+// Several chains of one size and layout advanced together (sd_run_many):
+// per-chain lattices, threshold tables and stream ids; every chain's
+// half-step is done by blocks_per_chain workgroups of one launch.
+constexpr uint32_t kManyMax = 16;
+struct ManyChains {
+    void* sigma[kManyMax];
+    void* tau[kManyMax];
+    uint32_t T[kManyMax][6];
+    uint32_t stream[kManyMax];
+    uint32_t n_chains;
+    uint32_t blocks_per_chain;
+};
+// Workgroups per chain of a multi-chain half-step (64-word tiles, four per
+// workgroup, at most kMaxBlocks).
+uint32_t many_blocks_per_chain(const Geom& G);
+// which = 0: tau_a <- sigma_a, which = 1: sigma_a <- tau_a for every chain a;
+// with partials (which = 1 only) the workgroups of chain a leave their
+// partial sums at partials + 4 * (a * blocks_per_chain + block).
+hipError_t launch_half_step_many(int layout, int which, const ManyChains& mc, const Geom& G, const DrawParams& base,
+                                 bool paired, int64_t* partials, hipStream_t st);
+// Writes records rec0 .. rec0 + n_rec - 1 of every chain: record r of chain a
+// from the partials at partials + r * stride + 4 * a * n_blocks, into
+// obs + a * obs_chain + 3 * (rec0 + r).
+hipError_t launch_obs_finish_many(const int64_t* partials, uint32_t n_blocks, uint32_t n_chains, uint32_t n_rec,
+                                  uint32_t stride, int64_t* obs, uint64_t obs_chain, uint32_t rec0, hipStream_t st);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
                        hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);

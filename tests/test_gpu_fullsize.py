@@ -13,7 +13,9 @@ benchmark times, on outputs the oracle can compute one by one:
 * the differentiation workload (256 trajectories of 256^2, 2000 steps):
   trajectory 0 lattice by lattice and its counts and paired statistics
   against the oracle; for the whole set, the site total, the pair map of
-  the counts and the FP32 LL and gradient against FP64 from the counts."""
+  the counts, the FP32 LL and gradient against FP64 from the counts, FP64
+  finite differences, and the gradient ascent recovering (0.45, 0.7) within
+  three Fisher-information standard errors."""
 import os
 
 import numpy as np
@@ -168,6 +170,55 @@ def test_C5_full_loglik_sampled(oracle):
             gg = g.cpu().numpy().astype(np.float64)
             for i in range(2):
                 assert abs(gg[i] - g64[i]) <= 1e-5 * abs(g64[i]) + 1e-9 * scale, (Jp, qp, i, gg[i], g64[i])
+    # FP64 finite differences of the LL of the full counts (5-point stencil,
+    # step 1e-4) against the FP64 analytic gradient, at the ascent start and
+    # at the generating point
+    eps = 1e-4
+    for Jp, qp in ((0.2, 0.2), (0.45, 0.7)):
+        g64 = oracle.loglik_grad(ch, Jp, qp)
+
+        def fd(dJ, dq):
+            f = [oracle.loglik(ch, Jp + m * dJ, qp + m * dq) for m in (-2, -1, 1, 2)]
+            return (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / 12.0
+
+        scale = 2.0 * float(ch.sum())
+        assert abs(fd(eps, 0) / eps - g64[0]) <= 1e-7 * scale, (Jp, qp)
+        assert abs(fd(0, eps) / eps - g64[1]) <= 1e-7 * scale, (Jp, qp)
+    # the generating (J, q) recovered within three standard errors: FP32
+    # gradient ascent on LL / N through the backward kernel, against the FP64
+    # Newton maximum of the same counts and its Fisher-information errors
+    N = float(ch.sum())
+    x = torch.tensor([0.2, 0.2], dtype=torch.float32, device="cuda", requires_grad=True)
+    for _ in range(300):
+        (gg,) = torch.autograd.grad(AG.loglik(x, stats) / N, x)
+        with torch.no_grad():
+            x += 0.5 * gg
+    est = x.detach().cpu().numpy().astype(np.float64)
+    mle, se = _newton_mle(oracle, ch)
+    print(f"C5 ascent {est}, FP64 MLE {mle}, standard errors {se}", flush=True)
+    assert np.all(np.abs(mle - np.array([J, q])) < 3 * se), (mle, se)
+    assert np.all(np.abs(est - np.array([J, q])) < 3 * se), (est, se)
+    assert np.all(np.abs(est - mle) < 0.5 * se), (est, mle, se)
+
+
+def _hessian(c, J, q):
+    """FP64 Hessian of the LL of the 12 counts: -sum n sech^2 h (a, b)(a, b)^T
+    with a = 2k - 2, b = 2c - 1 the coefficients of J and q in h."""
+    H = np.zeros((2, 2))
+    for k in range(3):
+        for cp in range(2):
+            a, b = 2 * k - 2, 2 * cp - 1
+            h = J * a + q * b
+            n = float(c[2 * (2 * k + cp)] + c[2 * (2 * k + cp) + 1])
+            H -= n / np.cosh(h) ** 2 * np.array([[a * a, a * b], [a * b, b * b]])
+    return H
+
+
+def _newton_mle(oracle, c):
+    theta = np.array([0.2, 0.2])
+    for _ in range(30):
+        theta = theta - np.linalg.solve(_hessian(c, *theta), oracle.loglik_grad(c, *theta))
+    return theta, np.sqrt(np.diag(np.linalg.inv(-_hessian(c, *theta))))
 
 
 def test_C2_full_length_point(oracle):

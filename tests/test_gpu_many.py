@@ -1,0 +1,148 @@
+"""GPU parity of sd_run_many (several chains of one size, one launch per
+half-step for all of them) through the C ABI: every chain's lattices and
+records equal sd_run's for the same chain, bit for bit, on every layout and
+kernel family (int8 rows and generic int8, 64-bit words with and without
+row-aligned 64-word chunks, bit strings, 32-bit words); a small case and the
+1024^2 int8 sweep prefix also directly against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1908_07341_amd as sd
+from paper_1908_07341_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x9E3779B97F4A7C15
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sd.lib()
+
+
+def to_device(lat, layout):
+    L = lat.shape[0]
+    t = sd.new_lattice(L, layout)
+    if layout == sd.SD_I8:
+        t.copy_(torch.from_numpy(np.ascontiguousarray(lat, dtype=np.int8)))
+    else:
+        t.view(torch.uint8).view(-1).copy_(torch.from_numpy(inputs.pack_bits(lat)))
+    return t
+
+
+def to_host(t, L, layout):
+    torch.cuda.synchronize()
+    if layout == sd.SD_I8:
+        return t.cpu().numpy().astype(np.int8)
+    return inputs.unpack_bits(t.cpu().numpy(), L)
+
+
+# a spread of tables, the degenerate ones (h = 0 classes) and a negative J included
+PARAMS = [(0.4, 0.6), (0.0, 0.0), (0.5, 1.0), (0.8, 0.0), (-0.3, 0.5), (1.2, 0.2), (0.0, 0.7)]
+
+
+@pytest.mark.parametrize("L,layout,n,step0,k,every,flags", [
+    (1024, sd.SD_I8, 5, 0, 7, 1, 0),           # int8 rows, the sweep's shape
+    (96, sd.SD_I8, 3, 17, 10, 3, 0),           # generic int8 (rows of 1.5 groups)
+    (17, sd.SD_I8, 2, 5, 6, 4, 0),             # generic int8, odd L
+    (4096, sd.SD_P64, 3, 2, 4, 2, 0),          # 64-bit words, row-aligned 64-word chunks
+    (1024, sd.SD_P64, 4, 0, 6, 1, 0),          # 64-bit words, 16 words per row
+    (200, sd.SD_P64, 7, 9, 8, 3, 0),           # bit string (rows off word boundaries)
+    (96, sd.SD_P32, 2, 1, 5, 1, 0),            # 32-bit words
+    (1024, sd.SD_I8, 3, 3, 5, 2, sd.SD_FLAG_GENERAL_COMPARE),
+    (256, sd.SD_P64, 2, 0, 4, 1, sd.SD_FLAG_COMPLEMENT_RNG),
+    (2048, sd.SD_P64, 16, 0, 2, 1, 0),         # the largest number of chains
+])
+def test_many_equals_sd_run(L, layout, n, step0, k, every, flags):
+    print(f"sd_run_many L={L} layout={layout} n={n} k={k} every={every} flags={flags}", flush=True)
+    starts = [inputs.random_lattice(L, 700 + a) for a in range(n)]
+    J = [PARAMS[a % len(PARAMS)][0] for a in range(n)]
+    q = [PARAMS[a % len(PARAMS)][1] for a in range(n)]
+    streams = [11 * a + 3 for a in range(n)]
+    sig = [to_device(s0, layout) for s0 in starts]
+    tau = [sd.new_lattice(L, layout) for _ in range(n)]
+    n_rec = k // every
+    obs = torch.full((n, n_rec, 3), -7, dtype=torch.int64, device="cuda")
+    sd.sd_run_many(sig, tau, L, layout, J, q, SEED, streams, step0, k, obs, every, flags)
+    torch.cuda.synchronize()
+    for a in range(n):
+        s1, t1 = to_device(starts[a], layout), sd.new_lattice(L, layout)
+        o1 = torch.full((max(n_rec, 1), 3), -7, dtype=torch.int64, device="cuda")
+        sd.sd_run(s1, t1, L, layout, J[a], q[a], SEED, streams[a], step0, k, o1, every,
+                  flags | sd.SD_FLAG_GLOBAL_KERNELS)
+        torch.cuda.synchronize()
+        assert torch.equal(s1, sig[a]) and torch.equal(t1, tau[a]), a
+        assert torch.equal(o1[:n_rec], obs[a]), a
+
+
+def test_many_without_records_and_zero_steps():
+    L, layout, n = 1024, sd.SD_I8, 3
+    starts = [inputs.random_lattice(L, 40 + a) for a in range(n)]
+    sig = [to_device(s0, layout) for s0 in starts]
+    tau = [sd.new_lattice(L, layout) for _ in range(n)]
+    before = [t.clone() for t in sig]
+    sd.sd_run_many(sig, tau, L, layout, [0.5] * n, [0.5] * n, 1, [0, 1, 2], 0, 0)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(sig, before))
+    sd.sd_run_many(sig, tau, L, layout, [0.5] * n, [0.5] * n, 1, [0, 1, 2], 0, 9)
+    for a in range(n):
+        s1, t1 = to_device(starts[a], layout), sd.new_lattice(L, layout)
+        sd.sd_run(s1, t1, L, layout, 0.5, 0.5, 1, a, 0, 9)
+        torch.cuda.synchronize()
+        assert torch.equal(s1, sig[a]) and torch.equal(t1, tau[a]), a
+
+
+def test_many_small_case_against_oracle(oracle):
+    L, layout, n, k, every = 96, sd.SD_I8, 3, 7, 2
+    starts = [inputs.random_lattice(L, 300 + a) for a in range(n)]
+    J, q = [0.3, 0.7, 0.0], [0.9, 0.2, 0.0]
+    sig = [to_device(s0, layout) for s0 in starts]
+    tau = [sd.new_lattice(L, layout) for _ in range(n)]
+    obs = torch.zeros((n, k // every, 3), dtype=torch.int64, device="cuda")
+    sd.sd_run_many(sig, tau, L, layout, J, q, SEED, [5, 6, 7], 4, k, obs, every)
+    for a in range(n):
+        rs, rt, ro = oracle.run(starts[a], J[a], q[a], SEED, 5 + a, 4, k, obs_every=every)
+        assert np.array_equal(to_host(sig[a], L, layout), rs), a
+        assert np.array_equal(to_host(tau[a], L, layout), rt), a
+        assert np.array_equal(obs[a].cpu().numpy(), ro), a
+
+
+def test_C2_prefix_sweep_many_against_oracle(oracle):
+    # the 1024^2 int8 sweep (q = J on five points, stream = point index) as
+    # the benchmark runs it: one sd_run_many for the five chains, records every
+    # step, then D(r <= 512) of every chain, against the oracle
+    L, k = 1024, 6
+    points = [0.2, 0.4, 0.6, 0.8, 1.0]
+    s0 = oracle.init(L, oracle.INIT_RANDOM, 0.5, 1, 0)
+    sig = [to_device(oracle.init(L, oracle.INIT_RANDOM, 0.5, 1, a), sd.SD_I8) for a in range(5)]
+    tau = [sd.new_lattice(L, sd.SD_I8) for _ in range(5)]
+    obs = torch.zeros((5, k, 3), dtype=torch.int64, device="cuda")
+    sd.sd_run_many(sig, tau, L, sd.SD_I8, points, points, 1, list(range(5)), 0, k, obs, 1)
+    D = torch.zeros((5, 513), dtype=torch.int64, device="cuda")
+    for a in range(5):
+        sd.sd_corr_row(sig[a], L, sd.SD_I8, 512, D[a])
+    for a, J in enumerate(points):
+        print(f"C2 prefix through sd_run_many, J=q={J}", flush=True)
+        start = s0 if a == 0 else oracle.init(L, oracle.INIT_RANDOM, 0.5, 1, a)
+        rs, rt, ro = oracle.run(start, J, J, 1, a, 0, k, obs_every=1)
+        assert np.array_equal(obs[a].cpu().numpy(), ro), a
+        assert np.array_equal(to_host(sig[a], L, sd.SD_I8), rs), a
+        assert np.array_equal(D[a].cpu().numpy(), oracle.corr_row(rs, 512)), a
+
+
+def test_many_rejects_bad_arguments():
+    L, layout = 64, sd.SD_P64
+    a, b, c = (sd.new_lattice(L, layout) for _ in range(3))
+    with pytest.raises(sd.ShakenError):   # sigma of chain 1 is tau of chain 0
+        sd.sd_run_many([a, b], [b, c], L, layout, [0.5, 0.5], [0.5, 0.5], 1, [0, 1], 0, 2)
+    with pytest.raises(sd.ShakenError):   # 17 chains
+        lats = [sd.new_lattice(L, layout) for _ in range(34)]
+        sd.sd_run_many(lats[:17], lats[17:], L, layout, [0.5] * 17, [0.5] * 17, 1, list(range(17)), 0, 2)
+    with pytest.raises(sd.ShakenError):   # non-finite J
+        sd.sd_run_many([a], [b], L, layout, [float("inf")], [0.5], 1, [0], 0, 2)
+    with pytest.raises(sd.ShakenError):   # records without an interval
+        obs = torch.zeros((1, 2, 3), dtype=torch.int64, device="cuda")
+        sd.sd_run_many([a], [b], L, layout, [0.5], [0.5], 1, [0], 0, 2, obs, 0)
