@@ -158,7 +158,8 @@ def parse():
     p.add_argument("--no-replicas", action="store_true", help="skip the replica-coded chains leg")
     p.add_argument("--no-c2", action="store_true", help="skip the 1024^2 int8 sweep leg")
     p.add_argument("--batch-steps", type=int, default=5000)
-    p.add_argument("--plain-sample", type=int, default=24, help="chains timed one sd_run each")
+    p.add_argument("--plain-sample", type=int, default=32, help="chains per lattice size timed one sd_run each")
+    p.add_argument("--plain-full", action="store_true", help="time all 4096 chains one sd_run each")
     p.add_argument("--cpu-steps", type=int, default=2)
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_07341_amd", "tune_cache.json"))
     p.add_argument("--calibrate-copy", action="store_true",
@@ -488,7 +489,13 @@ def bench_cpu_plan(n_c5=8):
     return {"cpu_model": cpu_model(), "host_cpus": len(cores), "kind": "oracle", "jobs": results}
 
 
-def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
+def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache, plain_full=False):
+    """The (q, J) scan as one hipGraph launch of the batch plan, its load
+    balance (from a direct run with per-bucket times), and the same chains run
+    one sd_run each ("plain launches"), back to back with one synchronisation
+    at the end, on one stream and on four: all 4096 chains with plain_full,
+    else plain_sample chains per lattice size with the time scaled to the
+    whole scan per size."""
     qv, Jv, Lv = inputs.scan_table()
     n = len(qv)
     streams = np.arange(n, dtype=np.uint32)
@@ -520,50 +527,85 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     batch_rate = n * K / t_batch
-    # plain: the same chains, one sd_run each (with sd_run's launch choice tuned
-    # for each size), on a sample covering every size
+    # load balance: the same run as plain launches with per-bucket start/end
+    graph_lat, graph_tr = lat.clone(), traces.clone()
+    lat.copy_(start)
+    sd.sd_batch_run_direct(plan, lat, traces, 0)
+    torch.cuda.synchronize()
+    times = [sd.sd_batch_bucket_times(plan, i) for i in range(len(shapes))]
+    span = max(e for _, e in times)
+    busy = sum(e - s_ for s_, e in times)
+    same_direct = bool(torch.equal(lat, graph_lat) and torch.equal(traces, graph_tr))
+    # plain: one sd_run per chain (sd_run's launch choice tuned for each size)
     for size in sorted(set(Lv.tolist())):
         sd.sd_tune(int(size), sd.SD_P64, tune_cache)
-    rng = np.random.default_rng(0)
-    sample = []
     sizes = sorted(set(Lv.tolist()))
-    for size in sizes:
-        idx = np.flatnonzero(Lv == size)
-        per_size = max(1, plain_sample // len(sizes))
-        sample += rng.choice(idx, size=min(per_size, len(idx)), replace=False).tolist()
-    sample_cost = 0.0
-    identical = True
-    t_plain = 0.0
+    if plain_full:
+        sample = list(range(n))
+    else:
+        rng = np.random.default_rng(0)
+        sample = []
+        for size in sizes:
+            idx = np.flatnonzero(Lv == size)
+            sample += rng.choice(idx, size=min(plain_sample, len(idx)), replace=False).tolist()
+    bufs = []
     for c in sample:
         Lc = int(Lv[c])
         nb = sd.sd_lattice_bytes(Lc, sd.SD_P64)
-        so, to = sd.sd_batch_chain_offset(plan, c, 0), sd.sd_batch_chain_offset(plan, c, 1)
-        sig = start[so:so + nb].clone().view(torch.int64)
-        tau = torch.empty_like(sig)
-        obs = torch.empty((K, 3), dtype=torch.int64, device="cuda")
+        so = sd.sd_batch_chain_offset(plan, c, 0)
+        bufs.append((c, Lc, start[so:so + nb].clone().view(torch.int64),
+                     torch.empty(nb // 8, dtype=torch.int64, device="cuda"),
+                     torch.empty((K, 3), dtype=torch.int64, device="cuda")))
+    cur = torch.cuda.current_stream()
+    side = [torch.cuda.Stream() for _ in range(4)]
+
+    def plain(n_streams):
+        for c, Lc, sig, tau, obs in bufs:
+            so = sd.sd_batch_chain_offset(plan, c, 0)
+            sig.view(torch.uint8).copy_(start[so:so + sig.numel() * 8])
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sd.sd_run(sig, tau, Lc, sd.SD_P64, float(Jv[c]), float(qv[c]), seed, int(streams[c]), 0, K, obs, 1)
+        sts = [cur] if n_streams == 1 else side[:n_streams]
+        for st in sts:
+            st.wait_stream(cur)
+        t_start = time.perf_counter()
+        for i, (c, Lc, sig, tau, obs) in enumerate(bufs):
+            sd.sd_run(sig, tau, Lc, sd.SD_P64, float(Jv[c]), float(qv[c]), seed, int(streams[c]), 0, K, obs, 1,
+                      hip_stream=sts[i % len(sts)])
+        for st in sts:
+            cur.wait_stream(st)
         torch.cuda.synchronize()
-        t_plain += time.perf_counter() - t0
-        sample_cost += Lc * Lc
-        identical &= bool(torch.equal(sig, lat[so:so + nb].view(torch.int64)))
-        identical &= bool(torch.equal(obs.view(-1), traces.view(n, K * 3)[c]))
-    # scale the sample's time to the whole batch by lattice area
+        return time.perf_counter() - t_start
+
+    t1 = plain(1)
+    t4 = plain(4)
+    identical = True
+    tr = traces.view(n, K * 3)
+    for c, Lc, sig, tau, obs in bufs:
+        so = sd.sd_batch_chain_offset(plan, c, 0)
+        identical &= bool(torch.equal(sig.view(torch.uint8), lat[so:so + sig.numel() * 8]))
+        identical &= bool(torch.equal(obs.view(-1), tr[c]))
+    # the sample's time scaled to the whole scan by lattice area
     total_cost = float((Lv.astype(np.float64) ** 2).sum())
-    plain_est = t_plain * total_cost / sample_cost
-    plain_rate = n * K / plain_est
+    sample_cost = float(sum(Lc * Lc for _, Lc, _, _, _ in bufs))
+    scale = total_cost / sample_cost
+    plain1, plain4 = t1 * scale, t4 * scale
     plan.close()
     return {
         "workload": f"{n} chains, q in [0,2] x J in [0,1.5] on a 64x64 grid, L from {{128,256,512}} "
                     f"(numpy default_rng(1)), packed-64, random starts, {K} steps, (M,A,B) every step",
         "chain_steps_per_s": batch_rate, "seconds": t_batch,
-        "plain_chain_steps_per_s": plain_rate, "plain_seconds_estimated": plain_est,
-        "plain_sample_chains": len(sample), "plain_sample_seconds": t_plain,
-        "speedup_vs_plain": batch_rate / plain_rate, "bit_identical_on_sample": identical,
-        "spin_updates_per_ns": 2.0 * float((Lv.astype(np.float64) ** 2).sum()) * K / t_batch / 1e9,
-        "plan_seconds": t_plan, "launch_shapes": [list(s) for s in shapes],
-        "plain_run_choices": {int(z): list(sd.sd_tuned_choice(int(z), sd.SD_P64)) for z in sorted(set(Lv.tolist()))},
+        "spin_updates_per_ns": 2.0 * total_cost * K / t_batch / 1e9,
+        "load_balance": {"bucket_start_end_ms": [[round(s_, 2), round(e, 2)] for s_, e in times],
+                         "span_ms": span, "efficiency": busy / (len(times) * span),
+                         "direct_run_identical_to_graph": same_direct},
+        "plain": {"chains_run": len(bufs), "all_chains": bool(plain_full),
+                  "seconds_one_stream": t1, "seconds_four_streams": t4,
+                  "scan_seconds_one_stream": plain1, "scan_seconds_four_streams": plain4,
+                  "chain_steps_per_s_one_stream": n * K / plain1, "chain_steps_per_s_four_streams": n * K / plain4,
+                  "scaled_by_area": not plain_full, "bit_identical": identical},
+        "speedup_vs_plain_one_stream": plain1 / t_batch, "speedup_vs_plain_four_streams": plain4 / t_batch,
+        "plan_seconds": t_plan, "launch_shapes": [list(s_) for s_ in shapes],
+        "plain_run_choices": {int(z): list(sd.sd_tuned_choice(int(z), sd.SD_P64)) for z in sizes},
     }
 
 
@@ -987,11 +1029,13 @@ def main():
         log(f"[bench] sweep {out['int8_sweep']['spin_updates_per_ns']:.0f} spin updates/ns")
     if not args.no_batch:
         log(f"[bench] batched scan, {args.batch_steps} steps")
-        out["batched_scan"] = bench_batched(sd, torch, inputs, args.batch_steps, args.plain_sample, args.tune_cache)
+        out["batched_scan"] = bench_batched(sd, torch, inputs, args.batch_steps, args.plain_sample, args.tune_cache,
+                                            args.plain_full)
         # how close the three concurrent buckets come to the single large chain, per spin update
         out["batched_scan"]["rate_vs_single_chain"] = out["batched_scan"]["spin_updates_per_ns"] / value
         log(f"[bench] batched {out['batched_scan']['chain_steps_per_s']:.3g} chain-steps/s, "
-            f"x{out['batched_scan']['speedup_vs_plain']:.1f} vs plain")
+            f"x{out['batched_scan']['speedup_vs_plain_four_streams']:.1f} vs plain on 4 streams, load balance "
+            f"{out['batched_scan']['load_balance']['efficiency']:.3f}")
     if not args.no_loglik:
         log("[bench] log-likelihood")
         out["loglik"] = bench_loglik(sd, torch)

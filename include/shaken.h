@@ -446,6 +446,17 @@ SD_API sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* trac
 SD_API sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_t* traces, uint64_t step0,
                                      void* hip_stream);
 
+/*
+ * Times of bucket `bucket` (the order of sd_batch_launch_shape) in the last
+ * sd_batch_run_direct of the plan, in ms from the start of that run: when its
+ * persistent launch started and when it ended.  A launch takes chains of its
+ * own size first, then of the later (smaller) buckets of the same kernel
+ * form, so that no bucket's workgroups wait while another's queue still holds
+ * chains.  Synchronises with that run.  EINVAL: no such bucket, null outputs,
+ * or no direct run yet.
+ */
+SD_API sd_status sd_batch_bucket_times(sd_batch_plan* plan, int32_t bucket, float* start_ms, float* end_ms);
+
 /* Free a plan (NULL is ignored).  Synchronises with nothing; the caller must
  * not destroy a plan whose graph is still executing. */
 SD_API void sd_batch_plan_destroy(sd_batch_plan* plan);

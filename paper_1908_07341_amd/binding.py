@@ -53,6 +53,7 @@ SIGNATURES = {
     "sd_batch_run": (_I32, [_VP, _VP, _VP, _U64, _VP]),
     "sd_batch_run_direct": (_I32, [_VP, _VP, _VP, _U64, _VP]),
     "sd_batch_plan_destroy": (None, [_VP]),
+    "sd_batch_bucket_times": (_I32, [_VP, _I32, ctypes.POINTER(_F32), ctypes.POINTER(_F32)]),
     "sd_trajectory": (_I32, [_VP, _VP, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP]),
     "sd_trajectories": (_I32, [_VP, _VP, _I32, _I32, _I32, _F64, _F64, _U64, _U32, _U64, _U32, _VP]),
     "sd_loglik_counts": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
@@ -398,6 +399,13 @@ def sd_batch_run(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None
 def sd_batch_run_direct(plan: sd_batch_plan, lattices, traces, step0=0, hip_stream=None) -> None:
     _batch_sizes("sd_batch_run_direct", plan, lattices, traces)
     _check(lib().sd_batch_run_direct(plan.handle, _ptr(lattices), _ptr(traces), step0, _stream(hip_stream)))
+
+
+def sd_batch_bucket_times(plan: sd_batch_plan, bucket: int):
+    """(start_ms, end_ms) of a bucket's launch in the plan's last direct run."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    _check(lib().sd_batch_bucket_times(plan.handle, bucket, ctypes.byref(a), ctypes.byref(b)))
+    return float(a.value), float(b.value)
 
 
 def sd_batch_plan_destroy(plan: sd_batch_plan) -> None:

@@ -508,7 +508,53 @@ sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, in
     const uint64_t obs_chain = 3ull * n_rec;
     uint32_t pending = 0;
     hipError_t e = hipSuccess;
-    for (uint32_t m = 0; m < k_steps && e == hipSuccess; ++m) {
+    // Rows of at most 64 words: whole steps in one launch each (bands with a
+    // halo row, sigma alternating between the two lattices of each chain) for
+    // an even number of steps, so that sigma ends where it started; the last
+    // one or two steps take the half-step kernels, which leave tau in place.
+    const uint32_t R = band_rows(L);
+    const bool band_ok = R != 0 && (layout == SD_P64 || klay == kLayI8Row) && k_steps >= 3 &&
+                         4ull * ((uint32_t)L / R) * mc.n_chains <= kPartialsWords;
+    const uint32_t n_fused = band_ok ? k_steps - (k_steps % 2 ? 1u : 2u) : 0u;
+    if (n_fused) {
+        BandArgs ba;
+        std::memset(&ba, 0, sizeof ba);
+        for (int32_t a = 0; a < n_chains; ++a) {
+            std::memcpy(ba.T[a], mc.T[a], sizeof ba.T[a]);
+            ba.stream[a] = mc.stream[a];
+        }
+        ba.n_chains = mc.n_chains;
+        ba.L = (uint32_t)L;
+        ba.W = (uint32_t)L / 64u;
+        ba.R = R;
+        ba.bands = (uint32_t)L / R;
+        ba.divW = make_fastdiv(ba.W);
+        ba.key0 = base.key0;
+        ba.key1 = base.key1;
+        const uint32_t stride_b = 4u * ba.bands * ba.n_chains;
+        const uint32_t chunk_b = (uint32_t)(kPartialsWords / stride_b);
+        const bool complement = (flags & SD_FLAG_COMPLEMENT_RNG) != 0;
+        for (uint32_t m = 0; m < n_fused && e == hipSuccess; ++m) {
+            for (int32_t a = 0; a < n_chains; ++a) {
+                ba.src[a] = m % 2 ? tau[a] : sigma[a];
+                ba.dst[a] = m % 2 ? sigma[a] : tau[a];
+            }
+            ba.t0 = (uint32_t)(2 * (step0 + m));
+            const bool rec = n_rec && (m + 1) % obs_every == 0;
+            e = launch_band_step(ba, layout == SD_I8, paired, complement,
+                                 rec ? partials + (size_t)pending * stride_b : nullptr, st);
+            if (rec && e == hipSuccess) {
+                const uint32_t r = (m + 1) / obs_every - 1;
+                ++pending;
+                if (pending == chunk_b || m + obs_every >= n_fused) {
+                    e = launch_obs_finish_many(partials, ba.bands, mc.n_chains, pending, stride_b, obs, obs_chain,
+                                               r + 1 - pending, st);
+                    pending = 0;
+                }
+            }
+        }
+    }
+    for (uint32_t m = n_fused; m < k_steps && e == hipSuccess; ++m) {
         const uint64_t n = step0 + m;
         base.t = (uint32_t)(2 * n);
         e = launch_half_step_many(klay, 0, mc, G, base, paired, nullptr, st);

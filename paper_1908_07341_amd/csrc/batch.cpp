@@ -45,6 +45,9 @@ struct sd_batch_plan {
     hipStream_t capture = nullptr;   // stream the graph is captured on
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> events;
+    // timing of the last direct run: the fork, then each bucket's start and end
+    std::vector<hipEvent_t> timing;
+    bool timed = false;
 };
 
 namespace sd {
@@ -93,26 +96,54 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     a.bits = bk.L % 64u != 0 ? 1u : 0u;
     a.int8_io = p->layout == SD_I8 ? 1u : 0u;
     a.paired = bk.paired;
+    // later buckets (smaller lattices) of the same kernel form: taken from
+    // once this bucket's queue is empty, so that no bucket's workgroups idle
+    // while another bucket still has chains waiting
+    for (size_t c = b + 1; c < p->buckets.size() && a.n_steal < kMaxSteal; ++c) {
+        const sd_batch_plan::Bucket& o = p->buckets[c];
+        if (o.paired != bk.paired || (o.L % 64u != 0) != (bk.L % 64u != 0) || o.max_words > bk.max_words)
+            continue;
+        a.steal_order[a.n_steal] = p->d_order + o.first;
+        a.steal_count[a.n_steal] = o.count;
+        a.steal_counter[a.n_steal] = p->d_counters + c;
+        ++a.n_steal;
+    }
     return a;
 }
 
-hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint64_t step0, hipStream_t st) {
+// timed (direct runs only, never under capture): record the fork and each
+// bucket's start and end on the plan's timing events.
+hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint64_t step0, hipStream_t st,
+                         bool timed = false) {
     hipError_t e = launch_zero_u32(p->d_counters, (uint32_t)p->buckets.size(), st);
     if (e != hipSuccess)
         return e;
+    if (timed)
+        e = hipEventRecord(p->timing[0], st);
     if (p->buckets.size() == 1) {
         const auto& bk = p->buckets[0];
-        return launch_batch_chains(bucket_args(p, 0, lattices, traces, step0), bk.blocks, bk.threads, st);
+        if (timed && e == hipSuccess)
+            e = hipEventRecord(p->timing[1], st);
+        if (e == hipSuccess)
+            e = launch_batch_chains(bucket_args(p, 0, lattices, traces, step0), bk.blocks, bk.threads, st);
+        if (timed && e == hipSuccess)
+            e = hipEventRecord(p->timing[2], st);
+        return e;
     }
     // fork: every bucket runs on its own stream after the counters are zeroed
-    e = hipEventRecord(p->events[0], st);
+    if (e == hipSuccess)
+        e = hipEventRecord(p->events[0], st);
     for (size_t b = 0; b < p->buckets.size() && e == hipSuccess; ++b) {
         hipStream_t s = p->side[b];
         e = hipStreamWaitEvent(s, p->events[0], 0);
+        if (timed && e == hipSuccess)
+            e = hipEventRecord(p->timing[1 + 2 * b], s);
         if (e == hipSuccess) {
             const auto& bk = p->buckets[b];
             e = launch_batch_chains(bucket_args(p, b, lattices, traces, step0), bk.blocks, bk.threads, s);
         }
+        if (timed && e == hipSuccess)
+            e = hipEventRecord(p->timing[2 + 2 * b], s);
         if (e == hipSuccess)
             e = hipEventRecord(p->events[1 + b], s);
         if (e == hipSuccess)
@@ -408,6 +439,12 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         if (e == hipSuccess)
             p->events.push_back(ev);
     }
+    for (size_t i = 0; i < 2 * p->buckets.size() + 1 && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreate(&ev);
+        if (e == hipSuccess)
+            p->timing.push_back(ev);
+    }
     if (e != hipSuccess) {
         sd_batch_plan_destroy(p);
         return hip_fail(e, "sd_batch_plan_create");
@@ -520,8 +557,23 @@ sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_t* trac
         return fail(SD_EINVAL, "sd_batch_run_direct: step indices must stay below 2^29");
     if (reinterpret_cast<uintptr_t>(lattices) % 16u)
         return fail(SD_EINVAL, "sd_batch_run_direct: lattices must be 16-byte aligned");
-    hipError_t e = enqueue_batch(plan, lattices, traces, step0, static_cast<hipStream_t>(hip_stream));
+    hipError_t e = enqueue_batch(plan, lattices, traces, step0, static_cast<hipStream_t>(hip_stream), true);
+    plan->timed = e == hipSuccess;
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run_direct");
+}
+
+sd_status sd_batch_bucket_times(sd_batch_plan* plan, int32_t bucket, float* start_ms, float* end_ms) {
+    if (!plan || bucket < 0 || (size_t)bucket >= plan->buckets.size() || !start_ms || !end_ms)
+        return fail(SD_EINVAL, "sd_batch_bucket_times: no such bucket or null output");
+    if (!plan->timed)
+        return fail(SD_EINVAL, "sd_batch_bucket_times: no direct run of this plan yet");
+    const size_t b = (size_t)bucket;
+    hipError_t e = hipEventSynchronize(plan->timing[2 + 2 * b]);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(start_ms, plan->timing[0], plan->timing[1 + 2 * b]);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(end_ms, plan->timing[0], plan->timing[2 + 2 * b]);
+    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_bucket_times");
 }
 
 void sd_batch_plan_destroy(sd_batch_plan* plan) {
@@ -533,6 +585,8 @@ void sd_batch_plan_destroy(sd_batch_plan* plan) {
     if (plan->capture)
         (void)hipStreamDestroy(plan->capture);
     for (hipEvent_t ev : plan->events)
+        (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : plan->timing)
         (void)hipEventDestroy(ev);
     if (plan->d_descs)
         (void)hipFree(plan->d_descs);

@@ -298,22 +298,41 @@ template <bool COMPLEMENT, bool PAIRED, bool BITS>
 __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t s_chain;
+    __shared__ uint32_t s_queue;   // the queue this workgroup takes chains from (0: its own)
     __shared__ ChainShared s_ch;
     __shared__ int64_t red[3 * 8];
     uint64_t* sig = smem;
     uint64_t* tau = smem + a.max_words;
     WaveWordList& wl = reinterpret_cast<WaveWordList*>(tau + a.max_words)[threadIdx.x >> 6];
 
+    if (threadIdx.x == 0)
+        s_queue = 0;
     for (uint32_t iter = 0;; ++iter) {
         ChainDesc cd;
         if (a.counter) {
-            if (threadIdx.x == 0)
-                s_chain = atomicAdd(a.counter, 1u);
+            // the next chain of this launch's queue, then of the later queues
+            // in turn once it is empty (every queue is exhausted at most once
+            // per workgroup: s_queue only moves forward)
+            if (threadIdx.x == 0) {
+                uint32_t chain = ~0u;
+                while (s_queue <= a.n_steal) {
+                    const uint32_t q = s_queue;
+                    uint32_t* ctr = q == 0 ? a.counter : a.steal_counter[q - 1];
+                    const uint32_t cnt = q == 0 ? a.n_chains : a.steal_count[q - 1];
+                    const uint32_t i = atomicAdd(ctr, 1u);
+                    if (i < cnt) {
+                        chain = q == 0 ? a.order[i] : a.steal_order[q - 1][i];
+                        break;
+                    }
+                    s_queue = q + 1;
+                }
+                s_chain = chain;
+            }
             __syncthreads();
-            const uint32_t qi = s_chain;
-            if (qi >= a.n_chains)
+            const uint32_t ci = s_chain;
+            if (ci == ~0u)
                 break;
-            cd = a.chains[a.order[qi]];
+            cd = a.chains[ci];
         } else if (a.n_uniform) {
             if (iter > 0 || blockIdx.x >= a.n_uniform)
                 break;

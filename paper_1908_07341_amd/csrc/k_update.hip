@@ -26,45 +26,6 @@ constexpr int kTailCap = 1024;
 // two apart.
 constexpr int kLayP64Rows = 16;
 
-__device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t x) {
-    // byte k of x is 0x01 (+1) or 0xFF (-1); bit k of the result is 1 for +1
-    uint32_t y = (~x >> 7) & 0x01010101u;
-    return (y * 0x10204080u) >> 28;
-}
-
-__device__ __forceinline__ uint32_t bits4_to_bytes(uint32_t n) {
-    uint32_t z = (n * 0x00204081u) & 0x01010101u;   // byte k = bit k of n
-    uint32_t w = z ^ 0x01010101u;                    // 1 where the spin is -1
-    return z | ((w << 8) - w);
-}
-
-__device__ __forceinline__ uint64_t load_bits64_i8(const int8_t* p) {
-    const uint4* v = reinterpret_cast<const uint4*>(p);
-    uint64_t bits = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint4 x = v[q];
-        uint32_t b16 = bytes_to_bits4(x.x) | (bytes_to_bits4(x.y) << 4) | (bytes_to_bits4(x.z) << 8) |
-                       (bytes_to_bits4(x.w) << 12);
-        bits |= (uint64_t)b16 << (16 * q);
-    }
-    return bits;
-}
-
-__device__ __forceinline__ void store_bits64_i8(int8_t* p, uint64_t bits) {
-    uint4* v = reinterpret_cast<uint4*>(p);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint32_t b16 = (uint32_t)(bits >> (16 * q)) & 0xFFFFu;
-        uint4 x;
-        x.x = bits4_to_bytes(b16 & 0xF);
-        x.y = bits4_to_bytes((b16 >> 4) & 0xF);
-        x.z = bits4_to_bytes((b16 >> 8) & 0xF);
-        x.w = bits4_to_bytes((b16 >> 12) & 0xF);
-        v[q] = x;
-    }
-}
-
 // Partner bits c and neighbour bits n1, n2 of group g (all 64 bits valid for
 // every layout except the generic int8 one, which reports its valid mask).
 template <int LAYOUT, int WHICH>

@@ -18,11 +18,19 @@ struct ChainDesc {
     uint64_t trace_offset;  // first int64 of the chain's trace
 };
 
+// Queues of later buckets a launch may take chains from once its own is
+// empty (buckets of smaller lattices with the same kernel form).
+constexpr uint32_t kMaxSteal = 3;
+
 struct BatchArgs {
     const ChainDesc* chains;
     const uint32_t* order;   // queue position -> chain index (longest first)
     uint32_t n_chains;       // chains in this launch's queue
     uint32_t* counter;       // queue head, zero before the launch; null: run `single` in block 0
+    uint32_t n_steal;        // further queues, taken in order after this one
+    const uint32_t* steal_order[kMaxSteal];
+    uint32_t steal_count[kMaxSteal];
+    uint32_t* steal_counter[kMaxSteal];
     ChainDesc single;        // the chain of a single-chain launch (offsets unused)
     uint8_t* single_sig;     // its sigma
     uint8_t* single_tau;     // its tau

@@ -94,6 +94,29 @@ hipError_t launch_half_step_many(int layout, int which, const ManyChains& mc, co
 // obs + a * obs_chain + 3 * (rec0 + r).
 hipError_t launch_obs_finish_many(const int64_t* partials, uint32_t n_blocks, uint32_t n_chains, uint32_t n_rec,
                                   uint32_t stride, int64_t* obs, uint64_t obs_chain, uint32_t rec0, hipStream_t st);
+// Whole steps of several chains in one launch each (lattices whose rows are
+// at most 64 words, L = 64 * W with W dividing 256): workgroup (chain, band)
+// draws a step for R = 256 / W rows from sigma in src, writing sigma' to dst
+// (the other lattice of the pair).  Every field but src, dst and t0 is fixed
+// for a run.
+constexpr uint32_t kBandMaxWords = 256;   // R * W
+struct BandArgs {
+    const void* src[kManyMax];
+    void* dst[kManyMax];
+    uint32_t T[kManyMax][6];
+    uint32_t stream[kManyMax];
+    uint32_t n_chains;
+    uint32_t bands;    // L / R per chain
+    uint32_t L, W, R;
+    FastDiv divW;
+    uint32_t key0, key1;
+    uint32_t t0;       // half-step index of the step's half-step A
+};
+// Rows per band for L, or 0 when L does not take the whole-step kernel.
+uint32_t band_rows(int32_t L);
+// partials (non-null: a recorded step): workgroup b's sums at partials + 4 b.
+hipError_t launch_band_step(const BandArgs& ba, bool int8, bool paired, bool complement, int64_t* partials,
+                            hipStream_t st);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,
                        hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, size_t n, int64_t v, hipStream_t st);
