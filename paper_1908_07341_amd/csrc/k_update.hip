@@ -217,10 +217,24 @@ struct WaveList {
     uint16_t local[kMaxWaveTile];     // tile index of the listed word
 };
 
+// Words whose second and later undecided sites wait for the workgroup's
+// last pass (64-bit word layouts, whole tiles).
+constexpr uint32_t kPoolCap = 256;
+struct TailPool {
+    uint32_t count;
+    uint32_t g[kPoolCap];
+    uint64_t und[kPoolCap];
+};
+
 struct HalfStepScratch {
     WaveList list[kWavesPerBlock];
     uint32_t T24[6];               // tail thresholds of the classes (paired_tail in the paired form)
+    TailPool pool;
 };
+
+// Layouts whose words are the lattice's 64-bit words: a decided +1 site can be
+// or-ed into a stored word later.
+constexpr bool pooled_layout(int layout) { return layout == kLayP64 || layout == kLayP64Rows || layout == kLayBits; }
 
 struct ObsAcc {
     int64_t pc = 0, d_up = 0, d_right = 0, d_self = 0, nsites = 0;
@@ -250,7 +264,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS, bool FULL, int WPL>
 __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, void* __restrict__ dst, const Geom& G,
                                                const DrawParams& dp, const PlaneMasks& pm, const uint32_t* T24,
-                                               WaveList& wl, uint32_t tile0, uint32_t lane, ObsAcc& acc) {
+                                               WaveList& wl, uint32_t tile0, uint32_t lane, ObsAcc& acc,
+                                               TailPool& pool) {
     constexpr int kWordsPerLane = WPL;
     constexpr bool kRowWalk = LAYOUT == kLayP64 || LAYOUT == kLayI8Row;
     uint64_t lt[kWordsPerLane], c[kWordsPerLane], n1[kWordsPerLane], n2[kWordsPerLane], valid[kWordsPerLane];
@@ -354,11 +369,35 @@ __device__ __forceinline__ void half_step_tile(const void* __restrict__ src, voi
         listed += (uint32_t)__popcll(need);
     }
     wave_sync_lds();
+    // Every listed word has one undecided site or more (two or more in about
+    // one word of eight).  Resolving all of a word's sites here would run as
+    // many tail passes as the most crowded word has sites; on whole tiles of
+    // the 64-bit word layouts only the first site is resolved here, and the
+    // rest of the word goes to the workgroup's pool, resolved once at the end
+    // of the launch and or-ed into the stored word.
+    constexpr bool kPool = FULL && pooled_layout(LAYOUT);
     for (uint32_t e = lane; e < listed; e += 64u) {
         const uint32_t g = tile0 + wl.local[e];
         uint64_t cc, a1, a2, v;
         gather<LAYOUT, WHICH>(src, G, g, cc, a1, a2, v);
-        wl.und[e] = resolve_word(dp, T24, wl.und[e], cc, a1, a2, 64u * g);
+        const uint64_t u = wl.und[e];
+        if constexpr (kPool) {
+            const uint64_t first = u & (0ull - u);
+            const uint64_t rest = u ^ first;
+            uint64_t r = resolve_word(dp, T24, first, cc, a1, a2, 64u * g);
+            if (rest) {
+                const uint32_t slot = atomicAdd(&pool.count, 1u);
+                if (slot < kPoolCap) {
+                    pool.g[slot] = g;
+                    pool.und[slot] = rest;
+                } else {
+                    r |= resolve_word(dp, T24, rest, cc, a1, a2, 64u * g);
+                }
+            }
+            wl.und[e] = r;
+        } else {
+            wl.und[e] = resolve_word(dp, T24, u, cc, a1, a2, 64u * g);
+        }
     }
     wave_sync_lds();
 #pragma unroll
@@ -407,6 +446,7 @@ __device__ __forceinline__ void half_step_body(const void* __restrict__ src, voi
 #pragma unroll
         for (int i = 0; i < 6; ++i)
             sh.T24[i] = PAIRED ? paired_tail(dp.T, i) : dp.T[i] & 0xFFFFFFu;
+        sh.pool.count = 0;
     }
     __syncthreads();
     const uint32_t n_tiles = (G.n_groups + kWaveTile - 1) / kWaveTile;
@@ -419,12 +459,40 @@ __device__ __forceinline__ void half_step_body(const void* __restrict__ src, voi
     for (uint32_t tile = block * kWavesPerBlock + wave; tile < n_tiles; tile += n_blocks * kWavesPerBlock) {
         if (tile < n_full) {
             half_step_tile<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, true, WPL>(src, dst, G, dp, pm, sh.T24, wl,
-                                                                              tile * kWaveTile, lane, acc);
+                                                                              tile * kWaveTile, lane, acc, sh.pool);
         } else {
             // the last, partial tile: 64 words at a time, with bounds checks
             for (uint32_t sub = tile * kWaveTile; sub < (tile + 1) * kWaveTile; sub += 64u)
                 half_step_tile<kPartLayout, WHICH, PAIRED, COMPLEMENT, OBS, false, 1>(src, dst, G, dp, pm, sh.T24,
-                                                                                       wl, sub, lane, acc);
+                                                                                       wl, sub, lane, acc, sh.pool);
+        }
+    }
+    if constexpr (pooled_layout(LAYOUT)) {
+        // the pool's sites: every word of the workgroup is stored (each
+        // wavefront waits for its stores before the barrier), so the decided
+        // +1 sites are or-ed into the words in memory; with observables, the
+        // owner counted those sites as -1 and the resolver adds the difference
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t n_pool = sh.pool.count < kPoolCap ? sh.pool.count : kPoolCap;
+            uint64_t* d = static_cast<uint64_t*>(dst);
+            for (uint32_t e = lane; e < n_pool; e += 64u) {
+                const uint32_t g = sh.pool.g[e];
+                uint64_t cc, a1, a2, v;
+                gather<kPartLayout, WHICH>(src, G, g, cc, a1, a2, v);
+                const uint64_t r = resolve_word(dp, sh.T24, sh.pool.und[e], cc, a1, a2, 64u * g);
+                if (r) {
+                    atomicOr(reinterpret_cast<unsigned long long*>(d + g), (unsigned long long)r);
+                    if constexpr (OBS) {
+                        const int64_t n = __popcll(r);
+                        acc.pc += n;
+                        acc.d_up += n - 2 * __popcll(r & a1);
+                        acc.d_right += n - 2 * __popcll(r & a2);
+                        acc.d_self += n - 2 * __popcll(r & cc);
+                    }
+                }
+            }
         }
     }
     if constexpr (OBS) {
@@ -443,14 +511,31 @@ __device__ __forceinline__ void half_step_body(const void* __restrict__ src, voi
     }
 }
 
+// The half-step kernel, held to six wavefronts per SIMD (80 VGPRs) where that
+// costs no scratch spills (the plain half-steps on 64- and 32-bit words with
+// the paired compare), and left to the compiler's register count otherwise.
 template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
-__global__ __launch_bounds__(256) void k_half_step(const void* __restrict__ src, void* __restrict__ dst, Geom G,
-                                                   DrawParams dp, int64_t* __restrict__ obs,
-                                                   int64_t* __restrict__ partials) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_half_step(
+    const void* __restrict__ src, void* __restrict__ dst, Geom G, DrawParams dp, int64_t* __restrict__ obs,
+    int64_t* __restrict__ partials) {
     __shared__ HalfStepScratch sh;
     __shared__ int64_t red[4 * 4];
     half_step_body<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, words_per_lane(LAYOUT, PAIRED)>(
         src, dst, G, dp, obs, partials, blockIdx.x, gridDim.x, sh, red);
+}
+
+template <int LAYOUT, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
+__global__ __launch_bounds__(256) void k_half_step_free(const void* __restrict__ src, void* __restrict__ dst, Geom G,
+                                                        DrawParams dp, int64_t* __restrict__ obs,
+                                                        int64_t* __restrict__ partials) {
+    __shared__ HalfStepScratch sh;
+    __shared__ int64_t red[4 * 4];
+    half_step_body<LAYOUT, WHICH, PAIRED, COMPLEMENT, OBS, words_per_lane(LAYOUT, PAIRED)>(
+        src, dst, G, dp, obs, partials, blockIdx.x, gridDim.x, sh, red);
+}
+
+constexpr bool six_waves(int layout, bool paired, bool obs) {
+    return paired && !obs && (layout == kLayP64 || layout == kLayP64Rows || layout == kLayP32);
 }
 
 // Several chains of one size advanced together: workgroups
@@ -574,21 +659,28 @@ uint32_t grid_for(uint32_t n_groups) {
 
 }  // namespace
 
+template <int LAY, int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
+void launch_half_step_kernel(dim3 grid, dim3 block, hipStream_t st, const void* src, void* dst, const Geom& G,
+                             const DrawParams& dp, int64_t* obs, int64_t* partials) {
+    if constexpr (six_waves(LAY, PAIRED, OBS))
+        hipLaunchKernelGGL((k_half_step<LAY, WHICH, PAIRED, COMPLEMENT, OBS>), grid, block, 0, st, src, dst, G, dp,
+                           obs, partials);
+    else
+        hipLaunchKernelGGL((k_half_step_free<LAY, WHICH, PAIRED, COMPLEMENT, OBS>), grid, block, 0, st, src, dst,
+                           G, dp, obs, partials);
+}
+
 template <int LAY, int WHICH, bool OBS>
 void launch_half_step_mode(bool paired, bool complement, dim3 grid, dim3 block, hipStream_t st, const void* src,
                            void* dst, const Geom& G, const DrawParams& dp, int64_t* obs, int64_t* partials) {
     if (paired && !complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
-                           partials);
+        launch_half_step_kernel<LAY, WHICH, true, false, OBS>(grid, block, st, src, dst, G, dp, obs, partials);
     else if (paired)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, true, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
-                           partials);
+        launch_half_step_kernel<LAY, WHICH, true, true, OBS>(grid, block, st, src, dst, G, dp, obs, partials);
     else if (!complement)
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, false, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
-                           partials);
+        launch_half_step_kernel<LAY, WHICH, false, false, OBS>(grid, block, st, src, dst, G, dp, obs, partials);
     else
-        hipLaunchKernelGGL((k_half_step<LAY, WHICH, false, true, OBS>), grid, block, 0, st, src, dst, G, dp, obs,
-                           partials);
+        launch_half_step_kernel<LAY, WHICH, false, true, OBS>(grid, block, st, src, dst, G, dp, obs, partials);
 }
 
 uint32_t half_step_blocks(int layout, const Geom& G, bool paired, uint32_t max_blocks) {
