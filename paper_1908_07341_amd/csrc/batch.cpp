@@ -242,7 +242,8 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
             }
             return best_ms / 1e3;
         };
-        best = tune_pick({64, 128, 256, 512}, measure);
+        best = paired ? tune_pick({64, 128, 256, 512, (long)kBatchMaxThreads}, measure)
+                      : tune_pick({64, 128, 256, 512}, measure);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -414,7 +415,7 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     size_t max_words = 0;
     for (auto& bk : p->buckets)
         max_words = std::max(max_words, (size_t)bk.max_words);
-    e = batch_kernel_attributes(batch_lds_bytes((uint32_t)max_words, 512));
+    e = batch_kernel_attributes(batch_lds_bytes((uint32_t)max_words, kBatchMaxThreads));
     if (e == hipSuccess)
         e = hipMalloc(&p->d_descs, sizeof(ChainDesc) * p->descs.size());
     if (e == hipSuccess)

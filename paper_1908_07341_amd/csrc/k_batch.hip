@@ -295,7 +295,7 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS
 // PAIRED: every chain of the launch has a paired threshold table.  BITS: the
 // chains' L are multiples of 8 but not of 64 (bit-string neighbours).
 template <bool COMPLEMENT, bool PAIRED, bool BITS>
-__global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
+__device__ __forceinline__ void batch_chains_body(const BatchArgs& a) {
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t s_chain;
     __shared__ uint32_t s_queue;   // the queue this workgroup takes chains from (0: its own)
@@ -329,7 +329,9 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
                 s_chain = chain;
             }
             __syncthreads();
-            const uint32_t ci = s_chain;
+            // a workgroup-uniform index, so that the descriptor is read with
+            // scalar loads into scalar registers
+            const uint32_t ci = __builtin_amdgcn_readfirstlane(s_chain);
             if (ci == ~0u)
                 break;
             cd = a.chains[ci];
@@ -454,6 +456,21 @@ __global__ __launch_bounds__(512) void k_batch_chains(BatchArgs a) {
     }
 }
 
+// The paired compare (every threshold table by default) in workgroups of up
+// to 640 threads held to 96 VGPRs, so that two workgroups of ten wavefronts
+// share a CU with the largest (512^2) chains in LDS; the six-class compare
+// keeps the compiler's register count and at most 512 threads.
+template <bool COMPLEMENT, bool BITS>
+__global__ __launch_bounds__(kBatchMaxThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_chains(
+    BatchArgs a) {
+    batch_chains_body<COMPLEMENT, true, BITS>(a);
+}
+
+template <bool COMPLEMENT, bool BITS>
+__global__ __launch_bounds__(512) void k_batch_chains_general(BatchArgs a) {
+    batch_chains_body<COMPLEMENT, false, BITS>(a);
+}
+
 __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         p[i] = 0;
@@ -468,13 +485,13 @@ size_t batch_lds_bytes(uint32_t max_words, uint32_t threads) {
 template <bool BITS>
 void launch_batch_chains_t(const BatchArgs& a, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t st) {
     if (a.rng_xor && a.paired)
-        hipLaunchKernelGGL((k_batch_chains<true, true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((k_batch_chains<true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
     else if (a.rng_xor)
-        hipLaunchKernelGGL((k_batch_chains<true, false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((k_batch_chains_general<true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
     else if (a.paired)
-        hipLaunchKernelGGL((k_batch_chains<false, true, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((k_batch_chains<false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
     else
-        hipLaunchKernelGGL((k_batch_chains<false, false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((k_batch_chains_general<false, BITS>), dim3(blocks), dim3(threads), lds, st, a);
 }
 
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st) {
@@ -492,14 +509,14 @@ hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st) {
 }
 
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
-    const void* kernels[8] = {reinterpret_cast<const void*>(&k_batch_chains<false, false, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<false, true, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, false, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, true, false>),
-                              reinterpret_cast<const void*>(&k_batch_chains<false, false, true>),
-                              reinterpret_cast<const void*>(&k_batch_chains<false, true, true>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, false, true>),
-                              reinterpret_cast<const void*>(&k_batch_chains<true, true, true>)};
+    const void* kernels[8] = {reinterpret_cast<const void*>(&k_batch_chains_general<false, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains_general<true, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, false>),
+                              reinterpret_cast<const void*>(&k_batch_chains_general<false, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<false, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains_general<true, true>),
+                              reinterpret_cast<const void*>(&k_batch_chains<true, true>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds);
         if (e != hipSuccess)
@@ -509,10 +526,10 @@ hipError_t batch_kernel_attributes(size_t max_dynamic_lds) {
 }
 
 hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, bool bits, int* blocks_per_cu) {
-    const void* k = bits ? (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, true, true>)
-                                   : reinterpret_cast<const void*>(&k_batch_chains<false, false, true>))
-                         : (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, true, false>)
-                                   : reinterpret_cast<const void*>(&k_batch_chains<false, false, false>));
+    const void* k = bits ? (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, true>)
+                                   : reinterpret_cast<const void*>(&k_batch_chains_general<false, true>))
+                         : (paired ? reinterpret_cast<const void*>(&k_batch_chains<false, false>)
+                                   : reinterpret_cast<const void*>(&k_batch_chains_general<false, false>));
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, (int)threads, lds);
 }
 

@@ -55,6 +55,10 @@ struct BatchArgs {
     uint64_t traj_chain_bytes;
 };
 
+// Largest workgroup of the batched kernel (the paired compare; the six-class
+// compare takes at most 512 threads).
+constexpr uint32_t kBatchMaxThreads = 640;
+
 // Dynamic LDS of a launch: the two lattice buffers and one list of undecided
 // words per wavefront of a threads-sized workgroup.
 constexpr uint32_t kMomentWords = 5;
