@@ -121,9 +121,15 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, copy_bytes: int = 512 
         if k in write:
             kernels[k] = {"fetch_kib": fetch[k], "write_kib": write[k],
                           "bytes": f_fac * fetch[k] * 1024.0 + w_fac * write[k] * 1024.0}
-    # the plain half-step A kernel (no observables) stands for the launch
-    main = min((k for k in kernels if "k_half_step<" in k and ", 0, " in k.split("<", 1)[1][:6]),
-               key=lambda k: kernels[k]["bytes"], default=None)
+    # the plain half-step A kernel (no observables) stands for the launch:
+    # template arguments <layout, half-step, paired, complemented, observables>
+    def plain_a(name):
+        if "k_half_step<" not in name:
+            return False
+        args = [a.strip() for a in name.split("<", 1)[1].split(">", 1)[0].split(",")]
+        return len(args) == 5 and args[1] == "0" and args[4] == "false"
+
+    main = min((k for k in kernels if plain_a(k)), key=lambda k: kernels[k]["bytes"], default=None)
     return {"kernel_sha256": kernel_hash(), "kernel": main,
             "bytes_per_launch": kernels[main]["bytes"] if main else None,
             "fetch_factor": f_fac, "write_factor": w_fac, "copy_bytes": copy_bytes, "kernels": kernels}
@@ -192,10 +198,11 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     """The five-point q = J sweep on 1024^2 int8 lattices: random start, 10^4
     steps per point with (M, A, B) every step and D(r <= 512) every 100 steps,
     stream = point index.  The five chains advance together through
-    sd_run_many (one launch per half-step for all of them, records fused into
-    half-step B); for comparison the same sweep with one sd_run per point, on
-    a stream each and on a single stream (a 1024^2 half-step alone fills a
-    small part of the device, so those are bound by launches)."""
+    sd_run_many (whole-step launches of up to eight steps for all five, each
+    workgroup a band of rows with its halo in LDS, records fused in); for
+    comparison the same sweep with one sd_run per point, on a stream each and
+    on a single stream (a 1024^2 half-step alone fills a small part of the
+    device, so those are bound by launches)."""
     sd.sd_tune(L, sd.SD_I8, tune_cache)
     points = [0.2, 0.4, 0.6, 0.8, 1.0]
     n_pts = len(points)
@@ -257,7 +264,7 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     return {"workload": f"{L}x{L} int8, q = J in {points}, random start, {n_steps} steps per point, "
                         f"(M, A, B) every step, D(r <= {rmax}) every {corr_every} steps",
             "spin_updates_per_ns": updates / (ms_many * 1e6), "seconds": ms_many / 1e3,
-            "path": "sd_run_many: the five chains in one launch per half-step",
+            "path": "sd_run_many: the five chains in whole-step launches of up to eight steps",
             "hbm_algorithmic_GBps": 2.0 * updates / (ms_many * 1e-3) / 1e9,
             "spin_updates_per_ns_sd_run_5_streams": updates / (ms_streams * 1e6),
             "spin_updates_per_ns_sd_run_one_stream": updates / (ms_one * 1e6),
@@ -406,11 +413,12 @@ def bench_cpu_plan(n_c5=8):
     if len(cores) < 4:
         raise SystemExit("--cpu-plan needs at least 4 host cores")
 
-    def pinned(core, fn):
+    def pinned(core, fn, name):
         def run():
             os.sched_setaffinity(0, {core})
             t0 = time.perf_counter()
             out = fn()
+            log(f"[cpu-plan] {name} done on CPU {core} in {time.perf_counter() - t0:.1f} s")
             return time.perf_counter() - t0, out
         return run
 
@@ -450,18 +458,20 @@ def bench_cpu_plan(n_c5=8):
     c4_cores = cores[3:]
     results = {}
     with ThreadPoolExecutor(max_workers=len(cores)) as ex:
-        futs = {name: ex.submit(pinned(core, fn)) for name, core, fn in jobs}
+        futs = {name: ex.submit(pinned(core, fn, name)) for name, core, fn in jobs}
 
         def c4_worker(core, mine):
             os.sched_setaffinity(0, {core})
             t0 = time.perf_counter()
             ups = sum(c4_chain(c) for c in mine)
+            log(f"[cpu-plan] {len(mine)} C4 chains done on CPU {core} in {time.perf_counter() - t0:.1f} s")
             return time.perf_counter() - t0, ups
 
         def c5_worker(core):
             os.sched_setaffinity(0, {core})
             t0 = time.perf_counter()
             n = sum(c5_one(a) for a in range(n_c5))
+            log(f"[cpu-plan] {n_c5} C5 trajectories done on CPU {core} in {time.perf_counter() - t0:.1f} s")
             return time.perf_counter() - t0, n
 
         f4 = [ex.submit(c4_worker, core, chains[i::len(c4_cores)]) for i, core in enumerate(c4_cores)]

@@ -3,6 +3,7 @@
 // entry point are in include/shaken.h.
 #include "shaken.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -508,14 +509,24 @@ sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, in
     const uint64_t obs_chain = 3ull * n_rec;
     uint32_t pending = 0;
     hipError_t e = hipSuccess;
-    // Rows of at most 64 words: whole steps in one launch each (bands with a
-    // halo row, sigma alternating between the two lattices of each chain) for
-    // an even number of steps, so that sigma ends where it started; the last
-    // one or two steps take the half-step kernels, which leave tau in place.
+    // Rows of at most 64 words: whole steps, several per launch (bands with
+    // halo rows, sigma alternating between the two lattices of each chain),
+    // for all but the last step, in an even number of launches so that sigma
+    // ends where it started; the last step takes the half-step kernels, which
+    // leave tau in place.
     const uint32_t R = band_rows(L);
-    const bool band_ok = R != 0 && (layout == SD_P64 || klay == kLayI8Row) && k_steps >= 3 &&
-                         4ull * ((uint32_t)L / R) * mc.n_chains <= kPartialsWords;
-    const uint32_t n_fused = band_ok ? k_steps - (k_steps % 2 ? 1u : 2u) : 0u;
+    uint32_t depth = R ? band_depth(L) : 0u;
+    if (depth && n_rec) {   // the records of one launch must fit the partial-sum buffer
+        const uint64_t per_rec = 4ull * ((uint32_t)L / R) * mc.n_chains;
+        depth = std::min<uint64_t>(depth, kPartialsWords / per_rec);
+    }
+    const bool band_ok = depth != 0 && (layout == SD_P64 || klay == kLayI8Row) && k_steps >= 3;
+    uint32_t n_fused = band_ok ? k_steps - 1u : 0u;
+    // an even number of launches of at most `depth` steps, none empty
+    uint32_t n_launch = n_fused ? (n_fused + depth - 1) / depth : 0u;
+    n_launch += n_launch % 2;
+    if (n_launch > n_fused)   // one step per launch and an odd count: leave one more step to the half-steps
+        n_launch = --n_fused;
     if (n_fused) {
         BandArgs ba;
         std::memset(&ba, 0, sizeof ba);
@@ -533,24 +544,42 @@ sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, in
         ba.key1 = base.key1;
         const uint32_t stride_b = 4u * ba.bands * ba.n_chains;
         const uint32_t chunk_b = (uint32_t)(kPartialsWords / stride_b);
+        ba.rec_stride = stride_b;
         const bool complement = (flags & SD_FLAG_COMPLEMENT_RNG) != 0;
-        for (uint32_t m = 0; m < n_fused && e == hipSuccess; ++m) {
+        uint32_t m = 0;   // steps done
+        for (uint32_t j = 0; j < n_launch && e == hipSuccess; ++j) {
+            const uint32_t steps = n_fused / n_launch + (j < n_fused % n_launch ? 1u : 0u);
             for (int32_t a = 0; a < n_chains; ++a) {
-                ba.src[a] = m % 2 ? tau[a] : sigma[a];
-                ba.dst[a] = m % 2 ? sigma[a] : tau[a];
+                ba.src[a] = j % 2 ? tau[a] : sigma[a];
+                ba.dst[a] = j % 2 ? sigma[a] : tau[a];
             }
             ba.t0 = (uint32_t)(2 * (step0 + m));
-            const bool rec = n_rec && (m + 1) % obs_every == 0;
+            ba.steps = steps;
+            ba.threads = band_threads(R, ba.W, steps);
+            ba.rec_mask = 0;
+            uint32_t n_here = 0;
+            if (n_rec)
+                for (uint32_t s = 0; s < steps; ++s)
+                    if ((m + s + 1) % obs_every == 0) {
+                        ba.rec_mask |= 1u << s;
+                        ++n_here;
+                    }
+            if (n_here && pending + n_here > chunk_b) {
+                const uint32_t r_next = (m + obs_every) / obs_every - 1;   // first record of this launch
+                e = launch_obs_finish_many(partials, ba.bands, mc.n_chains, pending, stride_b, obs, obs_chain,
+                                           r_next - pending, st);
+                pending = 0;
+                if (e != hipSuccess)
+                    break;
+            }
             e = launch_band_step(ba, layout == SD_I8, paired, complement,
-                                 rec ? partials + (size_t)pending * stride_b : nullptr, st);
-            if (rec && e == hipSuccess) {
-                const uint32_t r = (m + 1) / obs_every - 1;
-                ++pending;
-                if (pending == chunk_b || m + obs_every >= n_fused) {
-                    e = launch_obs_finish_many(partials, ba.bands, mc.n_chains, pending, stride_b, obs, obs_chain,
-                                               r + 1 - pending, st);
-                    pending = 0;
-                }
+                                 n_here ? partials + (size_t)pending * stride_b : nullptr, st);
+            m += steps;
+            pending += n_here;
+            if (e == hipSuccess && pending && j + 1 == n_launch) {
+                e = launch_obs_finish_many(partials, ba.bands, mc.n_chains, pending, stride_b, obs, obs_chain,
+                                           m / obs_every - pending, st);
+                pending = 0;
             }
         }
     }
@@ -600,7 +629,10 @@ sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax
         return fail(SD_EINVAL, "sd_corr_row: null output");
     if (rmax < 0 || rmax >= L)
         return fail(SD_EINVAL, "sd_corr_row: rmax must satisfy 0 <= rmax < L");
-    const int klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
+    // rows of whole 64-bit words where the layout has them
+    int klay = kernel_layout(L, layout, sigma);
+    if (klay != kLayP64 && klay != kLayI8Row)
+        klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
     hipError_t e = launch_corr_row(klay, sigma, make_geom(L, klay), rmax, out, static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
 }

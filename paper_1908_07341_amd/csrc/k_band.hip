@@ -1,46 +1,44 @@
-// Whole steps of several chains of one size in one launch each (sd_run_many
-// on lattices of a few thousand words).
+// Whole steps of several chains of one size, several steps per launch
+// (sd_run_many on lattices of a few thousand words).
 //
 // A full step of the shaken dynamics is half-step A (eq. (15): every tau_x
 // from sigma at x, below and left) followed by half-step B (eq. (16): every
-// sigma'_x from tau at x, above and right).  So sigma' on rows [a, a + R)
-// depends on tau on rows [a, a + R], and that tau on sigma on rows
-// [a - 1, a + R]: a band of R rows can take a whole step from R + 2 rows of
-// sigma with no other band's help.  Workgroup (chain, band) loads those rows
-// into LDS, draws tau on its R rows and on the row above the band (the next
-// band draws that row too, from the same counter-based uniforms, so both get
-// the same bits), then sigma' on its R rows, and writes sigma' to the other
-// buffer of the pair: every band reads the previous sigma while others write
-// the new one, so the launch alternates the two lattices of each chain.  One
-// launch per step instead of two, and nothing but sigma goes through global
-// memory.  tau itself is not written: the caller runs the last step (or two)
-// with the half-step kernels, which leave tau of the last step in place.
+// sigma'_x from tau at x, above and right).  So sigma' on a row depends on
+// tau on that row and the one above, and that tau on sigma on the same two
+// rows and the one below: a step widens the dependence of a row by one row
+// on each side, and n steps of rows [a, a + R) depend only on sigma on rows
+// [a - n, a + R + n).  Workgroup (chain, band) loads those R + 2n rows into
+// LDS and runs the n steps there, each half-step on the rows whose
+// dependence is still inside the loaded ones (one row fewer at the bottom
+// after each half-step A and at the top after each half-step B); the rows
+// outside [a, a + R) are drawn by the neighbouring bands too, from the same
+// counter-based uniforms of the same sites, so they get the same bits.  The
+// last sigma of the band's own rows goes to the other lattice of the pair
+// (every band reads the previous sigma while others write theirs), so the
+// launches alternate the two lattices of each chain, and nothing but sigma
+// crosses global memory.  tau itself is not written: the caller runs the last
+// step (or two) with the half-step kernels, which leave tau in place.
 //
 // Within each half-step a wavefront takes 64-word tiles (one word per lane);
 // words with undecided sites are listed through a ballot and resolved by the
 // wavefront at the end of the half-step (one tail draw per undecided site),
 // the resolver or-ing the decided bits into the LDS word.  On recorded steps
-// half-step B also counts M, A, B of the new pair: the owner counts its
-// decided sites, the resolver the rest.
+// half-step B also counts M, A, B of the band's own rows: the owner counts
+// its decided sites, the resolver the rest.
 #include "sd_kernels.hpp"
+
 
 namespace sd {
 
 namespace {
 
-constexpr uint32_t kBandWaves = 5;
-constexpr uint32_t kBandListCap = 128;   // a half-step lists at most 64 words per tile before resolving
-
-struct BandList {
-    uint64_t und[kBandListCap];
-    uint32_t u[kBandListCap];
-};
+constexpr uint32_t kBandWaves = kBandMaxThreads / 64;
+constexpr uint32_t kBandListCap = 128;   // sites listed by a wavefront before it resolves them
 
 struct BandShared {
-    uint64_t sig[kBandMaxWords + 2 * 64];   // sigma rows a - 1 .. a + R
-    uint64_t tau[kBandMaxWords + 64];       // tau rows a .. a + R
-    uint64_t out[kBandMaxWords];            // sigma' rows a .. a + R - 1
-    BandList list[kBandWaves];
+    uint64_t sig[kBandMaxRowsWords];         // sigma, rows a - n .. a + R + n - 1
+    uint64_t tau[kBandMaxRowsWords];         // tau, the same rows
+    uint32_t site[kBandWaves][kBandListCap]; // undecided sites of each wavefront: 64 * LDS word + bit
     uint32_t T24[6];
 };
 
@@ -54,119 +52,166 @@ __device__ __forceinline__ void band_sync_wave() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Partner and neighbour words of output word u = t * W + w of a half-step:
-// A (WHICH 0): tau row t from sigma rows t + 1 (the same lattice row) and t
-// (the row below); B (WHICH 1): sigma' row t from tau rows t and t + 1 (above).
+// Partner and neighbour words of LDS row i, word w of a half-step (both
+// lattices use the same row numbering): A (WHICH 0) from sigma rows i (the
+// site's own) and i - 1 (below); B (WHICH 1) from tau rows i and i + 1 (above).
 template <int WHICH>
-__device__ __forceinline__ void band_gather(const uint64_t* src, uint32_t t, uint32_t w, uint32_t W, uint64_t& c,
+__device__ __forceinline__ void band_gather(const uint64_t* src, uint32_t i, uint32_t w, uint32_t W, uint64_t& c,
                                             uint64_t& n1, uint64_t& n2) {
+    const uint64_t* row = src + i * W;
+    c = row[w];
     if constexpr (WHICH == 0) {
-        const uint64_t* row = src + (t + 1) * W;
-        c = row[w];
-        n1 = src[t * W + w];
+        n1 = src[(i - 1) * W + w];
         const uint32_t prev_hi = (uint32_t)(row[w == 0 ? W - 1 : w - 1] >> 32);
         n2 = (uint64_t)__builtin_amdgcn_alignbit((uint32_t)c, prev_hi, 31) |
              ((uint64_t)__builtin_amdgcn_alignbit((uint32_t)(c >> 32), (uint32_t)c, 31) << 32);
     } else {
-        const uint64_t* row = src + t * W;
-        c = row[w];
-        n1 = src[(t + 1) * W + w];
+        n1 = src[(i + 1) * W + w];
         const uint32_t next_lo = (uint32_t)row[w == W - 1 ? 0 : w + 1];
         n2 = (uint64_t)__builtin_amdgcn_alignbit((uint32_t)(c >> 32), (uint32_t)c, 1) |
              ((uint64_t)__builtin_amdgcn_alignbit(next_lo, (uint32_t)(c >> 32), 1) << 32);
     }
 }
 
-// One half-step of the band: n_out words of dst from src (both LDS).  Output
-// row t is lattice row (a + t) mod L, so its word w is stream group
-// ((a + t) mod L) * W + w.
+// Decision of undecided site b of LDS word u of a half-step (tail uniform
+// below the threshold's low 24 bits), with its word and neighbour words.
+template <int WHICH>
+__device__ __forceinline__ uint32_t band_tail(const uint64_t* src, uint32_t u, uint32_t b, uint32_t base, uint32_t L,
+                                              uint32_t W, const FastDiv& divW, const DrawParams& dp,
+                                              const uint32_t* T24, uint32_t& i, uint64_t& c, uint64_t& n1,
+                                              uint64_t& n2) {
+    i = fdiv(u, divW);
+    const uint32_t w = u - i * W;
+    band_gather<WHICH>(src, i, w, W, c, n1, n2);
+    uint32_t row = base + i;
+    row = row >= L ? row - L : row;
+    row = row >= L ? row - L : row;
+    return draw_tail24(dp, 64u * (row * W + w) + b) < T24[class_at(c, n1, n2, (int)b)] ? 1u : 0u;
+}
+
+template <bool OBS>
+__device__ __forceinline__ void band_count_site(uint32_t bit, uint64_t c, uint64_t n1, uint64_t n2, uint32_t b,
+                                                BandSums& acc) {
+    if constexpr (OBS) {
+        acc.pc += bit;
+        acc.dpair += (bit ^ (uint32_t)((n1 >> b) & 1u)) + (bit ^ (uint32_t)((n2 >> b) & 1u));
+        acc.dself += bit ^ (uint32_t)((c >> b) & 1u);
+    }
+}
+
+// Resolve the first k sites of a wavefront's list, one per lane, or-ing the
+// decided bits into dst (several sites may share a word).
+template <int WHICH, bool OBS>
+__device__ __forceinline__ void band_resolve(const uint64_t* src, uint64_t* dst, const uint32_t* list, uint32_t k,
+                                             uint32_t o0, uint32_t o1, uint32_t base, uint32_t L, uint32_t W,
+                                             const FastDiv& divW, const DrawParams& dp, const uint32_t* T24,
+                                             BandSums& acc) {
+    band_sync_wave();
+    for (uint32_t e = threadIdx.x & 63u; e < k; e += 64u) {
+        const uint32_t v = list[e];
+        const uint32_t u = v >> 6, b = v & 63u;
+        uint32_t i;
+        uint64_t c, n1, n2;
+        const uint32_t bit = band_tail<WHICH>(src, u, b, base, L, W, divW, dp, T24, i, c, n1, n2);
+        if (bit)
+            atomicOr(reinterpret_cast<unsigned long long*>(&dst[u]), 1ull << b);
+        if (OBS && i >= o0 && i < o1)
+            band_count_site<OBS>(bit, c, n1, n2, b, acc);
+    }
+    band_sync_wave();
+}
+
+// One half-step of the band on LDS rows [r0, r1) of dst, from src (both LDS,
+// the same row numbering; B writes sigma in place, which it does not read).
+// LDS row i is lattice row (base + i) mod L, so its word w is stream group
+// ((base + i) mod L) * W + w.  OBS: count the new pair on rows [o0, o1).
+// Must be called by every thread of the workgroup; ends with a barrier, after
+// which dst holds the half-step's result.
+//
+// Wavefronts take 64-word tiles (one word per lane) and write the decided
+// bits; each wavefront lists its undecided sites (one per lane and round of
+// ballots) and resolves them one site per lane whenever 64 are listed and at
+// the end.
 template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
-__device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, uint32_t n_out, uint32_t a, uint32_t L,
-                                          uint32_t W, const FastDiv& divW, const DrawParams& dp, const PlaneMasks& pm,
-                                          const uint32_t* T24, BandList& wl, BandSums& acc) {
+__device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, uint32_t r0, uint32_t r1, uint32_t o0,
+                                          uint32_t o1, uint32_t base, uint32_t L, uint32_t W, const FastDiv& divW,
+                                          const DrawParams& dp, const PlaneMasks& pm, BandShared& sh,
+                                          BandSums& acc) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n_waves = blockDim.x >> 6;
+    const uint32_t n_out = (r1 - r0) * W;
     const uint32_t n_tiles = (n_out + 63u) / 64u;
+    uint32_t* list = sh.site[wave];
     uint32_t listed = 0;
-    for (uint32_t tile = wave; tile < n_tiles; tile += kBandWaves) {
-        const uint32_t u = 64u * tile + lane;
-        const bool active = u < n_out;
-        const uint32_t t = fdiv(u, divW);
-        const uint32_t w = u - t * W;
+    for (uint32_t tile = wave; tile < n_tiles; tile += n_waves) {
+        const uint32_t uo = 64u * tile + lane;
+        const bool active = uo < n_out;
+        const uint32_t t = fdiv(uo, divW);
+        const uint32_t i = r0 + t;
+        const uint32_t w = uo - t * W;
+        const uint32_t u = i * W + w;
         uint64_t c = 0, n1 = 0, n2 = 0;
         if (active)
-            band_gather<WHICH>(src, t, w, W, c, n1, n2);
-        const uint32_t row = a + t >= L ? a + t - L : a + t;
+            band_gather<WHICH>(src, i, w, W, c, n1, n2);
+        uint32_t row = base + i;
+        row = row >= L ? row - L : row;
+        row = row >= L ? row - L : row;
         uint64_t P[8];
         draw_planes(dp, active ? row * W + w : 0u, P);
         const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
-        const uint64_t und = active ? wd.und : 0ull;
+        uint64_t und = active ? wd.und : 0ull;
         if (active) {
             dst[u] = wd.lt;
-            if constexpr (OBS) {
+            if (OBS && i >= o0 && i < o1) {
                 acc.pc += __popcll(wd.lt);
                 acc.dpair += __popcll((wd.lt ^ n1) & ~und) + __popcll((wd.lt ^ n2) & ~und);
                 acc.dself += __popcll((wd.lt ^ c) & ~und);
             }
         }
-        const uint64_t need = __ballot(und != 0);
-        if (und != 0) {
-            const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-            wl.und[e] = und;
-            wl.u[e] = u;
-        }
-        listed += (uint32_t)__popcll(need);
-        if (listed >= 64u || tile + kBandWaves >= n_tiles) {
-            band_sync_wave();
-            for (uint32_t e = lane; e < listed; e += 64u) {
-                const uint32_t uu = wl.u[e];
-                const uint64_t ud = wl.und[e];
-                const uint32_t tt = fdiv(uu, divW);
-                const uint32_t ww = uu - tt * W;
-                uint64_t cc, a1, a2;
-                band_gather<WHICH>(src, tt, ww, W, cc, a1, a2);
-                const uint32_t rr = a + tt >= L ? a + tt - L : a + tt;
-                const uint32_t site0 = 64u * (rr * W + ww);
-                uint64_t r = 0, rem = ud;
-                while (rem) {
-                    const int b = __ffsll((unsigned long long)rem) - 1;
-                    rem &= rem - 1;
-                    if (draw_tail24(dp, site0 + (uint32_t)b) < T24[class_at(cc, a1, a2, b)])
-                        r |= 1ull << b;
-                }
-                dst[uu] |= r;   // this lane is the only writer of word uu in this half-step
-                if constexpr (OBS) {
-                    acc.pc += __popcll(r);
-                    acc.dpair += __popcll((r ^ a1) & ud) + __popcll((r ^ a2) & ud);
-                    acc.dself += __popcll((r ^ cc) & ud);
-                }
+        for (;;) {
+            const uint64_t m = __ballot(und != 0);
+            if (m == 0)
+                break;
+            if (und != 0) {
+                const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                list[e] = 64u * u + (uint32_t)__builtin_ctzll(und);
+                und &= und - 1;
             }
-            band_sync_wave();
-            listed = 0;
+            listed += (uint32_t)__popcll(m);
+            if (listed >= 64u) {
+                band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, divW, dp, sh.T24, acc);
+                listed = 0;
+            }
         }
     }
+    if (listed)
+        band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, divW, dp, sh.T24, acc);
+    __syncthreads();
 }
 
+// ba.steps whole steps of band (chain, band) from step index ba.t0 / 2.
 // INT8: lattices in global memory are int8 (16-byte aligned rows), else
-// 64-bit words.  OBS: the workgroup's (#+1, #differences to up + right, #to
-// the partner, #sites) go to partials[4 * blockIdx.x ...].
+// 64-bit words.  OBS: for every step s (from 0) with bit s of ba.rec_mask, the
+// workgroup's (#+1, #differences to up + right, #to the partner, #sites) of
+// its own rows go to partials + k * ba.rec_stride + 4 * blockIdx.x, k the
+// number of recorded steps before s in this launch.
 template <bool INT8, bool PAIRED, bool COMPLEMENT, bool OBS>
-__global__ __launch_bounds__(64 * kBandWaves) void k_band_step(BandArgs ba, int64_t* __restrict__ partials) {
+__global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int64_t* __restrict__ partials) {
     __shared__ BandShared sh;
     __shared__ int64_t red[3 * kBandWaves];
     const uint32_t chain = blockIdx.x / ba.bands;
     const uint32_t band = blockIdx.x - chain * ba.bands;
-    const uint32_t L = ba.L, W = ba.W, R = ba.R;
+    const uint32_t L = ba.L, W = ba.W, R = ba.R, n = ba.steps;
     const uint32_t a = band * R;
-    // sigma rows a - 1 .. a + R into LDS
-    const uint32_t n_in = (R + 2) * W;
-    for (uint32_t q = threadIdx.x; q < n_in; q += blockDim.x) {
-        const uint32_t t = fdiv(q, ba.divW);
-        const uint32_t w = q - t * W;
-        uint32_t row = a + t;   // lattice row a - 1 + t, kept non-negative
-        row = row == 0 ? L - 1 : row - 1;
-        row = row >= L ? row - L : row;
+    const uint32_t H = R + 2u * n;                        // LDS rows: lattice rows a - n .. a + R + n - 1
+    const uint32_t base = a + (n / L + 1u) * L - n;       // lattice row of LDS row 0, plus a multiple of L
+    const uint32_t base_mod = base % L;
+    for (uint32_t q = threadIdx.x; q < H * W; q += blockDim.x) {
+        const uint32_t i = fdiv(q, ba.divW);
+        const uint32_t w = q - i * W;
+        const uint32_t row = (base_mod + i) % L;
         if constexpr (INT8)
             sh.sig[q] = load_bits64_i8(static_cast<const int8_t*>(ba.src[chain]) + (size_t)row * L + 64u * w);
         else
@@ -185,38 +230,50 @@ __global__ __launch_bounds__(64 * kBandWaves) void k_band_step(BandArgs ba, int6
     dp.tag2 = 2u * kTagDynamics;
     dp.rng_xor = COMPLEMENT ? 0xFFFFFFFFu : 0u;
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
-    BandList& wl = sh.list[threadIdx.x >> 6];
-    BandSums acc;
-    dp.t = ba.t0;
-    band_half<0, PAIRED, COMPLEMENT, false>(sh.sig, sh.tau, (R + 1) * W, a, L, W, ba.divW, dp, pm, sh.T24, wl, acc);
-    __syncthreads();
-    dp.t = ba.t0 + 1u;
-    band_half<1, PAIRED, COMPLEMENT, OBS>(sh.tau, sh.out, R * W, a, L, W, ba.divW, dp, pm, sh.T24, wl, acc);
-    __syncthreads();
-    // sigma' rows a .. a + R - 1 to the other lattice of the pair
-    const uint32_t n_out = R * W;
-    for (uint32_t u = threadIdx.x; u < n_out; u += blockDim.x) {
-        if constexpr (INT8)
-            store_bits64_i8(static_cast<int8_t*>(ba.dst[chain]) + (size_t)a * L + 64u * u, sh.out[u]);
-        else
-            static_cast<uint64_t*>(ba.dst[chain])[(size_t)a * W + u] = sh.out[u];
-    }
-    if constexpr (OBS) {
-        int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
-        block_sum_i64<3>(v, red);
-        if (threadIdx.x == 0) {
-            int64_t* p = partials + 4u * (size_t)blockIdx.x;
-            p[0] = v[0];
-            p[1] = v[1];
-            p[2] = v[2];
-            p[3] = (int64_t)n_out * 64;
+    uint32_t rec = 0;
+    for (uint32_t s = 1; s <= n; ++s) {
+        BandSums acc;
+        dp.t = ba.t0 + 2u * (s - 1u);
+        // tau on rows s .. H - s (its sigma rows below are valid from s - 1)
+        band_half<0, PAIRED, COMPLEMENT, false>(sh.sig, sh.tau, s, H - s + 1u, 0, 0, base_mod, L, W, ba.divW, dp,
+                                                pm, sh, acc);
+        dp.t += 1u;
+        const bool recorded = OBS && ((ba.rec_mask >> (s - 1u)) & 1u);
+        if (recorded) {
+            band_half<1, PAIRED, COMPLEMENT, true>(sh.tau, sh.sig, s, H - s, n, n + R, base_mod, L, W, ba.divW, dp,
+                                                   pm, sh, acc);
+        } else {
+            band_half<1, PAIRED, COMPLEMENT, false>(sh.tau, sh.sig, s, H - s, 0, 0, base_mod, L, W, ba.divW, dp, pm,
+                                                    sh, acc);
         }
+        if constexpr (OBS) {
+            if (recorded) {
+                int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
+                block_sum_i64<3>(v, red);
+                if (threadIdx.x == 0) {
+                    int64_t* p = partials + (size_t)rec * ba.rec_stride + 4u * (size_t)blockIdx.x;
+                    p[0] = v[0];
+                    p[1] = v[1];
+                    p[2] = v[2];
+                    p[3] = (int64_t)R * L;
+                }
+                ++rec;
+            }
+        }
+    }
+    // the band's own rows (LDS rows n .. n + R - 1) to the other lattice
+    const uint64_t* own = sh.sig + n * W;
+    for (uint32_t u = threadIdx.x; u < R * W; u += blockDim.x) {
+        if constexpr (INT8)
+            store_bits64_i8(static_cast<int8_t*>(ba.dst[chain]) + (size_t)a * L + 64u * u, own[u]);
+        else
+            static_cast<uint64_t*>(ba.dst[chain])[(size_t)a * W + u] = own[u];
     }
 }
 
 template <bool INT8, bool OBS>
 void launch_band_t(const BandArgs& ba, bool paired, bool complement, int64_t* partials, hipStream_t st) {
-    const dim3 grid(ba.n_chains * ba.bands), block(64 * kBandWaves);
+    const dim3 grid(ba.n_chains * ba.bands), block(ba.threads);
     if (paired && !complement)
         hipLaunchKernelGGL((k_band_step<INT8, true, false, OBS>), grid, block, 0, st, ba, partials);
     else if (paired)
@@ -229,14 +286,43 @@ void launch_band_t(const BandArgs& ba, bool paired, bool complement, int64_t* pa
 
 }  // namespace
 
+// Rows per band and steps per launch, measured on five chains with records
+// every step: the small lattices leave most of the device idle, so they take
+// narrow bands and many steps per launch (latency bound: the redundant halo
+// rows cost nothing); the larger ones are issue bound, and the halo's share
+// of the work, (2 steps - 1) / (2 R) of a step, decides.
 uint32_t band_rows(int32_t L) {
     if (L < 64 || L % 64 != 0)
         return 0;
     const uint32_t W = (uint32_t)L / 64u;
-    if (W > 64u || 256u % W != 0)
-        return 0;
-    const uint32_t R = 256u / W;   // four 64-word tiles of output rows per band
-    return R < (uint32_t)L ? R : (uint32_t)L;
+    switch (W) {
+        case 1:
+        case 2:
+        case 4:
+            return 32u / W;   // half a tile of own words
+        case 8:
+            return 16u;       // two tiles
+        case 16:
+            return 16u;       // four tiles
+        case 32:
+            return 8u;
+        case 64:
+            return 4u;
+        default:
+            return 0;         // rows of more than 64 words, or not dividing 256
+    }
+}
+
+uint32_t band_depth(int32_t L) {
+    const uint32_t W = (uint32_t)L / 64u;
+    return W <= 16u ? 8u : W == 32u ? 4u : 1u;
+}
+
+uint32_t band_threads(uint32_t R, uint32_t W, uint32_t steps) {
+    // the widest half-step is the first A: rows 1 .. R + 2 steps - 1
+    const uint32_t tiles = ((R + 2u * steps - 1u) * W + 63u) / 64u;
+    const uint32_t t = 64u * tiles;
+    return t < kBandMaxThreads ? t : kBandMaxThreads;
 }
 
 hipError_t launch_band_step(const BandArgs& ba, bool int8, bool paired, bool complement, int64_t* partials,

@@ -167,6 +167,59 @@ __global__ __launch_bounds__(256) void k_corr_row(const void* __restrict__ sigma
         atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)acc);
 }
 
+// Rows of whole 64-bit words (the packed string with L % 64 == 0, or int8
+// rows whose 64-site groups are 16-byte aligned): workgroup x takes rows
+// [x * rpb, (x + 1) * rpb), staged `chunk` rows at a time as W = L / 64 words
+// each; thread t of r-block y takes the shift r = 1024 y + t (if r <= rmax)
+// and sums popcount(row ^ row rotated by r) over the W words of each staged
+// row, the rotation a funnel shift of consecutive words.  Within a wavefront
+// r >> 6 is uniform, so the LDS reads are broadcasts.  Results are added to
+// out[r] (zeroed first).
+constexpr uint32_t kCorr64Words = 4096;   // staged words (32 KB)
+
+template <bool INT8>
+__global__ __launch_bounds__(1024) void k_corr_row64(const void* __restrict__ sigma, uint32_t L, uint32_t rpb,
+                                                     uint32_t chunk, int32_t rmax, int64_t* __restrict__ out) {
+    __shared__ uint64_t rows[kCorr64Words];
+    const uint32_t W = L / 64u;
+    const uint32_t j0 = blockIdx.x * rpb;
+    const uint32_t j1 = j0 + rpb < L ? j0 + rpb : L;
+    const uint32_t r = 1024u * blockIdx.y + threadIdx.x;
+    const bool active = r <= (uint32_t)rmax;
+    const uint32_t s = __builtin_amdgcn_readfirstlane(r >> 6);   // uniform in the wavefront
+    const uint32_t sh = r & 63u;
+    int64_t acc = 0;
+    for (uint32_t j = j0; j < j1; j += chunk) {
+        const uint32_t n = j + chunk < j1 ? chunk : j1 - j;
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < n * W; q += blockDim.x) {
+            if constexpr (INT8)
+                rows[q] = load_bits64_i8(static_cast<const int8_t*>(sigma) + (size_t)j * L + 64u * q);
+            else
+                rows[q] = static_cast<const uint64_t*>(sigma)[(size_t)j * W + q];
+        }
+        __syncthreads();
+        if (active) {
+            for (uint32_t i = 0; i < n; ++i) {
+                const uint64_t* row = rows + i * W;
+                uint32_t diff = 0;
+                // words s .. W - 1 of the row, then 0 .. s - 1: word w + s (mod W) pairs with word w
+#pragma unroll 8
+                for (uint32_t w = 0; w < W; ++w) {
+                    uint32_t q0 = w + s;
+                    q0 = q0 >= W ? q0 - W : q0;
+                    const uint32_t q1 = q0 + 1u == W ? 0u : q0 + 1u;
+                    const uint64_t rot = (row[q0] >> sh) | ((row[q1] << 1) << (63u - sh));
+                    diff += (uint32_t)__popcll(row[w] ^ rot);
+                }
+                acc += (int64_t)L - 2 * (int64_t)diff;
+            }
+        }
+    }
+    if (active)
+        atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)acc);
+}
+
 // Diagonal correlation sums (section 3.3, Table 1).  Block (x, y): direction
 // d = x / (lmax + 1) (0: partner (i+l, j+l), SW-NE; 1: partner (i+l, j-l),
 // NW-SE) and l = x % (lmax + 1), rows j = y, y + gridDim.y, ...; the block's
@@ -272,6 +325,21 @@ hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t
     hipError_t e = launch_fill_i64(out, (size_t)rmax + 1, 0, st);
     if (e != hipSuccess)
         return e;
+    if (layout == kLayP64 || layout == kLayI8Row) {
+        const uint32_t W = G.L / 64u;
+        const uint32_t n_blk = G.L < 256u ? G.L : 256u;
+        const uint32_t rpb = (G.L + n_blk - 1u) / n_blk;
+        uint32_t chunk = kCorr64Words / W;
+        chunk = chunk < rpb ? chunk : rpb;
+        const uint32_t n_r = (uint32_t)rmax + 1u;
+        const dim3 grid((G.L + rpb - 1u) / rpb, (n_r + 1023u) / 1024u);
+        const dim3 block(n_r < 1024u ? 64u * ((n_r + 63u) / 64u) : 1024u);
+        if (layout == kLayI8Row)
+            hipLaunchKernelGGL((k_corr_row64<true>), grid, block, 0, st, sigma, G.L, rpb, chunk, rmax, out);
+        else
+            hipLaunchKernelGGL((k_corr_row64<false>), grid, block, 0, st, sigma, G.L, rpb, chunk, rmax, out);
+        return hipGetLastError();
+    }
     const uint32_t r_chunks = ((uint32_t)rmax + 256u) / 256u;
     uint32_t row_blocks = kMaxBlocks / r_chunks;
     row_blocks = row_blocks < G.L ? row_blocks : G.L;

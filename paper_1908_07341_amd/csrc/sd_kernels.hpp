@@ -94,27 +94,39 @@ hipError_t launch_half_step_many(int layout, int which, const ManyChains& mc, co
 // obs + a * obs_chain + 3 * (rec0 + r).
 hipError_t launch_obs_finish_many(const int64_t* partials, uint32_t n_blocks, uint32_t n_chains, uint32_t n_rec,
                                   uint32_t stride, int64_t* obs, uint64_t obs_chain, uint32_t rec0, hipStream_t st);
-// Whole steps of several chains in one launch each (lattices whose rows are
+// Whole steps of several chains, several per launch (lattices whose rows are
 // at most 64 words, L = 64 * W with W dividing 256): workgroup (chain, band)
-// draws a step for R = 256 / W rows from sigma in src, writing sigma' to dst
-// (the other lattice of the pair).  Every field but src, dst and t0 is fixed
-// for a run.
-constexpr uint32_t kBandMaxWords = 256;   // R * W
+// runs `steps` steps of R = band_rows(L) rows (R * W at most 256) from sigma
+// in src, with `steps` rows of halo on each side, writing the last sigma of
+// its rows to dst (the other lattice of the pair).  src, dst, t0, steps and
+// rec_mask change from launch to launch.
+constexpr uint32_t kBandMaxSteps = 8;
+constexpr uint32_t kBandMaxRowsWords = 256 + 2 * kBandMaxSteps * 64;   // (R + 2 steps) * W
+constexpr uint32_t kBandMaxThreads = 768;
 struct BandArgs {
     const void* src[kManyMax];
     void* dst[kManyMax];
     uint32_t T[kManyMax][6];
     uint32_t stream[kManyMax];
     uint32_t n_chains;
-    uint32_t bands;    // L / R per chain
+    uint32_t bands;      // L / R per chain
     uint32_t L, W, R;
     FastDiv divW;
     uint32_t key0, key1;
-    uint32_t t0;       // half-step index of the step's half-step A
+    uint32_t t0;         // half-step index of the launch's first half-step A
+    uint32_t steps;      // 1 .. kBandMaxSteps
+    uint32_t threads;    // workgroup size: 64 per tile of the widest half-step
+    uint32_t rec_mask;   // bit s: record step s of the launch
+    uint32_t rec_stride; // int64 between the partial sums of consecutive records
 };
 // Rows per band for L, or 0 when L does not take the whole-step kernel.
 uint32_t band_rows(int32_t L);
-// partials (non-null: a recorded step): workgroup b's sums at partials + 4 b.
+// Steps per launch of the whole-step kernel for lattices of side L.
+uint32_t band_depth(int32_t L);
+// Workgroup size for `steps` steps of bands of R rows of W words.
+uint32_t band_threads(uint32_t R, uint32_t W, uint32_t steps);
+// partials (non-null when rec_mask is not zero): the sums of recorded step k
+// of the launch at partials + k * rec_stride + 4 b for workgroup b.
 hipError_t launch_band_step(const BandArgs& ba, bool int8, bool paired, bool complement, int64_t* partials,
                             hipStream_t st);
 hipError_t launch_init(int layout, void* dst, const Geom& G, int const_up, bool random, const DrawParams& dp,

@@ -55,14 +55,17 @@ PARAMS = [(0.4, 0.6), (0.0, 0.0), (0.5, 1.0), (0.8, 0.0), (-0.3, 0.5), (1.2, 0.2
     (1024, sd.SD_I8, 3, 3, 5, 2, sd.SD_FLAG_GENERAL_COMPARE),
     (256, sd.SD_P64, 2, 0, 4, 1, sd.SD_FLAG_COMPLEMENT_RNG),
     (2048, sd.SD_P64, 16, 0, 2, 1, 0),         # the largest number of chains
-    # whole-step launches (rows of at most 64 words) for all but the last one
-    # or two steps, records landing in both parts
+    # whole-step launches (rows of at most 64 words, several steps each) for
+    # all but the last step, records landing in both parts
     (2048, sd.SD_P64, 16, 3, 5, 1, 0),
     (1024, sd.SD_P64, 2, 5, 10, 3, 0),
     (1024, sd.SD_I8, 4, 0, 12, 4, sd.SD_FLAG_COMPLEMENT_RNG),
     (64, sd.SD_I8, 3, 1, 5, 1, 0),              # one band holding the whole lattice
     (128, sd.SD_P64, 2, 0, 9, 2, 0),
     (4096, sd.SD_I8, 2, 0, 3, 1, 0),            # rows of 64 words, four rows per band
+    (1024, sd.SD_I8, 3, 0, 4, 1, 0),            # an odd number of fused steps over two launches
+    (512, sd.SD_P64, 3, 7, 37, 5, 0),           # ten launches of three or four steps
+    (2048, sd.SD_P64, 16, 0, 13, 1, 0),         # records flushed between launches
 ])
 def test_many_equals_sd_run(L, layout, n, step0, k, every, flags):
     print(f"sd_run_many L={L} layout={layout} n={n} k={k} every={every} flags={flags}", flush=True)

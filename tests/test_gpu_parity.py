@@ -224,6 +224,23 @@ def test_observe_and_corr_match_oracle(oracle, L):
             assert np.array_equal(dg.cpu().numpy().reshape(2, rmax + 1), ref_diag[:, :rmax + 1]), (L, layout, rmax)
 
 
+@pytest.mark.parametrize("L,layout,rmax", [
+    (128, sd.SD_P64, 127),
+    (192, sd.SD_I8, 100),
+    (1088, sd.SD_P64, 1087),    # two blocks of 1024 shifts, 17 words per row
+    (1152, sd.SD_I8, 1151),
+    (16384, sd.SD_P64, 2),      # rows staged in several chunks per workgroup
+])
+def test_corr_row_whole_words_match_oracle(oracle, L, layout, rmax):
+    # rows of whole 64-bit words (packed, or 16-byte aligned int8) take their
+    # own kernel; D(r) against the oracle's site-by-site sums
+    print(f"corr_row L={L} layout={layout} rmax={rmax}", flush=True)
+    s = inputs.random_lattice(L, 77 + L, 0.6)
+    out = torch.full((rmax + 1,), 99, dtype=torch.int64, device="cuda")
+    sd.sd_corr_row(to_device(s, layout), L, layout, rmax, out)
+    assert np.array_equal(out.cpu().numpy(), oracle.corr_row(s, rmax))
+
+
 def test_C2_prefix_sweep(oracle):
     # 1024x1024 int8, random start, q = J on the five-point sweep, stream = sweep
     # index; a 6-step prefix with (M, A, B) every step and D(r <= 512) at the end
