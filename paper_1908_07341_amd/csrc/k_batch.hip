@@ -11,16 +11,16 @@
 // final lattices and the traces.
 //
 // Within a half-step each wavefront takes 64-word tiles of the lattice in
-// turn (one word per lane).  Decided bits go straight to the LDS lattice; a
-// word with undecided sites (top byte of the uniform equal to the threshold's,
-// about one site in 256, so 22% of the words) claims a slot of the
-// wavefront's LDS list through a ballot.  Whenever 64 or more words are
-// listed, and once at the end of the half-step, the wavefront resolves its
-// list (one listed word per lane: one tail draw per undecided site) and ors
-// the decided bits into the lattice words, which no other wavefront touches.
-// So a half-step needs a single workgroup barrier, before the next one reads
-// the lattice.  On recorded steps half-step B also accumulates M, A, B: the
-// owner counts the decided sites of its word, the resolver the rest.
+// turn (one word per lane).  Decided bits go straight to the LDS lattice; the
+// undecided sites (top byte of the uniform equal to the threshold's, about
+// one site in 256) are listed in the wavefront's LDS list, one per lane and
+// round of ballots.  Whenever 64 or more sites are listed, and once at the
+// end of the half-step, the wavefront resolves its list (one site per lane:
+// one tail draw each) and ors the decided bits into the lattice words with
+// LDS atomics (several sites may share a word; no other wavefront touches
+// it).  So a half-step needs a single workgroup barrier, before the next one
+// reads the lattice.  On recorded steps half-step B also accumulates M, A, B:
+// the owner counts the decided sites of its word, the resolver the rest.
 #include "sd_batch.hpp"
 
 namespace sd {
@@ -69,14 +69,13 @@ __device__ __forceinline__ void gather_lds(const HalfCtx<BITS>& h, uint32_t g, u
     }
 }
 
-// Per-wavefront list of words with undecided sites.  A tile adds at most 64
-// entries and the list is resolved as soon as it holds 64, so it never holds
-// more than 127.
+// Per-wavefront list of undecided sites (64 * word + bit).  A round of
+// ballots adds at most 64 entries and the list is resolved as soon as it
+// holds 64, so it never holds more than 127.
 constexpr uint32_t kWListCap = 128;
 
 struct WaveWordList {
-    uint64_t und[kWListCap];   // undecided sites of the listed word
-    uint32_t g[kWListCap];     // its index in the lattice
+    uint32_t site[kWListCap];
 };
 
 // The chain's per-launch constants in LDS.
@@ -88,27 +87,22 @@ struct ObsSums {
     int64_t pc = 0, dpair = 0, dself = 0;   // #+1, #differences to up+right, to the partner
 };
 
-// Resolves the first n entries of the wavefront's list into the lattice.
+// Resolves the first n sites of the wavefront's list into the lattice.
 template <int WHICH, bool OBS, bool BITS>
 __device__ __forceinline__ void resolve_list(const HalfCtx<BITS>& h, const DrawParams& dp, const uint32_t* T24,
                                              WaveWordList& wl, uint32_t n, ObsSums& acc) {
     for (uint32_t e = threadIdx.x & 63u; e < n; e += 64u) {
-        const uint32_t g = wl.g[e];
-        const uint64_t und = wl.und[e];
+        const uint32_t v = wl.site[e];
+        const uint32_t g = v >> 6, b = v & 63u;
         uint64_t c, n1, n2;
         gather_lds<WHICH>(h, g, c, n1, n2);
-        uint64_t r = 0, u = und;
-        while (u) {
-            const int b = __ffsll((unsigned long long)u) - 1;
-            u &= u - 1;
-            if (draw_tail24(dp, 64u * g + (uint32_t)b) < T24[class_at(c, n1, n2, b)])
-                r |= 1ull << b;
-        }
-        h.dst[g] |= r;   // this lane is the only writer of word g until the barrier
+        const uint32_t bit = draw_tail24(dp, v) < T24[class_at(c, n1, n2, (int)b)] ? 1u : 0u;
+        if (bit)
+            atomicOr(reinterpret_cast<unsigned long long*>(&h.dst[g]), 1ull << b);
         if constexpr (OBS) {
-            acc.pc += __popcll(r);
-            acc.dpair += __popcll((r ^ n1) & und) + __popcll((r ^ n2) & und);
-            acc.dself += __popcll((r ^ c) & und);
+            acc.pc += bit;
+            acc.dpair += (bit ^ (uint32_t)((n1 >> b) & 1u)) + (bit ^ (uint32_t)((n2 >> b) & 1u));
+            acc.dself += bit ^ (uint32_t)((c >> b) & 1u);
         }
     }
 }
@@ -161,7 +155,7 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
         uint64_t P[8];
         draw_planes(dp, active ? g : 0u, P);
         const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
-        const uint64_t und = active ? wd.und : 0ull;
+        uint64_t und = active ? wd.und : 0ull;
         if (active) {
             h.dst[g] = wd.lt;
             if constexpr (OBS) {
@@ -170,19 +164,23 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
                 acc.dself += __popcll((wd.lt ^ c) & ~und);
             }
         }
-        const uint64_t need = __ballot(und != 0);
-        if (und != 0) {
-            const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-            wl.und[e] = und;
-            wl.g[e] = g;
-        }
-        listed += (uint32_t)__popcll(need);
-        if (listed >= 64u) {
-            wave_sync_lds();
-            resolve_list<WHICH, OBS>(h, dp, T24, wl, listed, acc);
-            wave_sync_lds();
-            listed = 0;
+        for (;;) {
+            const uint64_t m = __ballot(und != 0);
+            if (m == 0)
+                break;
+            if (und != 0) {
+                const uint32_t e = listed + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                wl.site[e] = 64u * g + (uint32_t)__builtin_ctzll(und);
+                und &= und - 1;
+            }
+            listed += (uint32_t)__popcll(m);
+            if (listed >= 64u) {
+                wave_sync_lds();
+                resolve_list<WHICH, OBS>(h, dp, T24, wl, listed, acc);
+                wave_sync_lds();
+                listed = 0;
+            }
         }
     }
     if (listed) {

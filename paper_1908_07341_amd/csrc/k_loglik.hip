@@ -74,7 +74,10 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 // Eleven accumulating v_bcnt and nine logic ops per half instead of counting
 // the six class masks and their +1 sites one by one; count_totals turns the
 // sums into the 12 counts.  A thread adds at most 32 per half-word and
-// transition, so 2^27 word-transitions per thread stay exact.
+// transition, so 2^27 word-transitions per thread stay exact.  base[0] (the
+// source's +1 sites) is left out: over consecutive transitions each lattice
+// is the target of one and the source of the next, so its sum is ybase[0]'s
+// plus the first source's and minus the last target's +1 sites.
 constexpr uint32_t kNeither = tt(~kTA & ~kTB & kTC), kBoth = tt(kTA & kTB & kTC);   // (a, b, mask)
 
 __device__ __forceinline__ void count_half(uint32_t c, uint32_t n1, uint32_t n2, uint32_t y, uint32_t live,
@@ -83,7 +86,6 @@ __device__ __forceinline__ void count_half(uint32_t c, uint32_t n1, uint32_t n2,
     const uint32_t k0 = lop3<kNeither>(n1, n2, live);
     const uint32_t k2 = lop3<kBoth>(n1, n2, live);
     const uint32_t k0c = k0 & c, k2c = k2 & c;
-    base[0] = bcnt_acc(cl, base[0]);
     base[1] = bcnt_acc(k0, base[1]);
     base[2] = bcnt_acc(k2, base[2]);
     base[3] = bcnt_acc(k0c, base[3]);
@@ -267,6 +269,15 @@ __global__ __launch_bounds__(THREADS, (counts_min_waves<THREADS, PAIRED, FULL>()
         for (uint32_t k = 0; k < WPT; ++k)
             cur[k] = X0[gi[k]];
     }
+    // +1 sites of the chunk's first lattice (the counts' source sum, see count_half)
+    if (!PAIRED) {
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k) {
+            const uint32_t lv = FULL ? ~0u : live[k];
+            base[0][0] = bcnt_acc(lo32(cur[k]) & lv, base[0][0]);
+            base[1][0] = bcnt_acc(hi32(cur[k]) & lv, base[1][0]);
+        }
+    }
 #pragma unroll
     for (uint32_t d = 0; d < DEPTH; ++d) {
         const uint32_t mf = m0 + 1 + d <= m1 ? m0 + 1 + d : m1;
@@ -335,6 +346,17 @@ __global__ __launch_bounds__(THREADS, (counts_min_waves<THREADS, PAIRED, FULL>()
         pair_stats(sums, (int64_t)n_mine * (m1 - m0), acc);
         flush_counts<6>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
     } else {
+        // sources' +1 sites = targets' + first lattice's - last lattice's (cur)
+        uint32_t last[2] = {0, 0};
+#pragma unroll
+        for (uint32_t k = 0; k < WPT; ++k) {
+            const uint32_t lv = FULL ? ~0u : live[k];
+            last[0] = bcnt_acc(lo32(cur[k]) & lv, last[0]);
+            last[1] = bcnt_acc(hi32(cur[k]) & lv, last[1]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            base[h][0] = base[h][0] + ybase[h][0] - last[h];
         int64_t B[5], Y[6], acc[12];
 #pragma unroll
         for (int i = 0; i < 5; ++i)
