@@ -38,21 +38,21 @@ struct HalfCtx {
     FastDiv divL;   // division by L (bit strings)
 };
 
-// Rows of whole words: the word at row j, column word w (g = j * W + w).
+// Rows of whole words: word g = j * W + w (row j, column word w) and its
+// neighbours; every index is g plus or minus W or 1.
 template <int WHICH, bool BITS>
-__device__ __forceinline__ void gather_lds_at(const HalfCtx<BITS>& h, uint32_t j, uint32_t w, uint64_t& c,
-                                              uint64_t& n1, uint64_t& n2) {
-    const uint32_t row = j * h.W;
-    c = h.src[row + w];
+__device__ __forceinline__ void gather_lds_g(const HalfCtx<BITS>& h, uint32_t g, uint32_t j, uint32_t w,
+                                             uint64_t& c, uint64_t& n1, uint64_t& n2) {
+    c = h.src[g];
     const uint32_t c_lo = (uint32_t)c, c_hi = (uint32_t)(c >> 32);
     if constexpr (WHICH == 0) {
-        n1 = h.src[(j == 0 ? h.L - 1 : j - 1) * h.W + w];
-        const uint32_t prev_hi = (uint32_t)(h.src[row + (w == 0 ? h.W - 1 : w - 1)] >> 32);
+        n1 = h.src[j == 0 ? g + h.n_words - h.W : g - h.W];
+        const uint32_t prev_hi = (uint32_t)(h.src[w == 0 ? g + h.W - 1u : g - 1u] >> 32);
         n2 = (uint64_t)__builtin_amdgcn_alignbit(c_lo, prev_hi, 31) |
              ((uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 31) << 32);
     } else {
-        n1 = h.src[(j == h.L - 1 ? 0 : j + 1) * h.W + w];
-        const uint32_t next_lo = (uint32_t)h.src[row + (w == h.W - 1 ? 0 : w + 1)];
+        n1 = h.src[j == h.L - 1 ? g + h.W - h.n_words : g + h.W];
+        const uint32_t next_lo = (uint32_t)h.src[w == h.W - 1 ? g + 1u - h.W : g + 1u];
         n2 = (uint64_t)__builtin_amdgcn_alignbit(c_hi, c_lo, 1) |
              ((uint64_t)__builtin_amdgcn_alignbit(next_lo, c_hi, 1) << 32);
     }
@@ -65,7 +65,7 @@ __device__ __forceinline__ void gather_lds(const HalfCtx<BITS>& h, uint32_t g, u
         gather_bits<WHICH>(h.src, h.L, h.n_words, h.divL, g, c, n1, n2);
     } else {
         const uint32_t j = fdiv(g, h.divW);
-        gather_lds_at<WHICH>(h, j, g - j * h.W, c, n1, n2);
+        gather_lds_g<WHICH>(h, g, j, g - j * h.W, c, n1, n2);
     }
 }
 
@@ -142,7 +142,7 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
             if constexpr (BITS)
                 gather_lds<WHICH>(h, g, c, n1, n2);
             else
-                gather_lds_at<WHICH>(h, j, w, c, n1, n2);
+                gather_lds_g<WHICH>(h, g, j, w, c, n1, n2);
         }
         if constexpr (!BITS) {
             w += step_cols;
