@@ -539,7 +539,7 @@ sd_status sd_run_many(void* const* sigma, void* const* tau, int32_t n_chains, in
         ba.W = (uint32_t)L / 64u;
         ba.R = R;
         ba.bands = (uint32_t)L / R;
-        ba.divW = make_fastdiv(ba.W);
+        ba.shW = (uint32_t)__builtin_ctz(ba.W);
         ba.key0 = base.key0;
         ba.key1 = base.key1;
         const uint32_t stride_b = 4u * ba.bands * ba.n_chains;

@@ -52,22 +52,23 @@ __device__ __forceinline__ void band_sync_wave() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Partner and neighbour words of LDS row i, word w of a half-step (both
-// lattices use the same row numbering): A (WHICH 0) from sigma rows i (the
-// site's own) and i - 1 (below); B (WHICH 1) from tau rows i and i + 1 (above).
+// Partner and neighbour words of LDS word u = i * W + w (row i, word w) of a
+// half-step (both lattices use the same row numbering): A (WHICH 0) from
+// sigma rows i (the site's own) and i - 1 (below); B (WHICH 1) from tau rows
+// i and i + 1 (above).  The rows in LDS need no wrap-around; the words of a
+// row do.
 template <int WHICH>
-__device__ __forceinline__ void band_gather(const uint64_t* src, uint32_t i, uint32_t w, uint32_t W, uint64_t& c,
+__device__ __forceinline__ void band_gather(const uint64_t* src, uint32_t u, uint32_t w, uint32_t W, uint64_t& c,
                                             uint64_t& n1, uint64_t& n2) {
-    const uint64_t* row = src + i * W;
-    c = row[w];
+    c = src[u];
     if constexpr (WHICH == 0) {
-        n1 = src[(i - 1) * W + w];
-        const uint32_t prev_hi = (uint32_t)(row[w == 0 ? W - 1 : w - 1] >> 32);
+        n1 = src[u - W];
+        const uint32_t prev_hi = (uint32_t)(src[w == 0 ? u + W - 1u : u - 1u] >> 32);
         n2 = (uint64_t)__builtin_amdgcn_alignbit((uint32_t)c, prev_hi, 31) |
              ((uint64_t)__builtin_amdgcn_alignbit((uint32_t)(c >> 32), (uint32_t)c, 31) << 32);
     } else {
-        n1 = src[(i + 1) * W + w];
-        const uint32_t next_lo = (uint32_t)row[w == W - 1 ? 0 : w + 1];
+        n1 = src[u + W];
+        const uint32_t next_lo = (uint32_t)src[w == W - 1u ? u + 1u - W : u + 1u];
         n2 = (uint64_t)__builtin_amdgcn_alignbit((uint32_t)(c >> 32), (uint32_t)c, 1) |
              ((uint64_t)__builtin_amdgcn_alignbit(next_lo, (uint32_t)(c >> 32), 1) << 32);
     }
@@ -77,16 +78,16 @@ __device__ __forceinline__ void band_gather(const uint64_t* src, uint32_t i, uin
 // below the threshold's low 24 bits), with its word and neighbour words.
 template <int WHICH>
 __device__ __forceinline__ uint32_t band_tail(const uint64_t* src, uint32_t u, uint32_t b, uint32_t base, uint32_t L,
-                                              uint32_t W, const FastDiv& divW, const DrawParams& dp,
+                                              uint32_t W, uint32_t shW, const DrawParams& dp,
                                               const uint32_t* T24, uint32_t& i, uint64_t& c, uint64_t& n1,
                                               uint64_t& n2) {
-    i = fdiv(u, divW);
-    const uint32_t w = u - i * W;
-    band_gather<WHICH>(src, i, w, W, c, n1, n2);
+    i = u >> shW;
+    const uint32_t w = u & (W - 1u);
+    band_gather<WHICH>(src, u, w, W, c, n1, n2);
     uint32_t row = base + i;
     row = row >= L ? row - L : row;
     row = row >= L ? row - L : row;
-    return draw_tail24(dp, 64u * (row * W + w) + b) < T24[class_at(c, n1, n2, (int)b)] ? 1u : 0u;
+    return draw_tail24(dp, 64u * ((row << shW) + w) + b) < T24[class_at(c, n1, n2, (int)b)] ? 1u : 0u;
 }
 
 template <bool OBS>
@@ -104,7 +105,7 @@ __device__ __forceinline__ void band_count_site(uint32_t bit, uint64_t c, uint64
 template <int WHICH, bool OBS>
 __device__ __forceinline__ void band_resolve(const uint64_t* src, uint64_t* dst, const uint32_t* list, uint32_t k,
                                              uint32_t o0, uint32_t o1, uint32_t base, uint32_t L, uint32_t W,
-                                             const FastDiv& divW, const DrawParams& dp, const uint32_t* T24,
+                                             uint32_t shW, const DrawParams& dp, const uint32_t* T24,
                                              BandSums& acc) {
     band_sync_wave();
     for (uint32_t e = threadIdx.x & 63u; e < k; e += 64u) {
@@ -112,7 +113,7 @@ __device__ __forceinline__ void band_resolve(const uint64_t* src, uint64_t* dst,
         const uint32_t u = v >> 6, b = v & 63u;
         uint32_t i;
         uint64_t c, n1, n2;
-        const uint32_t bit = band_tail<WHICH>(src, u, b, base, L, W, divW, dp, T24, i, c, n1, n2);
+        const uint32_t bit = band_tail<WHICH>(src, u, b, base, L, W, shW, dp, T24, i, c, n1, n2);
         if (bit)
             atomicOr(reinterpret_cast<unsigned long long*>(&dst[u]), 1ull << b);
         if (OBS && i >= o0 && i < o1)
@@ -134,7 +135,7 @@ __device__ __forceinline__ void band_resolve(const uint64_t* src, uint64_t* dst,
 // the end.
 template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS>
 __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, uint32_t r0, uint32_t r1, uint32_t o0,
-                                          uint32_t o1, uint32_t base, uint32_t L, uint32_t W, const FastDiv& divW,
+                                          uint32_t o1, uint32_t base, uint32_t L, uint32_t W, uint32_t shW,
                                           const DrawParams& dp, const PlaneMasks& pm, BandShared& sh,
                                           BandSums& acc) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -147,18 +148,17 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
     for (uint32_t tile = wave; tile < n_tiles; tile += n_waves) {
         const uint32_t uo = 64u * tile + lane;
         const bool active = uo < n_out;
-        const uint32_t t = fdiv(uo, divW);
-        const uint32_t i = r0 + t;
-        const uint32_t w = uo - t * W;
-        const uint32_t u = i * W + w;
+        const uint32_t i = r0 + (uo >> shW);
+        const uint32_t w = uo & (W - 1u);
+        const uint32_t u = (r0 << shW) + uo;
         uint64_t c = 0, n1 = 0, n2 = 0;
         if (active)
-            band_gather<WHICH>(src, i, w, W, c, n1, n2);
+            band_gather<WHICH>(src, u, w, W, c, n1, n2);
         uint32_t row = base + i;
         row = row >= L ? row - L : row;
         row = row >= L ? row - L : row;
         uint64_t P[8];
-        draw_planes(dp, active ? row * W + w : 0u, P);
+        draw_planes(dp, active ? (row << shW) + w : 0u, P);
         const WordDraw wd = compare_planes<PAIRED, COMPLEMENT>(P, c, n1, n2, pm);
         uint64_t und = active ? wd.und : 0ull;
         if (active) {
@@ -181,13 +181,13 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
             }
             listed += (uint32_t)__popcll(m);
             if (listed >= 64u) {
-                band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, divW, dp, sh.T24, acc);
+                band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, shW, dp, sh.T24, acc);
                 listed = 0;
             }
         }
     }
     if (listed)
-        band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, divW, dp, sh.T24, acc);
+        band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, shW, dp, sh.T24, acc);
     __syncthreads();
 }
 
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int6
     const uint32_t base = a + (n / L + 1u) * L - n;       // lattice row of LDS row 0, plus a multiple of L
     const uint32_t base_mod = base % L;
     for (uint32_t q = threadIdx.x; q < H * W; q += blockDim.x) {
-        const uint32_t i = fdiv(q, ba.divW);
-        const uint32_t w = q - i * W;
+        const uint32_t i = q >> ba.shW;
+        const uint32_t w = q & (W - 1u);
         const uint32_t row = (base_mod + i) % L;
         if constexpr (INT8)
             sh.sig[q] = load_bits64_i8(static_cast<const int8_t*>(ba.src[chain]) + (size_t)row * L + 64u * w);
@@ -235,15 +235,15 @@ __global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int6
         BandSums acc;
         dp.t = ba.t0 + 2u * (s - 1u);
         // tau on rows s .. H - s (its sigma rows below are valid from s - 1)
-        band_half<0, PAIRED, COMPLEMENT, false>(sh.sig, sh.tau, s, H - s + 1u, 0, 0, base_mod, L, W, ba.divW, dp,
+        band_half<0, PAIRED, COMPLEMENT, false>(sh.sig, sh.tau, s, H - s + 1u, 0, 0, base_mod, L, W, ba.shW, dp,
                                                 pm, sh, acc);
         dp.t += 1u;
         const bool recorded = OBS && ((ba.rec_mask >> (s - 1u)) & 1u);
         if (recorded) {
-            band_half<1, PAIRED, COMPLEMENT, true>(sh.tau, sh.sig, s, H - s, n, n + R, base_mod, L, W, ba.divW, dp,
+            band_half<1, PAIRED, COMPLEMENT, true>(sh.tau, sh.sig, s, H - s, n, n + R, base_mod, L, W, ba.shW, dp,
                                                    pm, sh, acc);
         } else {
-            band_half<1, PAIRED, COMPLEMENT, false>(sh.tau, sh.sig, s, H - s, 0, 0, base_mod, L, W, ba.divW, dp, pm,
+            band_half<1, PAIRED, COMPLEMENT, false>(sh.tau, sh.sig, s, H - s, 0, 0, base_mod, L, W, ba.shW, dp, pm,
                                                     sh, acc);
         }
         if constexpr (OBS) {

@@ -111,7 +111,7 @@ struct BandArgs {
     uint32_t n_chains;
     uint32_t bands;      // L / R per chain
     uint32_t L, W, R;
-    FastDiv divW;
+    uint32_t shW;        // log2 W (W divides 256)
     uint32_t key0, key1;
     uint32_t t0;         // half-step index of the launch's first half-step A
     uint32_t steps;      // 1 .. kBandMaxSteps
