@@ -91,6 +91,10 @@ int main(void) {
     expect_err(sd_loglik_bwd(o, NULL, NULL, (float*)p2, NULL), "bwd null");
     expect_err(sd_replica_run(p, p2, 12, NULL, NULL, 1, 0, 0, 1, NULL), "replica null");
     {
+        float t0 = 0.0f, t1 = 0.0f;
+        expect_err(sd_batch_bucket_times(NULL, 0, &t0, &t1), "bucket times null plan");
+    }
+    {
         double J64[64], q64[64];
         for (int i = 0; i < 64; ++i) { J64[i] = 0.5; q64[i] = 0.5; }
         J64[7] = NAN;
