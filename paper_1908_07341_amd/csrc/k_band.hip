@@ -39,6 +39,7 @@ struct BandShared {
     uint64_t sig[kBandMaxRowsWords];         // sigma, rows a - n .. a + R + n - 1
     uint64_t tau[kBandMaxRowsWords];         // tau, the same rows
     uint32_t site[kBandWaves][kBandListCap]; // undecided sites of each wavefront: 64 * LDS word + bit
+    unsigned long long obs[3];               // a recorded step's sums, added by every wavefront
     uint32_t T24[6];
 };
 
@@ -188,6 +189,21 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
     }
     if (listed)
         band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, shW, dp, sh.T24, acc);
+    if constexpr (OBS) {
+        // a wavefront's counts of one half-step stay far below 2^32
+        uint32_t v[3] = {(uint32_t)acc.pc, (uint32_t)acc.dpair, (uint32_t)acc.dself};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                v[k] += __shfl_xor(v[k], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                atomicAdd(&sh.obs[k], (unsigned long long)v[k]);
+        }
+    }
     __syncthreads();
 }
 
@@ -200,7 +216,6 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
 template <bool INT8, bool PAIRED, bool COMPLEMENT, bool OBS>
 __global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int64_t* __restrict__ partials) {
     __shared__ BandShared sh;
-    __shared__ int64_t red[3 * kBandWaves];
     const uint32_t chain = blockIdx.x / ba.bands;
     const uint32_t band = blockIdx.x - chain * ba.bands;
     const uint32_t L = ba.L, W = ba.W, R = ba.R, n = ba.steps;
@@ -219,6 +234,8 @@ __global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int6
     }
     if (threadIdx.x < 6)
         sh.T24[threadIdx.x] = PAIRED ? paired_tail(ba.T[chain], threadIdx.x) : ba.T[chain][threadIdx.x] & 0xFFFFFFu;
+    if (threadIdx.x < 3)
+        sh.obs[threadIdx.x] = 0;
     __syncthreads();
     DrawParams dp;
 #pragma unroll
@@ -247,15 +264,17 @@ __global__ __launch_bounds__(kBandMaxThreads) void k_band_step(BandArgs ba, int6
                                                     sh, acc);
         }
         if constexpr (OBS) {
+            // every wavefront has added its sums before the half-step's
+            // barrier; the next recorded half-step adds again only after
+            // the next half-step A's barrier, so the reset cannot race
             if (recorded) {
-                int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
-                block_sum_i64<3>(v, red);
                 if (threadIdx.x == 0) {
                     int64_t* p = partials + (size_t)rec * ba.rec_stride + 4u * (size_t)blockIdx.x;
-                    p[0] = v[0];
-                    p[1] = v[1];
-                    p[2] = v[2];
+                    p[0] = (int64_t)sh.obs[0];
+                    p[1] = (int64_t)sh.obs[1];
+                    p[2] = (int64_t)sh.obs[2];
                     p[3] = (int64_t)R * L;
+                    sh.obs[0] = sh.obs[1] = sh.obs[2] = 0;
                 }
                 ++rec;
             }
