@@ -164,8 +164,10 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
         return fallback;
     const std::string key = "batch:" + device_arch() + ":L=" + std::to_string(L) + ":p=" + std::to_string(paired) +
                             ":k=" + std::to_string(p->obs_every ? 1 : 0);
+    // a cached block size is taken only if the kernel of this form can run it
+    const long max_threads = paired ? (long)kBatchMaxThreads : 512;
     const long cached = tune_cache_get(cache_path, key);
-    if (cached > 0)
+    if (cached >= 64 && cached <= max_threads && cached % 64 == 0)
         return (uint32_t)cached;
     int dev = 0, n_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||

@@ -47,20 +47,6 @@ struct BandSums {
     int64_t pc = 0, dpair = 0, dself = 0;
 };
 
-// Sum of v over the wavefront (all 64 lanes active), in every lane: prefix
-// sums within each row of 16 lanes by DPP row shifts (lanes shifted in from
-// outside the row read 0), then lane 15 of rows 0 and 2 added into rows 1 and
-// 3 and lane 31 into rows 2 and 3, which leaves the total in lane 63.
-__device__ __forceinline__ uint32_t band_wave_sum(uint32_t v) {
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
 __device__ __forceinline__ void band_sync_wave() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -205,8 +191,8 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
         band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, shW, dp, sh.T24, acc);
     if constexpr (OBS) {
         // a wavefront's counts of one half-step stay far below 2^32
-        const uint32_t v[3] = {band_wave_sum((uint32_t)acc.pc), band_wave_sum((uint32_t)acc.dpair),
-                               band_wave_sum((uint32_t)acc.dself)};
+        const uint32_t v[3] = {wave_sum_dpp((uint32_t)acc.pc), wave_sum_dpp((uint32_t)acc.dpair),
+                               wave_sum_dpp((uint32_t)acc.dself)};
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 3; ++k)

@@ -113,12 +113,28 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Adds the wavefront's observable sums to obs_sum[0 .. 2] (LDS), one atomic
+// per quantity.  A wavefront's counts of one half-step stay far below 2^32
+// (at most 2 per site of the lattice).
+__device__ __forceinline__ void add_wave_obs(const ObsSums& acc, unsigned long long* obs_sum) {
+    const uint32_t v0 = wave_sum_dpp((uint32_t)acc.pc);
+    const uint32_t v1 = wave_sum_dpp((uint32_t)acc.dpair);
+    const uint32_t v2 = wave_sum_dpp((uint32_t)acc.dself);
+    if ((threadIdx.x & 63u) == 0) {
+        atomicAdd(&obs_sum[0], (unsigned long long)v0);
+        atomicAdd(&obs_sum[1], (unsigned long long)v1);
+        atomicAdd(&obs_sum[2], (unsigned long long)v2);
+    }
+}
+
 // One half-step of the workgroup's chain, src -> dst in LDS, ending with a
 // workgroup barrier.  OBS (half-step B of a recorded step): accumulate the
-// observables of the new pair (dst, src) in acc.
+// observables of the new pair (dst, src) in acc and add the wavefront's sums
+// to obs_sum[0 .. 2] (LDS) before the closing barrier.
 template <int WHICH, bool PAIRED, bool COMPLEMENT, bool OBS, bool BITS>
 __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const DrawParams& dp, const PlaneMasks& pm,
-                                              const uint32_t* T24, WaveWordList& wl, ObsSums& acc) {
+                                              const uint32_t* T24, WaveWordList& wl, ObsSums& acc,
+                                              unsigned long long* obs_sum) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n_waves = blockDim.x >> 6;
     const uint32_t n_tiles = (h.n_words + 63u) / 64u;
@@ -187,6 +203,8 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
         wave_sync_lds();
         resolve_list<WHICH, OBS>(h, dp, T24, wl, listed, acc);
     }
+    if constexpr (OBS)
+        add_wave_obs(acc, obs_sum);
     __syncthreads();
 }
 
@@ -244,14 +262,15 @@ __device__ __forceinline__ void store_lattice(uint64_t* out, const uint64_t* lat
 template <bool PAIRED, bool COMPLEMENT, bool BITS>
 __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS>& hA, const HalfCtx<BITS>& hB,
                                           DrawParams dp,
-                                          const uint32_t* T24, WaveWordList& wl, int64_t* trace, int64_t* red,
-                                          uint64_t* traj, int64_t (&mom)[kMomentWords]) {
+                                          const uint32_t* T24, WaveWordList& wl, int64_t* trace,
+                                          unsigned long long* obs_sum, uint64_t* traj,
+                                          int64_t (&mom)[kMomentWords]) {
     const PlaneMasks pm = make_plane_masks<PAIRED>(dp);
     for (uint32_t m = 0; m < a.k_steps; ++m) {
         const uint32_t n = a.step0 + m;
         ObsSums acc;
         dp.t = 2u * n;
-        lds_half_step<0, PAIRED, COMPLEMENT, false>(hA, dp, pm, T24, wl, acc);
+        lds_half_step<0, PAIRED, COMPLEMENT, false>(hA, dp, pm, T24, wl, acc, obs_sum);
         // (each half-step ends with a barrier, so a copy made here is complete
         // before the lattice is next overwritten, two half-steps later)
         if (traj)
@@ -259,14 +278,18 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS
         dp.t = 2u * n + 1u;
         if (trace && (m + 1) % a.obs_every == 0) {
             if constexpr (PAIRED) {
-                lds_half_step<1, PAIRED, COMPLEMENT, true>(hB, dp, pm, T24, wl, acc);
+                lds_half_step<1, PAIRED, COMPLEMENT, true>(hB, dp, pm, T24, wl, acc, obs_sum);
             } else {
-                lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
+                lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc, obs_sum);
                 acc = lds_observe(hB.dst, hA.dst, hA);
+                add_wave_obs(acc, obs_sum);
+                __syncthreads();
             }
-            int64_t v[3] = {acc.pc, acc.dpair, acc.dself};
-            block_sum_i64<3>(v, red);
+            // every wavefront added its sums before the last barrier; the
+            // next recorded step adds again only after half-step A's barrier
             if (threadIdx.x == 0) {
+                const int64_t v[3] = {(int64_t)obs_sum[0], (int64_t)obs_sum[1], (int64_t)obs_sum[2]};
+                obs_sum[0] = obs_sum[1] = obs_sum[2] = 0;
                 const int64_t sites = (int64_t)hA.n_words * 64;
                 const int64_t M = 2 * v[0] - sites, A = 2 * sites - 2 * v[1], B = sites - 2 * v[2];
                 if (a.moments) {
@@ -283,7 +306,7 @@ __device__ __forceinline__ void run_steps(const BatchArgs& a, const HalfCtx<BITS
                 }
             }
         } else {
-            lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc);
+            lds_half_step<1, PAIRED, COMPLEMENT, false>(hB, dp, pm, T24, wl, acc, obs_sum);
         }
         if (traj)
             store_lattice(traj + (size_t)(2u * m + 2u) * hB.n_words, hB.dst, hB.n_words);
@@ -298,13 +321,15 @@ __device__ __forceinline__ void batch_chains_body(const BatchArgs& a) {
     __shared__ uint32_t s_chain;
     __shared__ uint32_t s_queue;   // the queue this workgroup takes chains from (0: its own)
     __shared__ ChainShared s_ch;
-    __shared__ int64_t red[3 * 8];
+    __shared__ unsigned long long s_obs[3];   // a recorded step's sums, added by every wavefront
     uint64_t* sig = smem;
     uint64_t* tau = smem + a.max_words;
     WaveWordList& wl = reinterpret_cast<WaveWordList*>(tau + a.max_words)[threadIdx.x >> 6];
 
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         s_queue = 0;
+        s_obs[0] = s_obs[1] = s_obs[2] = 0;
+    }
     for (uint32_t iter = 0;; ++iter) {
         ChainDesc cd;
         if (a.counter) {
@@ -410,7 +435,7 @@ __device__ __forceinline__ void batch_chains_body(const BatchArgs& a) {
             store_lattice(traj, sig, n_words);
 
         int64_t mom[kMomentWords] = {0, 0, 0, 0, 0};
-        run_steps<PAIRED, COMPLEMENT, BITS>(a, hA, hB, dp, s_ch.T24, wl, trace, red, traj, mom);
+        run_steps<PAIRED, COMPLEMENT, BITS>(a, hA, hB, dp, s_ch.T24, wl, trace, s_obs, traj, mom);
         if (a.moments && trace && threadIdx.x == 0) {
 #pragma unroll
             for (uint32_t i = 0; i < kMomentWords; ++i)

@@ -431,6 +431,21 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
     return v;
 }
 
+// Sum of v over a wavefront whose 64 lanes are all active, returned in every
+// lane: prefix sums within each row of 16 lanes by DPP row shifts (lanes
+// shifted in from outside the row read 0), then lane 15 of rows 0 and 2 added
+// into rows 1 and 3 and lane 31 into rows 2 and 3, which leaves the total in
+// lane 63.  All in-lane adds, no LDS round trip.
+__device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Block-wide sum of N int64 values, result valid in thread 0.  `red` must hold
 // N * (blockDim.x / 64) entries.
 template <int N>

@@ -139,6 +139,47 @@ def test_batch_autotune_cache(tmp_path):
     plan2.close()
 
 
+@pytest.mark.parametrize("threads", [64, 640, 128])
+def test_batch_forced_block_sizes_agree(tmp_path, threads):
+    # the same plan with its block size pinned through the tuner's cache:
+    # lattices and records identical whatever the block size (640, the
+    # paired kernel's largest workgroup, has ten wavefronts adding records)
+    import json
+    J, q, L, st = _chains(24, [64, 128, 256], seed=9)
+    k, every = 12, 1
+    path = str(tmp_path / "tune.json")
+
+    def run(plan):
+        lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+        tr = torch.full((sd.sd_batch_trace_len(plan),), -5, dtype=torch.int64, device="cuda")
+        sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+        sd.sd_batch_run(plan, lat, tr, 3)
+        torch.cuda.synchronize()
+        return lat, tr
+
+    plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=k, obs_every=every, tune_cache_path=path)
+    lat0, tr0 = run(plan)
+    plan.close()
+    with open(path) as f:
+        cache = json.load(f)
+    forced = {key: (min(threads, 640 if ":p=1" in key else 512) if key.startswith("batch:") else v)
+              for key, v in cache.items()}
+    with open(path, "w") as f:
+        json.dump(forced, f)
+    plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=k, obs_every=every, tune_cache_path=path)
+    shapes = []
+    for b in range(8):
+        try:
+            shapes.append(sd.sd_batch_launch_shape(plan, b))
+        except sd.ShakenError:
+            break
+    print("forced", threads, shapes, flush=True)
+    assert shapes and all(s[2] == min(threads, 640) for s in shapes)
+    lat1, tr1 = run(plan)
+    plan.close()
+    assert torch.equal(lat1, lat0) and torch.equal(tr1, tr0)
+
+
 @pytest.mark.parametrize("L", [40, 64, 128, 200, 256])
 def test_lds_and_global_paths_agree(L):
     J, q, k = 0.55, 0.45, 60
