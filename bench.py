@@ -46,7 +46,9 @@ METRIC = "spin updates/ns (1 GPU, L=16384 packed) + batched-scan chain-steps/s v
 
 # MI355X unit counts used for the ALU roofline: 256 CUs x 4 SIMDs x 16 lanes at
 # 2.4 GHz issue 39.32e12 32-bit VALU lane operations per second.
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_PEAK_OPS = N_SIMD * 16 * CLOCK_HZ
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU operations per spin update of the half-step:
 # Philox4x32-10 work of the stream contract, 4 calls per 64 sites plus one tail
@@ -79,24 +81,26 @@ def kernel_hash() -> str:
 
 
 def measured_traffic():
-    """(HBM bytes per half-step launch, kernel it was measured on) from the
-    committed counter summary, or (None, None) when there is none or the
-    kernel sources changed since it was taken."""
+    """(HBM bytes per half-step launch, kernel it was measured on, VALU wave
+    instructions per launch) from the committed counter record, or Nones when
+    there is none or the kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None, None
+        return None, None, None
     if rec.get("kernel_sha256") != kernel_hash():
-        return None, None
-    return rec.get("bytes_per_launch"), rec.get("kernel")
+        return None, None, None
+    return rec.get("bytes_per_launch"), rec.get("kernel"), rec.get("valu_insts_per_launch")
 
 
-def traffic_from_counters(fetch_csv: str, write_csv: str, copy_bytes: int = 512 * 1024 * 1024) -> dict:
+def traffic_from_counters(fetch_csv: str, write_csv: str, sq_csv: str | None = None,
+                          copy_bytes: int = 512 * 1024 * 1024) -> dict:
     """HBM bytes per launch of the half-step kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of the --calibrate-copy
     bench.  Each counter is scaled by the factor that maps its reading for the
-    device copy of copy_bytes to the bytes that copy moves."""
+    device copy of copy_bytes to the bytes that copy moves.  With the SQ run's
+    CSV, also the VALU wave instructions per launch (SQ_INSTS_VALU)."""
     import csv
 
     def per_kernel(path, counter):
@@ -130,8 +134,16 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, copy_bytes: int = 512 
         return len(args) == 5 and args[1] == "0" and args[4] == "false"
 
     main = min((k for k in kernels if plain_a(k)), key=lambda k: kernels[k]["bytes"], default=None)
+    valu = None
+    if sq_csv and main:
+        sums = {}
+        with open(sq_csv) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == "SQ_INSTS_VALU" and row["Kernel_Name"] == main:
+                    sums[row["Dispatch_Id"]] = sums.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+        valu = sum(sums.values()) / len(sums) if sums else None
     return {"kernel_sha256": kernel_hash(), "kernel": main,
-            "bytes_per_launch": kernels[main]["bytes"] if main else None,
+            "bytes_per_launch": kernels[main]["bytes"] if main else None, "valu_insts_per_launch": valu,
             "fetch_factor": f_fac, "write_factor": w_fac, "copy_bytes": copy_bytes, "kernels": kernels}
 
 
@@ -189,8 +201,9 @@ def parse():
     p.add_argument("--cpu-plan", action="store_true",
                    help="only the oracle on the CPU baseline plan's workloads (C1, a C2 point, 64 C4 chains, "
                         "a C5 sample), one pinned core per job")
-    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                   help="write the half-step traffic record from two rocprofv3 counter CSVs and exit")
+    p.add_argument("--traffic-from", nargs="+", metavar="CSV",
+                   help="write the half-step counter record from the rocprofv3 counter CSVs of the FETCH_SIZE "
+                        "and WRITE_SIZE runs (and optionally the SQ run) and exit")
     return p.parse_args()
 
 
@@ -590,6 +603,9 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache, plain_full=Fal
         for i, (c, Lc, sig, tau, obs) in enumerate(bufs):
             sd.sd_run(sig, tau, Lc, sd.SD_P64, float(Jv[c]), float(qv[c]), seed, int(streams[c]), 0, K, obs, 1,
                       hip_stream=sts[i % len(sts)])
+            if plain_full and (i + 1) % 256 == 0:
+                log(f"[bench] plain launches on {n_streams} stream(s): {i + 1} of {len(bufs)} chains enqueued "
+                    f"in {time.perf_counter() - t_start:.0f} s")
         for st in sts:
             cur.wait_stream(st)
         torch.cuda.synchronize()
@@ -971,6 +987,8 @@ def _fp64_newton(c):
 def main():
     args = parse()
     if args.traffic_from:
+        if len(args.traffic_from) not in (2, 3):
+            raise SystemExit("--traffic-from takes FETCH_CSV WRITE_CSV [SQ_CSV]")
         rec = traffic_from_counters(*args.traffic_from)
         with open(TRAFFIC_FILE, "w") as f:
             json.dump(rec, f, indent=1)
@@ -1026,7 +1044,16 @@ def main():
     hbm_gbs = ALG_BYTES_PER_SPIN_UPDATE * per_launch_updates / launch_s / 1e9
     alu_achieved = OPS_PER_SPIN_UPDATE * per_launch_updates / launch_s / 1e12
     alu_peak = VALU_PEAK_OPS / 1e12
-    traffic, traffic_kernel = measured_traffic()
+    traffic, traffic_kernel, valu_per_launch = measured_traffic()
+    # the measured instruction stream beside the algorithmic op count: VALU
+    # wave instructions per 64 words and the share of the launch they take to
+    # issue (4 cycles per wave64 instruction on each of the 1024 SIMDs)
+    valu_measured = None
+    if valu_per_launch:
+        issue_s = valu_per_launch * 4.0 / (N_SIMD * CLOCK_HZ)
+        valu_measured = {"valu_insts_per_64_words": valu_per_launch / (per_launch_updates / 64 / 64),
+                         "valu_issue_us": issue_s * 1e6, "valu_issue_frac": issue_s / launch_s,
+                         "source": "SQ_INSTS_VALU of the committed counter record"}
     blocks = choice[2]
     kernel = {1: "single-workgroup LDS kernel"}.get(
         choice[0], f"k_half_step on {choice[1]}-bit words, {blocks} workgroups of 256 threads")
@@ -1048,7 +1075,7 @@ def main():
                      "alu": {"achieved": alu_achieved, "peak": alu_peak, "unit": "T lane-ops/s",
                              "frac": alu_achieved / alu_peak, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
                              "hbm_frac_at_alu_peak": ALG_BYTES_PER_SPIN_UPDATE * VALU_PEAK_OPS /
-                             OPS_PER_SPIN_UPDATE / 1e9 / HBM_PEAK_GBS},
+                             OPS_PER_SPIN_UPDATE / 1e9 / HBM_PEAK_GBS, "measured": valu_measured},
                      "tuned_choice": list(choice), "preroll": r["preroll"]},
         "m_final": r["m_final"],
     }
