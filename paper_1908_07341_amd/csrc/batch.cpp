@@ -155,8 +155,9 @@ hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint
 }  // namespace
 
 // Measured choice of the batched kernel's block size for chains of size L: a
-// sample of this plan's chains of that size runs 16 steps on scratch lattices
-// for every candidate; the fastest is kept in the cache file.
+// sample of this plan's chains of that size runs 64 steps on scratch lattices
+// for every candidate (best of three launches after a warm-up); the fastest
+// is kept in the cache file.
 uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t paired, uint32_t n_chains,
                                 sd_batch_plan* p) {
     const uint32_t fallback = 256;
@@ -178,7 +179,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
         if (d.L == L && d.paired == paired && sample.size() < std::min<uint32_t>(n_chains, 2u * (uint32_t)n_cu))
             sample.push_back(d);
     const uint32_t S = (uint32_t)sample.size();
-    const uint32_t k = 16;
+    const uint32_t k = 64;   // long enough that the small lattices' launches are not timed in noise
     const size_t bytes = lattice_bytes((int32_t)L, p->layout);
     size_t off = 0;
     for (uint32_t i = 0; i < S; ++i) {
@@ -231,7 +232,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
                 return -1.0;
             const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(S, (uint32_t)per_cu * (uint32_t)n_cu));
             float best_ms = -1.0f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 4; ++rep) {   // the first launch warms up, the best of the other three counts
                 if (launch_zero_u32(cnt, 1, nullptr) != hipSuccess) return -1.0;
                 if (hipEventRecord(e0, nullptr) != hipSuccess) return -1.0;
                 if (launch_batch_chains(a, blocks, (uint32_t)threads, nullptr) != hipSuccess) return -1.0;
@@ -239,7 +240,7 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
                 if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
                 float ms = 0.0f;
                 if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
-                if (rep > 0)
+                if (rep > 0 && (best_ms < 0.0f || ms < best_ms))
                     best_ms = ms;
             }
             return best_ms / 1e3;
