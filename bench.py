@@ -553,20 +553,26 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache, plain_full=Fal
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     batch_rate = n * K / t_batch
-    # load balance: the same run as plain launches with per-bucket start/end
+    # load balance of the timed graph run: each bucket's first start and last
+    # end, stamped on the device by its own workgroups
+    times = [sd.sd_batch_bucket_times(plan, i) for i in range(len(shapes))]
+    span = max(e for _, e in times)
+    busy = sum(e - s_ for s_, e in times)
+    # the same run as plain launches (no graph) must give the same chains
     graph_lat, graph_tr = lat.clone(), traces.clone()
     lat.copy_(start)
     sd.sd_batch_run_direct(plan, lat, traces, 0)
     torch.cuda.synchronize()
-    times = [sd.sd_batch_bucket_times(plan, i) for i in range(len(shapes))]
-    span = max(e for _, e in times)
-    busy = sum(e - s_ for s_, e in times)
     # Buckets steal from later buckets' queues, so a bucket whose grid becomes
     # resident only when an earlier one ends can find its queue empty: it
-    # then runs for microseconds and did none of the scan's work.  Those
+    # then runs for microseconds and did none of the scan's work.  Such
     # launches are left out of the working-bucket efficiency.
     working = [(s_, e) for s_, e in times if e - s_ > 0.01 * span]
     busy_w = sum(e - s_ for s_, e in working)
+    # the buckets share their queues, so the balance that matters is how
+    # close together they end (a grid that becomes resident late has had
+    # its chains taken by the others meanwhile)
+    end_spread = (max(e for _, e in working) - min(e for _, e in working)) / span
     same_direct = bool(torch.equal(lat, graph_lat) and torch.equal(traces, graph_tr))
     # plain: one sd_run per chain (sd_run's launch choice tuned for each size)
     for size in sorted(set(Lv.tolist())):
@@ -630,8 +636,11 @@ def bench_batched(sd, torch, inputs, K, plain_sample, tune_cache, plain_full=Fal
                     f"(numpy default_rng(1)), packed-64, random starts, {K} steps, (M,A,B) every step",
         "chain_steps_per_s": batch_rate, "seconds": t_batch,
         "spin_updates_per_ns": 2.0 * total_cost * K / t_batch / 1e9,
-        "load_balance": {"bucket_start_end_ms": [[round(s_, 2), round(e, 2)] for s_, e in times],
-                         "span_ms": span, "efficiency": busy_w / (len(working) * span),
+        "load_balance": {"source": "the timed graph run: each bucket's first start and last end on the device "
+                                   "wall clock",
+                         "bucket_start_end_ms": [[round(s_, 2), round(e, 2)] for s_, e in times],
+                         "span_ms": span, "end_spread": end_spread,
+                         "efficiency": busy_w / (len(working) * span),
                          "working_buckets": len(working), "efficiency_all_launches": busy / (len(times) * span),
                          "direct_run_identical_to_graph": same_direct},
         "plain": {"chains_run": len(bufs), "all_chains": bool(plain_full),
@@ -1091,7 +1100,8 @@ def main():
         out["batched_scan"]["rate_vs_single_chain"] = out["batched_scan"]["spin_updates_per_ns"] / value
         log(f"[bench] batched {out['batched_scan']['chain_steps_per_s']:.3g} chain-steps/s, "
             f"x{out['batched_scan']['speedup_vs_plain_four_streams']:.1f} vs plain on 4 streams, load balance "
-            f"{out['batched_scan']['load_balance']['efficiency']:.3f}")
+            f"{out['batched_scan']['load_balance']['efficiency']:.3f}, bucket ends within "
+            f"{100 * out['batched_scan']['load_balance']['end_spread']:.1f} %")
     if not args.no_loglik:
         log("[bench] log-likelihood")
         out["loglik"] = bench_loglik(sd, torch)

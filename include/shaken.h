@@ -448,12 +448,15 @@ SD_API sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_
 
 /*
  * Times of bucket `bucket` (the order of sd_batch_launch_shape) in the last
- * sd_batch_run_direct of the plan, in ms from the start of that run: when its
- * persistent launch started and when it ended.  A launch takes chains of its
- * own size first, then of the later (smaller) buckets of the same kernel
- * form, so that no bucket's workgroups wait while another's queue still holds
- * chains.  Synchronises with that run.  EINVAL: no such bucket, null outputs,
- * or no direct run yet.
+ * run of the plan (sd_batch_run or sd_batch_run_direct), in ms from the
+ * earliest start among that run's launches: when the bucket's persistent
+ * launch started (its first workgroup) and when it ended (its last
+ * workgroup), taken on the device with its constant-rate wall clock.  A
+ * launch takes chains of its own size first, then of the later (smaller)
+ * buckets of the same kernel form, so that no bucket's workgroups wait while
+ * another's queue still holds chains.  Synchronises the device.  EINVAL: no
+ * such bucket, null outputs, or no run yet; EHIP: a HIP error, or no time
+ * stamps (the run failed).
  */
 SD_API sd_status sd_batch_bucket_times(sd_batch_plan* plan, int32_t bucket, float* start_ms, float* end_ms);
 

@@ -402,7 +402,8 @@ def sd_batch_run_direct(plan: sd_batch_plan, lattices, traces, step0=0, hip_stre
 
 
 def sd_batch_bucket_times(plan: sd_batch_plan, bucket: int):
-    """(start_ms, end_ms) of a bucket's launch in the plan's last direct run."""
+    """(start_ms, end_ms) of a bucket's launch in the plan's last run (graph or
+    direct), from the device's wall clock; synchronises the device."""
     a, b = ctypes.c_float(), ctypes.c_float()
     _check(lib().sd_batch_bucket_times(plan.handle, bucket, ctypes.byref(a), ctypes.byref(b)))
     return float(a.value), float(b.value)

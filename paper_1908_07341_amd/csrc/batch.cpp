@@ -45,9 +45,10 @@ struct sd_batch_plan {
     hipStream_t capture = nullptr;   // stream the graph is captured on
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> events;
-    // timing of the last direct run: the fork, then each bucket's start and end
-    std::vector<hipEvent_t> timing;
-    bool timed = false;
+    // device wall clock of each bucket's launch in the last run: first start
+    // (entries 0 .. n-1), last end (entries n .. 2n-1)
+    unsigned long long* d_times = nullptr;
+    bool ran = false;
 };
 
 namespace sd {
@@ -83,6 +84,8 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     a.order = p->d_order + bk.first;
     a.n_chains = bk.count;
     a.counter = p->d_counters + b;
+    a.t_start = p->d_times + b;
+    a.t_end = p->d_times + p->buckets.size() + b;
     a.lattices = static_cast<uint8_t*>(lattices);
     a.traces = p->n_rec ? traces : nullptr;
     a.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
@@ -111,39 +114,28 @@ BatchArgs bucket_args(const sd_batch_plan* p, size_t b, void* lattices, int64_t*
     return a;
 }
 
-// timed (direct runs only, never under capture): record the fork and each
-// bucket's start and end on the plan's timing events.
-hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint64_t step0, hipStream_t st,
-                         bool timed = false) {
-    hipError_t e = launch_zero_u32(p->d_counters, (uint32_t)p->buckets.size(), st);
+// The launches of a run: the queue counters and the time stamps reset, then
+// every bucket's persistent launch on its own side stream.
+hipError_t enqueue_batch(sd_batch_plan* p, void* lattices, int64_t* traces, uint64_t step0, hipStream_t st) {
+    const uint32_t nb = (uint32_t)p->buckets.size();
+    hipError_t e = launch_zero_u32(p->d_counters, nb, st);
+    if (e == hipSuccess)
+        e = launch_times_reset(p->d_times, p->d_times + nb, nb, st);
     if (e != hipSuccess)
         return e;
-    if (timed)
-        e = hipEventRecord(p->timing[0], st);
-    if (p->buckets.size() == 1) {
+    if (nb == 1) {
         const auto& bk = p->buckets[0];
-        if (timed && e == hipSuccess)
-            e = hipEventRecord(p->timing[1], st);
-        if (e == hipSuccess)
-            e = launch_batch_chains(bucket_args(p, 0, lattices, traces, step0), bk.blocks, bk.threads, st);
-        if (timed && e == hipSuccess)
-            e = hipEventRecord(p->timing[2], st);
-        return e;
+        return launch_batch_chains(bucket_args(p, 0, lattices, traces, step0), bk.blocks, bk.threads, st);
     }
     // fork: every bucket runs on its own stream after the counters are zeroed
-    if (e == hipSuccess)
-        e = hipEventRecord(p->events[0], st);
-    for (size_t b = 0; b < p->buckets.size() && e == hipSuccess; ++b) {
+    e = hipEventRecord(p->events[0], st);
+    for (size_t b = 0; b < nb && e == hipSuccess; ++b) {
         hipStream_t s = p->side[b];
         e = hipStreamWaitEvent(s, p->events[0], 0);
-        if (timed && e == hipSuccess)
-            e = hipEventRecord(p->timing[1 + 2 * b], s);
         if (e == hipSuccess) {
             const auto& bk = p->buckets[b];
             e = launch_batch_chains(bucket_args(p, b, lattices, traces, step0), bk.blocks, bk.threads, s);
         }
-        if (timed && e == hipSuccess)
-            e = hipEventRecord(p->timing[2 + 2 * b], s);
         if (e == hipSuccess)
             e = hipEventRecord(p->events[1 + b], s);
         if (e == hipSuccess)
@@ -426,6 +418,8 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
     if (e == hipSuccess)
         e = hipMalloc(&p->d_counters, sizeof(uint32_t) * p->buckets.size());
     if (e == hipSuccess)
+        e = hipMalloc(&p->d_times, sizeof(unsigned long long) * 2 * p->buckets.size());
+    if (e == hipSuccess)
         e = hipMemcpy(p->d_descs, p->descs.data(), sizeof(ChainDesc) * p->descs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_order, order.data(), sizeof(uint32_t) * order.size(), hipMemcpyHostToDevice);
@@ -442,12 +436,6 @@ sd_status sd_batch_plan_create(sd_batch_plan** plan_out, const sd_chain_desc* ch
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess)
             p->events.push_back(ev);
-    }
-    for (size_t i = 0; i < 2 * p->buckets.size() + 1 && e == hipSuccess; ++i) {
-        hipEvent_t ev = nullptr;
-        e = hipEventCreate(&ev);
-        if (e == hipSuccess)
-            p->timing.push_back(ev);
     }
     if (e != hipSuccess) {
         sd_batch_plan_destroy(p);
@@ -548,6 +536,7 @@ sd_status sd_batch_run(sd_batch_plan* plan, void* lattices, int64_t* traces, uin
         plan->g_step0 = step0;
     }
     e = hipGraphLaunch(plan->exec, st);
+    plan->ran = plan->ran || e == hipSuccess;
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run: graph launch");
 }
 
@@ -561,23 +550,39 @@ sd_status sd_batch_run_direct(sd_batch_plan* plan, void* lattices, int64_t* trac
         return fail(SD_EINVAL, "sd_batch_run_direct: step indices must stay below 2^29");
     if (reinterpret_cast<uintptr_t>(lattices) % 16u)
         return fail(SD_EINVAL, "sd_batch_run_direct: lattices must be 16-byte aligned");
-    hipError_t e = enqueue_batch(plan, lattices, traces, step0, static_cast<hipStream_t>(hip_stream), true);
-    plan->timed = e == hipSuccess;
+    hipError_t e = enqueue_batch(plan, lattices, traces, step0, static_cast<hipStream_t>(hip_stream));
+    plan->ran = plan->ran || e == hipSuccess;
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_run_direct");
 }
 
 sd_status sd_batch_bucket_times(sd_batch_plan* plan, int32_t bucket, float* start_ms, float* end_ms) {
     if (!plan || bucket < 0 || (size_t)bucket >= plan->buckets.size() || !start_ms || !end_ms)
         return fail(SD_EINVAL, "sd_batch_bucket_times: no such bucket or null output");
-    if (!plan->timed)
-        return fail(SD_EINVAL, "sd_batch_bucket_times: no direct run of this plan yet");
+    if (!plan->ran)
+        return fail(SD_EINVAL, "sd_batch_bucket_times: no run of this plan yet");
+    const size_t nb = plan->buckets.size();
+    std::vector<unsigned long long> t(2 * nb);
+    int dev = 0, khz = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(t.data(), plan->d_times, sizeof(unsigned long long) * 2 * nb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "sd_batch_bucket_times");
+    if (khz <= 0)
+        return fail(SD_EHIP, "sd_batch_bucket_times: the device reports no wall-clock rate");
+    unsigned long long t0 = ~0ull;
+    for (size_t b = 0; b < nb; ++b)
+        t0 = std::min(t0, t[b]);
     const size_t b = (size_t)bucket;
-    hipError_t e = hipEventSynchronize(plan->timing[2 + 2 * b]);
-    if (e == hipSuccess)
-        e = hipEventElapsedTime(start_ms, plan->timing[0], plan->timing[1 + 2 * b]);
-    if (e == hipSuccess)
-        e = hipEventElapsedTime(end_ms, plan->timing[0], plan->timing[2 + 2 * b]);
-    return e == hipSuccess ? SD_OK : hip_fail(e, "sd_batch_bucket_times");
+    if (t[b] == ~0ull || t[nb + b] < t[b])
+        return fail(SD_EHIP, "sd_batch_bucket_times: bucket %d left no time stamps", bucket);
+    *start_ms = (float)((double)(t[b] - t0) / khz);
+    *end_ms = (float)((double)(t[nb + b] - t0) / khz);
+    return SD_OK;
 }
 
 void sd_batch_plan_destroy(sd_batch_plan* plan) {
@@ -590,14 +595,14 @@ void sd_batch_plan_destroy(sd_batch_plan* plan) {
         (void)hipStreamDestroy(plan->capture);
     for (hipEvent_t ev : plan->events)
         (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : plan->timing)
-        (void)hipEventDestroy(ev);
     if (plan->d_descs)
         (void)hipFree(plan->d_descs);
     if (plan->d_order)
         (void)hipFree(plan->d_order);
     if (plan->d_counters)
         (void)hipFree(plan->d_counters);
+    if (plan->d_times)
+        (void)hipFree(plan->d_times);
     delete plan;
 }
 

@@ -329,6 +329,8 @@ __device__ __forceinline__ void batch_chains_body(const BatchArgs& a) {
     if (threadIdx.x == 0) {
         s_queue = 0;
         s_obs[0] = s_obs[1] = s_obs[2] = 0;
+        if (a.t_start)
+            atomicMin(a.t_start, (unsigned long long)wall_clock64());
     }
     for (uint32_t iter = 0;; ++iter) {
         ChainDesc cd;
@@ -477,6 +479,8 @@ __device__ __forceinline__ void batch_chains_body(const BatchArgs& a) {
         }
         __syncthreads();
     }
+    if (a.t_end && threadIdx.x == 0)
+        atomicMax(a.t_end, (unsigned long long)wall_clock64());
 }
 
 // The paired compare (every threshold table by default) in workgroups of up
@@ -523,6 +527,18 @@ hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t thr
         launch_batch_chains_t<true>(a, blocks, threads, lds, st);
     else
         launch_batch_chains_t<false>(a, blocks, threads, lds, st);
+    return hipGetLastError();
+}
+
+__global__ void k_times_reset(unsigned long long* starts, unsigned long long* ends, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        starts[i] = ~0ull;
+        ends[i] = 0ull;
+    }
+}
+
+hipError_t launch_times_reset(unsigned long long* starts, unsigned long long* ends, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_times_reset, dim3(1), dim3(64), 0, st, starts, ends, n);
     return hipGetLastError();
 }
 

@@ -53,6 +53,8 @@ struct BatchArgs {
                              // start, 2m+1 after half-step A of step m, 2m+2 after B) to
                              // traj + b * traj_chain_bytes + x * lattice bytes, and skips the write-back
     uint64_t traj_chain_bytes;
+    unsigned long long* t_start;   // non-null: the launch's first start and last end on the device
+    unsigned long long* t_end;     // wall clock (atomic min / max by thread 0 of every workgroup)
 };
 
 // Largest workgroup of the batched kernel (the paired compare; the six-class
@@ -72,6 +74,8 @@ void set_divisors(ChainDesc& d, uint32_t L);
 size_t batch_lds_bytes(uint32_t max_words, uint32_t threads);
 hipError_t launch_batch_chains(const BatchArgs& a, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, uint32_t n, hipStream_t st);
+// starts[0 .. n) = all ones and ends[0 .. n) = 0, before the launches that time themselves.
+hipError_t launch_times_reset(unsigned long long* starts, unsigned long long* ends, uint32_t n, hipStream_t st);
 hipError_t batch_kernel_attributes(size_t max_dynamic_lds);
 hipError_t batch_occupancy(uint32_t threads, size_t lds, bool paired, bool bits, int* blocks_per_cu);
 

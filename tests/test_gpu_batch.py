@@ -139,6 +139,35 @@ def test_batch_autotune_cache(tmp_path):
     plan2.close()
 
 
+def test_bucket_times_of_graph_and_direct_runs():
+    # each bucket's launch stamps its first start and last end on the device:
+    # the earliest start is 0, every end follows its start, and both kinds of
+    # run leave times (the graph run first)
+    J, q, L, st = _chains(48, [64, 128, 256], seed=6)
+    plan = sd.sd_batch_plan_create(J, q, L, st, seed=SEED, k_steps=20, obs_every=1)
+    lat = torch.zeros(sd.sd_batch_lattice_bytes(plan), dtype=torch.uint8, device="cuda")
+    tr = torch.zeros(sd.sd_batch_trace_len(plan), dtype=torch.int64, device="cuda")
+    sd.sd_batch_init(plan, lat, sd.SD_INIT_RANDOM, 0.5)
+    with pytest.raises(sd.ShakenError):   # no run yet
+        sd.sd_batch_bucket_times(plan, 0)
+    n_buckets = 0
+    while True:
+        try:
+            sd.sd_batch_launch_shape(plan, n_buckets)
+        except sd.ShakenError:
+            break
+        n_buckets += 1
+    for run in (sd.sd_batch_run, sd.sd_batch_run_direct):
+        run(plan, lat, tr, 0)
+        times = [sd.sd_batch_bucket_times(plan, b) for b in range(n_buckets)]
+        print(run.__name__, times, flush=True)
+        assert min(s_ for s_, _ in times) == 0.0
+        assert all(0.0 <= s_ <= e for s_, e in times)
+    with pytest.raises(sd.ShakenError):
+        sd.sd_batch_bucket_times(plan, n_buckets)
+    plan.close()
+
+
 @pytest.mark.parametrize("threads", [64, 640, 128])
 def test_batch_forced_block_sizes_agree(tmp_path, threads):
     # the same plan with its block size pinned through the tuner's cache:
