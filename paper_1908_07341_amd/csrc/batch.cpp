@@ -157,8 +157,12 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
         return fallback;
     const std::string key = "batch:" + device_arch() + ":L=" + std::to_string(L) + ":p=" + std::to_string(paired) +
                             ":k=" + std::to_string(p->obs_every ? 1 : 0);
-    // a cached block size is taken only if the kernel of this form can run it
-    const long max_threads = paired ? (long)kBatchMaxThreads : 512;
+    // a cached block size is taken only if the kernel of this form can run it;
+    // and no workgroup gets more wavefronts than a half-step has 64-word tiles
+    // (the rest would idle in every half-step while holding a slot that the
+    // scan's other buckets could use)
+    const long tiles = (long)((lattice_words(L) + 63u) / 64u);
+    const long max_threads = std::min<long>(paired ? (long)kBatchMaxThreads : 512, std::max<long>(64, 64 * tiles));
     const long cached = tune_cache_get(cache_path, key);
     if (cached >= 64 && cached <= max_threads && cached % 64 == 0)
         return (uint32_t)cached;
@@ -237,8 +241,11 @@ uint32_t autotune_batch_threads(const char* cache_path, uint32_t L, uint32_t pai
             }
             return best_ms / 1e3;
         };
-        best = paired ? tune_pick({64, 128, 256, 512, (long)kBatchMaxThreads}, measure)
-                      : tune_pick({64, 128, 256, 512}, measure);
+        std::vector<long> cand;
+        for (long t : {64L, 128L, 256L, 512L, (long)kBatchMaxThreads})
+            if (t <= max_threads)
+                cand.push_back(t);
+        best = tune_pick(cand, measure);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
