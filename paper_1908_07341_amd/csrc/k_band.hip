@@ -43,8 +43,10 @@ struct BandShared {
     uint32_t T24[6];
 };
 
+// A thread's counts of one half-step (at most 2 per site of a band of at
+// most 1280 words): 32 bits hold them.
 struct BandSums {
-    int64_t pc = 0, dpair = 0, dself = 0;
+    uint32_t pc = 0, dpair = 0, dself = 0;
 };
 
 __device__ __forceinline__ void band_sync_wave() {
@@ -190,9 +192,7 @@ __device__ __forceinline__ void band_half(const uint64_t* src, uint64_t* dst, ui
     if (listed)
         band_resolve<WHICH, OBS>(src, dst, list, listed, o0, o1, base, L, W, shW, dp, sh.T24, acc);
     if constexpr (OBS) {
-        // a wavefront's counts of one half-step stay far below 2^32
-        const uint32_t v[3] = {wave_sum_dpp((uint32_t)acc.pc), wave_sum_dpp((uint32_t)acc.dpair),
-                               wave_sum_dpp((uint32_t)acc.dself)};
+        const uint32_t v[3] = {wave_sum_dpp(acc.pc), wave_sum_dpp(acc.dpair), wave_sum_dpp(acc.dself)};
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 3; ++k)

@@ -83,8 +83,11 @@ struct ChainShared {
     uint32_t T24[6];   // tail thresholds of the classes (paired_tail in the paired form)
 };
 
+// A thread's counts of one half-step: at most 2 per site of the lattice
+// (10240 words of 64 sites at most in LDS), so 32 bits hold them and every
+// popcount adds in one instruction.
 struct ObsSums {
-    int64_t pc = 0, dpair = 0, dself = 0;   // #+1, #differences to up+right, to the partner
+    uint32_t pc = 0, dpair = 0, dself = 0;   // #+1, #differences to up+right, to the partner
 };
 
 // Resolves the first n sites of the wavefront's list into the lattice.
@@ -117,9 +120,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 // per quantity.  A wavefront's counts of one half-step stay far below 2^32
 // (at most 2 per site of the lattice).
 __device__ __forceinline__ void add_wave_obs(const ObsSums& acc, unsigned long long* obs_sum) {
-    const uint32_t v0 = wave_sum_dpp((uint32_t)acc.pc);
-    const uint32_t v1 = wave_sum_dpp((uint32_t)acc.dpair);
-    const uint32_t v2 = wave_sum_dpp((uint32_t)acc.dself);
+    const uint32_t v0 = wave_sum_dpp(acc.pc);
+    const uint32_t v1 = wave_sum_dpp(acc.dpair);
+    const uint32_t v2 = wave_sum_dpp(acc.dself);
     if ((threadIdx.x & 63u) == 0) {
         atomicAdd(&obs_sum[0], (unsigned long long)v0);
         atomicAdd(&obs_sum[1], (unsigned long long)v1);
