@@ -158,11 +158,19 @@ SD_API sd_status sd_run_noalloc(void* sigma, void* tau, int32_t L, int32_t layou
 /*
  * n_chains (1..16) chains of one size and layout advanced together: chain a
  * is exactly sd_run(sigma[a], tau[a], L, layout, J[a], q[a], seed,
- * streams[a], step0, k_steps, ...), but every half-step of all the chains is
- * one grid launch (the chains' words split into 64-word tiles, a share of
- * the workgroups per chain), so that lattices of a few thousand words, which
- * alone fill a small part of the device, run together at the launch rate of
- * one.  sigma, tau: host arrays of n_chains device lattice pointers (no two of
+ * streams[a], step0, k_steps, ...), but every launch covers all the chains,
+ * so that lattices of a few thousand words, which alone fill a small part of
+ * the device, run together at the launch rate of one.  Lattices whose rows
+ * are whole 64-bit words, at most 64 of them (L = 64 W with W dividing 256;
+ * packed, or int8 with 16-byte aligned lattices), run all but the last step
+ * as whole steps, up to eight per launch: each workgroup takes a band of rows
+ * plus one halo row per step on each side into LDS and recomputes the halo
+ * from the same counter-based uniforms (sections 2 and 4: eqs. (15)-(16)
+ * drawn site by site), so results do not change; tau's memory holds sigma
+ * between launches and the last step, as two half-step launches, leaves tau
+ * as sd_run does.  Other lattices take one launch per half-step for all the
+ * chains (the chains' words split into 64-word tiles, a share of the
+ * workgroups per chain).  sigma, tau: host arrays of n_chains device lattice pointers (no two of
  * the 2 n_chains lattices may overlap); J, q, streams: host arrays of
  * n_chains.  obs (device) NULL, or n_chains x (k_steps / obs_every) records
  * of (M, A, B), chain-major: obs[3 * (a * (k_steps / obs_every) + r) + {0,1,2}]
