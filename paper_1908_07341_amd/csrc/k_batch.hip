@@ -155,7 +155,9 @@ __device__ __forceinline__ void lds_half_step(const HalfCtx<BITS>& h, const Draw
     }
     for (uint32_t tile = threadIdx.x >> 6; tile < n_tiles; tile += n_waves) {
         const uint32_t g = 64u * tile + lane;
-        const bool active = g < h.n_words;
+        // rows of whole words hold L * L / 64 = 64 * L * (L / 64) words: every
+        // tile is full
+        const bool active = !BITS || g < h.n_words;
         uint64_t c = 0, n1 = 0, n2 = 0;
         if (active) {
             if constexpr (BITS)
