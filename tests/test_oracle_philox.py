@@ -85,3 +85,36 @@ def test_site_uniform_is_uniform(oracle):
         chi2 = float(((counts - 64.0) ** 2 / 64.0).sum())
         assert 150 < chi2 < 380, chi2   # 255 dof, roughly the 1e-6 tails
     assert len(np.unique(r)) > 16384 - 5
+
+
+def test_site_uniform_depends_on_every_counter_input(oracle):
+    # The uniform of site s at half-step t must change with t, with the
+    # site's 64-site group, its position inside the group, the half-step
+    # tag and the stream: each pair below compares 16384 sites of one
+    # half-step with a second set that differs in one of these inputs.
+    # Independent 24-bit tails coincide with probability 2^-24 and top bytes
+    # with probability 1/256; a counter that dropped the input would make
+    # every tail (or every top byte) coincide.  The Pearson correlation of
+    # the tails must also be that of independent draws (|r| < 5/sqrt(n)).
+    n = 16384
+    sites = np.arange(n)
+
+    def draw(stream, t, tag, offset):
+        return np.array([oracle.site_uniform(1, stream, t, tag, int(s) + offset) for s in sites], dtype=np.uint64)
+
+    base = draw(3, 10, 0, 0)
+    for other in (draw(3, 11, 0, 0),      # next half-step index
+                  draw(3, 10, 1, 0),      # the other half-step tag
+                  draw(4, 10, 0, 0),      # next stream
+                  draw(3, 10, 0, 64),     # same bit of the next 64-site group
+                  draw(3, 10, 0, 4),      # same Philox output word, next counter
+                  draw(3, 10, 0, 1)):     # next output word of the same call
+        tail_a, tail_b = base & 0xFFFFFF, other & 0xFFFFFF
+        assert int((tail_a == tail_b).sum()) <= 3
+        top_same = int(((base >> 24) == (other >> 24)).sum())
+        assert 20 < top_same < 120, top_same   # 64 expected
+        r = np.corrcoef(tail_a.astype(np.float64), tail_b.astype(np.float64))[0, 1]
+        assert abs(r) < 5 / np.sqrt(n), r
+    # within one site: the tail is not a function of the top byte
+    r = np.corrcoef((base >> 24).astype(np.float64), (base & 0xFFFFFF).astype(np.float64))[0, 1]
+    assert abs(r) < 5 / np.sqrt(n), r
