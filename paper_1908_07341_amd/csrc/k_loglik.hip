@@ -70,8 +70,15 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 // The popcounts of one 32-site half of a word-transition that fix its 12
 // counts, only the sites of `live`.  With k0 = sites whose two J-neighbours
 // are both -1 and k2 = both +1 (class idx = 2k + [c = +1]):
-//   base = {c, k0, k2, k0 & c, k2 & c}, ybase = the same five with y, and y.
-// Eleven accumulating v_bcnt and nine logic ops per half instead of counting
+//   base = {c, n1 | n2, k0 & c, k2 & c}, ybase = {y, c, k0, k2, k0 & c, k2 & c}
+//   each and-ed with y.
+// The totals of k0 and k2 come from the one popcount of n1 | n2: k0 is its
+// complement, and since each neighbour word of a whole lattice is a
+// permutation of the lattice's bits, the +1 neighbours n1 and n2 each sum to
+// the source's +1 sites, so #k2 = #n1 + #n2 - #(n1 | n2) = 2 #c - #(n1 | n2)
+// over a workgroup that covers every word (the counts are linear in these
+// sums, so one thread's share need not satisfy it).  Ten accumulating v_bcnt
+// per half minus the source's (below) and eight logic ops, instead of counting
 // the six class masks and their +1 sites one by one; count_totals turns the
 // sums into the 12 counts.  A thread adds at most 32 per half-word and
 // transition, so 2^27 word-transitions per thread stay exact.  base[0] (the
@@ -79,21 +86,20 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 // is the target of one and the source of the next, so its sum is ybase[0]'s
 // plus the first source's and minus the last target's +1 sites.
 constexpr uint32_t kNeither = tt(~kTA & ~kTB & kTC), kBoth = tt(kTA & kTB & kTC);   // (a, b, mask)
+constexpr uint32_t kEither = tt((kTA | kTB) & kTC);
 
 __device__ __forceinline__ void count_half(uint32_t c, uint32_t n1, uint32_t n2, uint32_t y, uint32_t live,
-                                           uint32_t (&base)[5], uint32_t (&ybase)[6]) {
-    const uint32_t cl = c & live;
-    const uint32_t k0 = lop3<kNeither>(n1, n2, live);
-    const uint32_t k2 = lop3<kBoth>(n1, n2, live);
-    const uint32_t k0c = k0 & c, k2c = k2 & c;
-    base[1] = bcnt_acc(k0, base[1]);
-    base[2] = bcnt_acc(k2, base[2]);
-    base[3] = bcnt_acc(k0c, base[3]);
-    base[4] = bcnt_acc(k2c, base[4]);
-    ybase[0] = bcnt_acc(y & live, ybase[0]);
+                                           uint32_t (&base)[4], uint32_t (&ybase)[6]) {
+    const uint32_t cl = c & live, yl = y & live;
+    const uint32_t k0c = lop3<kNeither>(n1, n2, cl);
+    const uint32_t k2c = lop3<kBoth>(n1, n2, cl);
+    base[1] = bcnt_acc(lop3<kEither>(n1, n2, live), base[1]);
+    base[2] = bcnt_acc(k0c, base[2]);
+    base[3] = bcnt_acc(k2c, base[3]);
+    ybase[0] = bcnt_acc(yl, ybase[0]);
     ybase[1] = bcnt_acc(cl & y, ybase[1]);
-    ybase[2] = bcnt_acc(k0 & y, ybase[2]);
-    ybase[3] = bcnt_acc(k2 & y, ybase[3]);
+    ybase[2] = bcnt_acc(lop3<kNeither>(n1, n2, yl), ybase[2]);
+    ybase[3] = bcnt_acc(lop3<kBoth>(n1, n2, yl), ybase[3]);
     ybase[4] = bcnt_acc(k0c & y, ybase[4]);
     ybase[5] = bcnt_acc(k2c & y, ybase[5]);
 }
@@ -233,15 +239,18 @@ __global__ __launch_bounds__(THREADS, (counts_min_waves<THREADS, PAIRED, FULL>()
     const uint32_t m1 = m0 + kChunk < n_trans ? m0 + kChunk : n_trans;
     const uint64_t* X = traj + (size_t)a * n_lat * n_words;
     // per 32-site half: [0] low, [1] high
-    uint32_t base[2][5], ybase[2][6], pst[2][5];
+    uint32_t base[2][4], ybase[2][6], pst[2][5];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int i = 0; i < 6; ++i)
             ybase[h][i] = 0;
 #pragma unroll
+        for (int i = 0; i < 4; ++i)
+            base[h][i] = 0;
+#pragma unroll
         for (int i = 0; i < 5; ++i)
-            base[h][i] = pst[h][i] = 0;
+            pst[h][i] = 0;
     }
     uint32_t n_mine = 0;
     uint32_t gi[WPT], i_down[WPT], i_up[WPT], i_prev[WPT], i_next[WPT];
@@ -357,14 +366,17 @@ __global__ __launch_bounds__(THREADS, (counts_min_waves<THREADS, PAIRED, FULL>()
 #pragma unroll
         for (int h = 0; h < 2; ++h)
             base[h][0] = base[h][0] + ybase[h][0] - last[h];
-        int64_t B[5], Y[6], acc[12];
+        int64_t S[4], Y[6], acc[12];
 #pragma unroll
-        for (int i = 0; i < 5; ++i)
-            B[i] = (int64_t)base[0][i] + (int64_t)base[1][i];
+        for (int i = 0; i < 4; ++i)
+            S[i] = (int64_t)base[0][i] + (int64_t)base[1][i];
 #pragma unroll
         for (int i = 0; i < 6; ++i)
             Y[i] = (int64_t)ybase[0][i] + (int64_t)ybase[1][i];
-        count_totals(B, Y, 64 * (int64_t)n_mine * (m1 - m0), acc);   // sites seen by this thread
+        // sites seen by this thread; #k0 and #k2 from #(n1 | n2) (count_half)
+        const int64_t n_sites = 64 * (int64_t)n_mine * (m1 - m0);
+        const int64_t B[5] = {S[0], n_sites - S[1], 2 * S[0] - S[1], S[2], S[3]};
+        count_totals(B, Y, n_sites, acc);
         flush_counts<12>(acc, red, counts, partials, blockIdx.y * gridDim.x + blockIdx.x);
     }
 }
