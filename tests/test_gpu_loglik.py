@@ -34,13 +34,13 @@ def _traj_gpu(L, J, q, n_traj, k, stream0=0):
 
 
 @pytest.mark.parametrize("L,n_traj,k", [(64, 3, 12), (64, 2, 130), (128, 2, 5), (192, 2, 71), (256, 1, 9),
-                                        (512, 1, 3), (576, 1, 2)])
+                                        (320, 2, 4), (512, 1, 3), (576, 1, 2)])
 def test_trajectory_and_counts_match_oracle(oracle, L, n_traj, k):
     # L <= 512 take the LDS-staged count kernel: one wave per lattice (64),
-    # one word per lane (128), four words per lane with idle lanes (192) and
-    # without (256, and 512 on 1024 lanes); k = 130 spans two transition
-    # chunks with a ragged second one, k = 71 and 9 end in a partial ring
-    # group.  L = 576 takes the generic kernel.
+    # one word per lane (128), four words per lane with idle lanes (192, and
+    # 320 on 1024 lanes) and without (256, and 512 on 1024 lanes); k = 130
+    # spans two transition chunks with a ragged second one, k = 71 and 9 end
+    # in a partial ring group.  L = 576 takes the generic kernel.
     J, q = 0.45, 0.7
     print(f"trajectories L={L} n={n_traj} k={k}", flush=True)
     traj = _traj_gpu(L, J, q, n_traj, k)
