@@ -168,56 +168,61 @@ __global__ __launch_bounds__(256) void k_corr_row(const void* __restrict__ sigma
 }
 
 // Rows of whole 64-bit words (the packed string with L % 64 == 0, or int8
-// rows whose 64-site groups are 16-byte aligned): workgroup x takes rows
-// [x * rpb, (x + 1) * rpb), staged `chunk` rows at a time as W = L / 64 words
-// each; thread t of r-block y takes the shift r = 1024 y + t (if r <= rmax)
-// and sums popcount(row ^ row rotated by r) over the W words of each staged
-// row, the rotation a funnel shift of consecutive words.  Within a wavefront
-// r >> 6 is uniform, so the LDS reads are broadcasts.  Results are added to
-// out[r] (zeroed first).
+// rows whose 64-site groups are 16-byte aligned): workgroup (x, y) takes the
+// 64 shifts r = 64 x + lane and the R rows from y R on, staged in LDS as
+// W = L / 64 words each; wavefront w sums popcount(row ^ row rotated by r)
+// over the W words of its rows w, w + 16, ..., the rotation a funnel shift of
+// consecutive words.  r >> 6 = x is uniform in the workgroup, so the LDS reads
+// are broadcasts.  The 16 wavefronts' sums are added in LDS and each r gets
+// one atomic add into out[r] (zeroed first) per workgroup.
 constexpr uint32_t kCorr64Words = 4096;   // staged words (32 KB)
+constexpr uint32_t kCorrWaves = 16;
 
 template <bool INT8>
-__global__ __launch_bounds__(1024) void k_corr_row64(const void* __restrict__ sigma, uint32_t L, uint32_t rpb,
-                                                     uint32_t chunk, int32_t rmax, int64_t* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_corr_row64(const void* __restrict__ sigma, uint32_t L, uint32_t R,
+                                                     int32_t rmax, int64_t* __restrict__ out) {
     __shared__ uint64_t rows[kCorr64Words];
+    __shared__ int64_t part[kCorrWaves][64];
     const uint32_t W = L / 64u;
-    const uint32_t j0 = blockIdx.x * rpb;
-    const uint32_t j1 = j0 + rpb < L ? j0 + rpb : L;
-    const uint32_t r = 1024u * blockIdx.y + threadIdx.x;
-    const bool active = r <= (uint32_t)rmax;
-    const uint32_t s = __builtin_amdgcn_readfirstlane(r >> 6);   // uniform in the wavefront
-    const uint32_t sh = r & 63u;
-    int64_t acc = 0;
-    for (uint32_t j = j0; j < j1; j += chunk) {
-        const uint32_t n = j + chunk < j1 ? chunk : j1 - j;
-        __syncthreads();
-        for (uint32_t q = threadIdx.x; q < n * W; q += blockDim.x) {
-            if constexpr (INT8)
-                rows[q] = load_bits64_i8(static_cast<const int8_t*>(sigma) + (size_t)j * L + 64u * q);
-            else
-                rows[q] = static_cast<const uint64_t*>(sigma)[(size_t)j * W + q];
-        }
-        __syncthreads();
-        if (active) {
-            for (uint32_t i = 0; i < n; ++i) {
-                const uint64_t* row = rows + i * W;
-                uint32_t diff = 0;
-                // words s .. W - 1 of the row, then 0 .. s - 1: word w + s (mod W) pairs with word w
-#pragma unroll 8
-                for (uint32_t w = 0; w < W; ++w) {
-                    uint32_t q0 = w + s;
-                    q0 = q0 >= W ? q0 - W : q0;
-                    const uint32_t q1 = q0 + 1u == W ? 0u : q0 + 1u;
-                    const uint64_t rot = (row[q0] >> sh) | ((row[q1] << 1) << (63u - sh));
-                    diff += (uint32_t)__popcll(row[w] ^ rot);
-                }
-                acc += (int64_t)L - 2 * (int64_t)diff;
-            }
-        }
+    const uint32_t j0 = blockIdx.y * R;
+    const uint32_t n = j0 + R < L ? R : L - j0;
+    for (uint32_t q = threadIdx.x; q < n * W; q += blockDim.x) {
+        if constexpr (INT8)
+            rows[q] = load_bits64_i8(static_cast<const int8_t*>(sigma) + (size_t)j0 * L + 64u * q);
+        else
+            rows[q] = static_cast<const uint64_t*>(sigma)[(size_t)j0 * W + q];
     }
-    if (active)
-        atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)acc);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t s = blockIdx.x;   // r >> 6, at most (L - 1) >> 6 = W - 1
+    const uint32_t sh = lane;        // r & 63
+    int64_t acc = 0;
+    for (uint32_t i = wave; i < n; i += kCorrWaves) {
+        const uint64_t* row = rows + i * W;
+        uint32_t diff = 0;
+        // words s .. W - 1 of the row, then 0 .. s - 1: word w + s (mod W) pairs with word w
+#pragma unroll 8
+        for (uint32_t w = 0; w < W; ++w) {
+            uint32_t q0 = w + s;
+            q0 = q0 >= W ? q0 - W : q0;
+            const uint32_t q1 = q0 + 1u == W ? 0u : q0 + 1u;
+            const uint64_t rot = (row[q0] >> sh) | ((row[q1] << 1) << (63u - sh));
+            diff += (uint32_t)__popcll(row[w] ^ rot);
+        }
+        acc += (int64_t)L - 2 * (int64_t)diff;
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+        int64_t t = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kCorrWaves; ++k)
+            t += part[k][lane];
+        const uint32_t r = 64u * blockIdx.x + lane;
+        if (r <= (uint32_t)rmax)
+            atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)t);
+    }
 }
 
 // Diagonal correlation sums (section 3.3, Table 1).  Block (x, y): direction
@@ -326,18 +331,16 @@ hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t
     if (e != hipSuccess)
         return e;
     if (layout == kLayP64 || layout == kLayI8Row) {
+        // 16 rows per workgroup (fewer when 16 rows exceed the staging
+        // buffer: W > 256), one 64-shift chunk of r per workgroup column
         const uint32_t W = G.L / 64u;
-        const uint32_t n_blk = G.L < 256u ? G.L : 256u;
-        const uint32_t rpb = (G.L + n_blk - 1u) / n_blk;
-        uint32_t chunk = kCorr64Words / W;
-        chunk = chunk < rpb ? chunk : rpb;
-        const uint32_t n_r = (uint32_t)rmax + 1u;
-        const dim3 grid((G.L + rpb - 1u) / rpb, (n_r + 1023u) / 1024u);
-        const dim3 block(n_r < 1024u ? 64u * ((n_r + 63u) / 64u) : 1024u);
+        const uint32_t R = W <= kCorr64Words / kCorrWaves ? kCorrWaves : kCorr64Words / W;
+        const dim3 grid(((uint32_t)rmax + 64u) / 64u, (G.L + R - 1u) / R);
+        const dim3 block(64u * kCorrWaves);
         if (layout == kLayI8Row)
-            hipLaunchKernelGGL((k_corr_row64<true>), grid, block, 0, st, sigma, G.L, rpb, chunk, rmax, out);
+            hipLaunchKernelGGL((k_corr_row64<true>), grid, block, 0, st, sigma, G.L, R, rmax, out);
         else
-            hipLaunchKernelGGL((k_corr_row64<false>), grid, block, 0, st, sigma, G.L, rpb, chunk, rmax, out);
+            hipLaunchKernelGGL((k_corr_row64<false>), grid, block, 0, st, sigma, G.L, R, rmax, out);
         return hipGetLastError();
     }
     const uint32_t r_chunks = ((uint32_t)rmax + 256u) / 256u;
