@@ -212,7 +212,8 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     steps per point with (M, A, B) every step and D(r <= 512) every 100 steps,
     stream = point index.  The five chains advance together through
     sd_run_many (whole-step launches of up to eight steps for all five, each
-    workgroup a band of rows with its halo in LDS, records fused in); for
+    workgroup a band of rows with its halo in LDS, records fused in) and
+    their D(r) through one sd_corr_row_many call per measurement; for
     comparison the same sweep with one sd_run per point, on a stream each and
     on a single stream (a 1024^2 half-step alone fills a small part of the
     device, so those are bound by launches)."""
@@ -224,6 +225,7 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     obs = torch.empty((n_pts, n_steps, 3), dtype=torch.int64, device="cuda")
     obs_blk = torch.empty((n_blk, n_pts, corr_every, 3), dtype=torch.int64, device="cuda")
     D = torch.empty((n_pts, n_blk, rmax + 1), dtype=torch.int64, device="cuda")
+    D_blk = torch.empty((n_blk, n_pts, rmax + 1), dtype=torch.int64, device="cuda")
     cur = torch.cuda.current_stream()
     side = [torch.cuda.Stream() for _ in points]
     sigmas, taus = [x for x, _ in lat], [y for _, y in lat]
@@ -246,8 +248,7 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
         for blk in range(n_blk):
             sd.sd_run_many(sigmas, taus, L, sd.SD_I8, points, points, 1, list(range(n_pts)), corr_every * blk,
                            corr_every, obs_blk[blk], 1)
-            for a in range(n_pts):
-                sd.sd_corr_row(sigmas[a], L, sd.SD_I8, rmax, D[a, blk])
+            sd.sd_corr_row_many(sigmas, L, sd.SD_I8, rmax, D_blk[blk])
 
     def per_point(streams):
         def body():
@@ -266,7 +267,7 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     ms_many = timed(many)
     fin_many = [sigma.clone() for sigma in sigmas]
     obs_many = obs_blk.permute(1, 0, 2, 3).reshape(n_pts, n_steps, 3).clone()
-    D_many = D.clone()
+    D_many = D_blk.permute(1, 0, 2).clone()
     ms_one = timed(per_point([cur] * n_pts))
     ms_streams = timed(per_point(side))
     same = all(torch.equal(x, y) for x, y in zip(fin_many, sigmas)) and torch.equal(obs_many, obs) and \
@@ -277,7 +278,8 @@ def bench_c2(sd, torch, tune_cache, L=1024, n_steps=10000, corr_every=100, rmax=
     return {"workload": f"{L}x{L} int8, q = J in {points}, random start, {n_steps} steps per point, "
                         f"(M, A, B) every step, D(r <= {rmax}) every {corr_every} steps",
             "spin_updates_per_ns": updates / (ms_many * 1e6), "seconds": ms_many / 1e3,
-            "path": "sd_run_many: the five chains in whole-step launches of up to eight steps",
+            "path": "sd_run_many: the five chains in whole-step launches of up to eight steps; "
+                    "their D(r) in one sd_corr_row_many call",
             "hbm_algorithmic_GBps": 2.0 * updates / (ms_many * 1e-3) / 1e9,
             "spin_updates_per_ns_sd_run_5_streams": updates / (ms_streams * 1e6),
             "spin_updates_per_ns_sd_run_one_stream": updates / (ms_one * 1e6),

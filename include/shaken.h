@@ -221,6 +221,21 @@ SD_API sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32
                       void* hip_stream);
 
 /*
+ * sd_corr_row for n (1..16) lattices of one size and layout in one pass:
+ * sigma is a host array of n device lattice pointers, out (device) receives
+ * n x (rmax + 1) int64, lattice a's D(r) at out[a * (rmax + 1) + r], each
+ * exactly what sd_corr_row returns for it.  Lattices whose rows are whole
+ * 64-bit words (packed with L % 64 == 0, or int8 with 16-byte aligned
+ * lattices) share one launch; other lattices take one launch each.  The
+ * sums are those of section 3.3's correlations, row by row, as for
+ * sd_corr_row.  EINVAL: n outside [1, 16], a null host array, output or
+ * lattice pointer, a packed lattice not aligned to its word size, an
+ * unsupported (L, layout), rmax outside [0, L).
+ */
+SD_API sd_status sd_corr_row_many(const void* const* sigma, int32_t n, int32_t L, int32_t layout, int32_t rmax,
+                                  int64_t* out, void* hip_stream);
+
+/*
  * Diagonal correlation sums of section 3.3 (Table 1) for l = 0 .. lmax
  * (0 <= lmax < L): out[l] = sum_x sigma_(i,j) sigma_(i+l, j+l) (SW-NE) and
  * out[lmax + 1 + l] = sum_x sigma_(i,j) sigma_(i+l, j-l) (NW-SE), coordinates

@@ -41,6 +41,7 @@ SIGNATURES = {
     "sd_run_many": (_I32, [_VP, _VP, _I32, _I32, _I32, _VP, _VP, _U64, _VP, _U64, _U32, _VP, _U32, _U32, _VP]),
     "sd_observe": (_I32, [_VP, _VP, _I32, _I32, _VP, _VP]),
     "sd_corr_row": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "sd_corr_row_many": (_I32, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
     "sd_corr_diag": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP]),
     "sd_batch_plan_create": (_I32, [ctypes.POINTER(_VP), ctypes.POINTER(sd_chain_desc), _I32, _I32, _U64, _U32,
                                      _U32, _U32, ctypes.c_char_p]),
@@ -225,6 +226,18 @@ def sd_corr_row(sigma, L, layout, rmax, out, hip_stream=None) -> None:
     _lattice(sigma, L, layout, "sd_corr_row(sigma)")
     _need(out, 8 * (rmax + 1), "sd_corr_row(out)")
     _check(lib().sd_corr_row(_ptr(sigma), L, layout, rmax, _ptr(out), _stream(hip_stream)))
+
+
+def sd_corr_row_many(sigmas, L, layout, rmax, out, hip_stream=None) -> None:
+    """D(r) of several lattices of one size; sigmas: list of device lattices;
+    out: [len(sigmas), rmax + 1] int64."""
+    n = len(sigmas)
+    for a in range(n):
+        _lattice(sigmas[a], L, layout, f"sd_corr_row_many(sigma[{a}])")
+    _need(out, 8 * n * (rmax + 1), "sd_corr_row_many(out)")
+    sp = (ctypes.c_void_p * max(n, 1))(*[_ptr(x).value for x in sigmas])
+    _check(lib().sd_corr_row_many(ctypes.cast(sp, ctypes.c_void_p), n, L, layout, rmax, _ptr(out),
+                                  _stream(hip_stream)))
 
 
 def sd_corr_diag(sigma, L, layout, lmax, out, hip_stream=None) -> None:

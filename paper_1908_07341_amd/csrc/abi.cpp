@@ -637,6 +637,35 @@ sd_status sd_corr_row(const void* sigma, int32_t L, int32_t layout, int32_t rmax
     return e == hipSuccess ? SD_OK : hip_fail(e, "sd_corr_row");
 }
 
+sd_status sd_corr_row_many(const void* const* sigma, int32_t n, int32_t L, int32_t layout, int32_t rmax,
+                           int64_t* out, void* hip_stream) {
+    const char* name = "sd_corr_row_many";
+    if (n < 1 || n > (int32_t)kManyMax)
+        return fail(SD_EINVAL, "%s: n must lie in [1, %u]", name, kManyMax);
+    if (!sigma)
+        return fail(SD_EINVAL, "%s: null host array", name);
+    for (int32_t a = 0; a < n; ++a) {
+        sd_status s = check_lattice(sigma[a], L, layout, name);
+        if (s != SD_OK)
+            return s;
+    }
+    if (!out)
+        return fail(SD_EINVAL, "%s: null output", name);
+    if (rmax < 0 || rmax >= L)
+        return fail(SD_EINVAL, "%s: rmax must satisfy 0 <= rmax < L", name);
+    // rows of whole 64-bit words when every lattice has them (int8 rows need
+    // 16-byte aligned lattices)
+    int klay = kernel_layout(L, layout, sigma[0]);
+    for (int32_t a = 1; a < n; ++a)
+        if (kernel_layout(L, layout, sigma[a]) != klay)
+            klay = -1;
+    if (klay != kLayP64 && klay != kLayI8Row)
+        klay = layout == SD_I8 ? kLayI8Any : packed_rows_layout(L);
+    hipError_t e = launch_corr_row_many(klay, sigma, (uint32_t)n, make_geom(L, klay), rmax, out,
+                                        static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SD_OK : hip_fail(e, name);
+}
+
 sd_status sd_corr_diag(const void* sigma, int32_t L, int32_t layout, int32_t lmax, int64_t* out,
                        void* hip_stream) {
     sd_status s = check_lattice(sigma, L, layout, "sd_corr_diag");

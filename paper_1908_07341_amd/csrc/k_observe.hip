@@ -174,15 +174,19 @@ __global__ __launch_bounds__(256) void k_corr_row(const void* __restrict__ sigma
 // over the W words of its rows w, w + 16, ..., the rotation a funnel shift of
 // consecutive words.  r >> 6 = x is uniform in the workgroup, so the LDS reads
 // are broadcasts.  The 16 wavefronts' sums are added in LDS and each r gets
-// one atomic add into out[r] (zeroed first) per workgroup.
+// one atomic add into out[r] (zeroed first) per workgroup.  Several
+// lattices of one size in one launch: lattice z = blockIdx.z, its sums at
+// out + z (rmax + 1).
 constexpr uint32_t kCorr64Words = 4096;   // staged words (32 KB)
 constexpr uint32_t kCorrWaves = 16;
 
 template <bool INT8>
-__global__ __launch_bounds__(1024) void k_corr_row64(const void* __restrict__ sigma, uint32_t L, uint32_t R,
-                                                     int32_t rmax, int64_t* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_corr_row64(CorrLattices cl, uint32_t L, uint32_t R, int32_t rmax,
+                                                     int64_t* __restrict__ out) {
     __shared__ uint64_t rows[kCorr64Words];
     __shared__ int64_t part[kCorrWaves][64];
+    const void* __restrict__ sigma = cl.p[blockIdx.z];
+    out += (size_t)blockIdx.z * ((uint32_t)rmax + 1u);
     const uint32_t W = L / 64u;
     const uint32_t j0 = blockIdx.y * R;
     const uint32_t n = j0 + R < L ? R : L - j0;
@@ -325,24 +329,10 @@ hipError_t launch_corr_diag(int layout, const void* sigma, const Geom& G, int32_
     return hipGetLastError();
 }
 
-hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
-                           hipStream_t st) {
-    hipError_t e = launch_fill_i64(out, (size_t)rmax + 1, 0, st);
-    if (e != hipSuccess)
-        return e;
-    if (layout == kLayP64 || layout == kLayI8Row) {
-        // 16 rows per workgroup (fewer when 16 rows exceed the staging
-        // buffer: W > 256), one 64-shift chunk of r per workgroup column
-        const uint32_t W = G.L / 64u;
-        const uint32_t R = W <= kCorr64Words / kCorrWaves ? kCorrWaves : kCorr64Words / W;
-        const dim3 grid(((uint32_t)rmax + 64u) / 64u, (G.L + R - 1u) / R);
-        const dim3 block(64u * kCorrWaves);
-        if (layout == kLayI8Row)
-            hipLaunchKernelGGL((k_corr_row64<true>), grid, block, 0, st, sigma, G.L, R, rmax, out);
-        else
-            hipLaunchKernelGGL((k_corr_row64<false>), grid, block, 0, st, sigma, G.L, R, rmax, out);
-        return hipGetLastError();
-    }
+// Any layout: one lattice, k_corr_row's workgroups over rows and shifts (out
+// zeroed by the caller).
+static hipError_t launch_corr_row_generic(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
+                                          hipStream_t st) {
     const uint32_t r_chunks = ((uint32_t)rmax + 256u) / 256u;
     uint32_t row_blocks = kMaxBlocks / r_chunks;
     row_blocks = row_blocks < G.L ? row_blocks : G.L;
@@ -356,5 +346,40 @@ hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t
         hipLaunchKernelGGL((k_corr_row<0>), grid, dim3(256), 0, st, sigma, G, rmax, out);
     return hipGetLastError();
 }
+
+hipError_t launch_corr_row_many(int layout, const void* const* sigma, uint32_t n, const Geom& G, int32_t rmax,
+                                int64_t* out, hipStream_t st) {
+    if (n < 1 || n > kManyMax)
+        return hipErrorInvalidValue;
+    hipError_t e = launch_fill_i64(out, (size_t)n * ((size_t)rmax + 1), 0, st);
+    if (e != hipSuccess)
+        return e;
+    if (layout == kLayP64 || layout == kLayI8Row) {
+        // 16 rows per workgroup (fewer when 16 rows exceed the staging
+        // buffer: W > 256), one 64-shift chunk of r per workgroup column,
+        // one lattice per grid layer
+        CorrLattices cl{};
+        for (uint32_t a = 0; a < n; ++a)
+            cl.p[a] = sigma[a];
+        const uint32_t W = G.L / 64u;
+        const uint32_t R = W <= kCorr64Words / kCorrWaves ? kCorrWaves : kCorr64Words / W;
+        const dim3 grid(((uint32_t)rmax + 64u) / 64u, (G.L + R - 1u) / R, n);
+        const dim3 block(64u * kCorrWaves);
+        if (layout == kLayI8Row)
+            hipLaunchKernelGGL((k_corr_row64<true>), grid, block, 0, st, cl, G.L, R, rmax, out);
+        else
+            hipLaunchKernelGGL((k_corr_row64<false>), grid, block, 0, st, cl, G.L, R, rmax, out);
+        return hipGetLastError();
+    }
+    for (uint32_t a = 0; a < n && e == hipSuccess; ++a)
+        e = launch_corr_row_generic(layout, sigma[a], G, rmax, out + (size_t)a * ((size_t)rmax + 1), st);
+    return e;
+}
+
+hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
+                           hipStream_t st) {
+    return launch_corr_row_many(layout, &sigma, 1u, G, rmax, out, st);
+}
+
 
 }  // namespace sd

@@ -138,6 +138,14 @@ hipError_t launch_observe(int layout, const void* sigma, const void* tau, const 
                           hipStream_t st);
 hipError_t launch_corr_row(int layout, const void* sigma, const Geom& G, int32_t rmax, int64_t* out,
                            hipStream_t st);
+// D(r) of n (1 .. kManyMax) lattices of one size and layout: lattice a's sums
+// at out + a (rmax + 1); one launch for rows of whole 64-bit words (P64,
+// I8Row), one per lattice otherwise.
+struct CorrLattices {
+    const void* p[kManyMax];
+};
+hipError_t launch_corr_row_many(int layout, const void* const* sigma, uint32_t n, const Geom& G, int32_t rmax,
+                                int64_t* out, hipStream_t st);
 hipError_t launch_corr_diag(int layout, const void* sigma, const Geom& G, int32_t lmax, int64_t* out,
                             hipStream_t st);
 

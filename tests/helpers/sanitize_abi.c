@@ -81,6 +81,13 @@ int main(void) {
     expect_err(sd_observe(p, p2, 64, SD_P64, NULL, NULL), "observe null");
     expect_err(sd_corr_row(p, 64, SD_P64, 64, o, NULL), "corr rmax");
     expect_err(sd_corr_row(p, 64, SD_P64, -1, o, NULL), "corr rmax<0");
+    {
+        const void* lg[2] = {p, p2};
+        expect_err(sd_corr_row_many(lg, 0, 64, SD_P64, 3, o, NULL), "corr many n=0");
+        expect_err(sd_corr_row_many(lg, 17, 64, SD_P64, 3, o, NULL), "corr many n=17");
+        expect_err(sd_corr_row_many(NULL, 2, 64, SD_P64, 3, o, NULL), "corr many null");
+        expect_err(sd_corr_row_many(lg, 2, 64, SD_P64, 64, o, NULL), "corr many rmax");
+    }
     expect_err(sd_corr_diag(p, 64, SD_P64, 64, o, NULL), "diag lmax");
     expect_err(sd_trajectory(p, p2, 64, SD_I8, 0.5, 0.5, 1, 0, 0, 3, NULL), "trajectory layout");
     expect_err(sd_trajectories(p, p2, -1, 64, SD_P64, 0.5, 0.5, 1, 0, 0, 3, NULL), "trajectories n");

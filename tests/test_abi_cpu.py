@@ -91,6 +91,17 @@ def test_bad_arguments_rejected_without_device_work():
     assert lib.sd_observe(fake, fake2, 64, sd.SD_I8, None, st) == sd.SD_EINVAL
     assert lib.sd_corr_row(fake, 64, sd.SD_I8, 64, fake2, st) == sd.SD_EINVAL
     assert lib.sd_corr_row(fake, 64, sd.SD_I8, -1, fake2, st) == sd.SD_EINVAL
+    lats = (ctypes.c_void_p * 17)(*([0x10000 + 0x10000 * a for a in range(17)]))
+    assert lib.sd_corr_row_many(lats, 0, 64, sd.SD_I8, 3, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_row_many(lats, 17, 64, sd.SD_I8, 3, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_row_many(None, 2, 64, sd.SD_I8, 3, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_row_many(lats, 2, 64, sd.SD_I8, 64, fake2, st) == sd.SD_EINVAL
+    assert lib.sd_corr_row_many(lats, 2, 64, sd.SD_I8, 3, None, st) == sd.SD_EINVAL
+    lats[1] = 0x10004
+    assert lib.sd_corr_row_many(lats, 2, 64, sd.SD_P64, 3, fake2, st) == sd.SD_EINVAL
+    assert b"aligned" in lib.sd_last_error()
+    lats[1] = None
+    assert lib.sd_corr_row_many(lats, 2, 64, sd.SD_I8, 3, fake2, st) == sd.SD_EINVAL
     assert lib.sd_corr_diag(fake, 64, sd.SD_I8, 64, fake2, st) == sd.SD_EINVAL
     assert lib.sd_corr_diag(fake, 64, sd.SD_I8, 3, None, st) == sd.SD_EINVAL
     assert lib.sd_trajectories(fake, fake2, -1, 64, sd.SD_P64, 0.4, 0.6, 1, 0, 0, 2, st) == sd.SD_EINVAL

@@ -227,9 +227,10 @@ def test_observe_and_corr_match_oracle(oracle, L):
 @pytest.mark.parametrize("L,layout,rmax", [
     (128, sd.SD_P64, 127),
     (192, sd.SD_I8, 100),
-    (1088, sd.SD_P64, 1087),    # two blocks of 1024 shifts, 17 words per row
+    (1088, sd.SD_P64, 1087),    # 17 chunks of 64 shifts, 17 words per row, a ragged last row group
     (1152, sd.SD_I8, 1151),
-    (16384, sd.SD_P64, 2),      # rows staged in several chunks per workgroup
+    (16384, sd.SD_P64, 2),      # 256 words per row: 16 rows fill the staging buffer
+    (16448, sd.SD_P64, 1),      # 257 words per row: 15 rows per workgroup, a ragged last group
 ])
 def test_corr_row_whole_words_match_oracle(oracle, L, layout, rmax):
     # rows of whole 64-bit words (packed, or 16-byte aligned int8) take their
@@ -239,6 +240,34 @@ def test_corr_row_whole_words_match_oracle(oracle, L, layout, rmax):
     out = torch.full((rmax + 1,), 99, dtype=torch.int64, device="cuda")
     sd.sd_corr_row(to_device(s, layout), L, layout, rmax, out)
     assert np.array_equal(out.cpu().numpy(), oracle.corr_row(s, rmax))
+
+
+@pytest.mark.parametrize("L,layout,n,rmax,misalign", [
+    (128, sd.SD_P64, 5, 127, False),   # whole words: one launch for all lattices
+    (192, sd.SD_I8, 16, 100, False),   # sixteen int8 lattices
+    (1024, sd.SD_I8, 5, 512, False),   # the sweep's five chains and shifts
+    (192, sd.SD_I8, 3, 191, True),     # one int8 lattice off 16 bytes: one launch per lattice
+    (200, sd.SD_P64, 3, 99, False),    # rows off word boundaries: one launch per lattice
+    (96, sd.SD_P32, 2, 95, False),
+    (64, sd.SD_P64, 1, 0, False),
+])
+def test_corr_row_many_matches_single_and_oracle(oracle, L, layout, n, rmax, misalign):
+    print(f"corr_row_many L={L} layout={layout} n={n} rmax={rmax} misalign={misalign}", flush=True)
+    host = [inputs.random_lattice(L, 500 + a, 0.3 + 0.03 * a) for a in range(n)]
+    lats = [to_device(x, layout) for x in host]
+    if misalign:
+        nb = sd.sd_lattice_bytes(L, layout)
+        buf = torch.empty(nb + 1, dtype=torch.uint8, device="cuda")
+        buf[1:].copy_(lats[1].view(torch.uint8).reshape(-1))
+        lats[1] = buf[1:]
+    out = torch.full((n, rmax + 1), 99, dtype=torch.int64, device="cuda")
+    sd.sd_corr_row_many(lats, L, layout, rmax, out)
+    for a in range(n):
+        one = torch.full((rmax + 1,), 7, dtype=torch.int64, device="cuda")
+        sd.sd_corr_row(lats[a], L, layout, rmax, one)
+        assert torch.equal(out[a], one), a
+    for a in sorted({0, n - 1}):
+        assert np.array_equal(out[a].cpu().numpy(), oracle.corr_row(host[a], rmax)), a
 
 
 def test_C2_prefix_sweep(oracle):
