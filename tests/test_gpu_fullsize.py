@@ -10,6 +10,9 @@ benchmark times, on outputs the oracle can compute one by one:
   against a recount of the returned lattice pair;
 * one point of the 1024^2 int8 sweep for its full 10^4 steps: records,
   D(r) and sampled sites of a further step against the oracle;
+* the sweep's own path (the five chains through sd_run_many in calls of 100
+  steps, their D(r) through sd_corr_row_many): one chain's lattices, records
+  and D(r) over the first 200 steps against the oracle;
 * the differentiation workload (256 trajectories of 256^2, 2000 steps):
   trajectory 0 lattice by lattice and its counts and paired statistics
   against the oracle; for the whole set, the site total, the pair map of
@@ -260,3 +263,34 @@ def test_C2_full_length_point(oracle):
 def to_host_i8(t: torch.Tensor, L: int) -> np.ndarray:
     torch.cuda.synchronize()
     return t.cpu().numpy().astype(np.int8).reshape(L, L)
+
+
+def test_C2_sweep_path_against_oracle(oracle):
+    # the five 1024^2 int8 chains of the sweep (q = J in {0.2, ..., 1.0},
+    # stream = point index) as the benchmark runs them: sd_run_many calls of
+    # 100 steps with (M, A, B) every step, then D(r <= 512) of all five in one
+    # sd_corr_row_many call; chain 4 (J = q = 1) over 200 steps against the
+    # oracle (the middle point's full length is checked above)
+    L, per_call, n_calls, rmax = 1024, 100, 2, 512
+    points = [0.2, 0.4, 0.6, 0.8, 1.0]
+    sigmas = [sd.new_lattice(L, sd.SD_I8) for _ in points]
+    taus = [sd.new_lattice(L, sd.SD_I8) for _ in points]
+    for a, sigma in enumerate(sigmas):
+        sd.sd_init(sigma, L, sd.SD_I8, sd.SD_INIT_RANDOM, 0.5, 1, a)
+    obs = torch.empty((n_calls, len(points), per_call, 3), dtype=torch.int64, device="cuda")
+    D = torch.empty((n_calls, len(points), rmax + 1), dtype=torch.int64, device="cuda")
+    for c in range(n_calls):
+        print(f"C2 sweep path call {c}", flush=True)
+        sd.sd_run_many(sigmas, taus, L, sd.SD_I8, points, points, 1, list(range(len(points))), per_call * c,
+                       per_call, obs[c], 1)
+        sd.sd_corr_row_many(sigmas, L, sd.SD_I8, rmax, D[c])
+    torch.cuda.synchronize()
+    for a in (4,):
+        print(f"C2 sweep path chain {a} against the oracle", flush=True)
+        s = oracle.init(L, oracle.INIT_RANDOM, 0.5, 1, a)
+        for c in range(n_calls):
+            s, t, o = oracle.run(s, points[a], points[a], 1, a, per_call * c, per_call, obs_every=1)
+            assert np.array_equal(obs[c, a].cpu().numpy(), o), (a, c)
+            assert np.array_equal(D[c, a].cpu().numpy(), oracle.corr_row(s, rmax)), (a, c)
+        assert np.array_equal(sigmas[a].cpu().numpy().reshape(L, L), s), a
+        assert np.array_equal(taus[a].cpu().numpy().reshape(L, L), t), a
